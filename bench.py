@@ -1,0 +1,202 @@
+"""Throughput of the whole critical-curve -> caustic -> crossing-map ->
+distance-map path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload n10k]
+
+One step = set_lenses + find_critical_curves (all m+1 rows) + map_caustics
+(every root) + caustic_crossings + caustic_distances on one seeded synthetic
+field whose inputs are already in HBM.  Prints one JSON line:
+  value           roots/s = m * 2N / (seconds per step)
+  roofline        the root-finder sweep kernel: algorithmic FP64 FLOP per
+                  sweep launch / its HIP-event-timed duration, against the
+                  FP64 vector peak
+  cpu_baseline    the CPU oracle on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FLOP/clk
+METRIC = "critical-curve roots/s at N=1e4 stars, % FP64 VALU peak; mixed vs FP64"
+
+WORKLOAD_TEXT = {
+    "n10k": "N=10,000 equal-mass stars, kappa_star=0.5, kappa_s=0, gamma=0.3, uniform disk; "
+            "20,000 phase steps (20,001 rows x 20,000 roots); caustics; N_cc int32 2048^2 and "
+            "FP64 distance map over 40x40 theta_E",
+    "n1k": "N=1,000 Salpeter stars on [0.08,1], kappa_star=0.4, kappa_s=0.2, gamma=0.45; "
+           "10,000 phase steps (2,000 roots each); caustics; N_cc 1024^2 over 20x20 theta_E",
+    "tiny": "N=10 equal-mass stars, kappa_star=0.3, kappa_s=0, gamma=0.3; 1,000 phase steps; "
+            "caustics; N_cc 256^2 over 16x16 theta_E",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="n10k", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
+    ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--cpu-sweeps", type=int, default=2,
+                    help="oracle Jacobi sweeps timed for the CPU baseline")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the path is single-GPU by design "
+              "(multi-GPU sharding by phase subchains is described, not built). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2506_02121_amd import fields, mlcc
+
+    wl = fields.workload(args.workload, args.seed)
+    f = wl.field
+    if wl.grid is None:
+        wl.grid = fields.Grid(0.0, 0.0, 8.0, 8.0, 256, 256)
+    m_steps = wl.m_steps
+    n = f.n
+    n_r = 2 * n
+    dev = torch.device("cuda", 0)
+    x = torch.as_tensor(f.x, device=dev)
+    y = torch.as_tensor(f.y, device=dev)
+    mm = torch.as_tensor(f.m, device=dev)
+    rows = m_steps + 1
+    roots_re = torch.empty((rows, n_r), dtype=torch.float64, device=dev)
+    roots_im = torch.empty_like(roots_re)
+    w_re = torch.empty_like(roots_re)
+    w_im = torch.empty_like(roots_re)
+    grid = mlcc.as_grid(wl.grid)
+    ncc = torch.empty((grid.ny, grid.nx), dtype=torch.int32, device=dev)
+    dist = torch.empty((grid.ny, grid.nx), dtype=torch.float64, device=dev)
+    bl = torch.empty((grid.ny, grid.nx), dtype=torch.uint8, device=dev)
+    ctx = mlcc.Context(0)
+    torch.cuda.synchronize()
+
+    def step():
+        ctx.set_lenses(x, y, mm, f.kappa_s, f.gamma)
+        _, _, cn, st, _ = ctx.find_critical_curves(m_steps, timing=True,
+                                                   out=(roots_re, roots_im))
+        ctx.map_caustics(roots_re.view(-1), roots_im.view(-1), out=(w_re.view(-1), w_im.view(-1)))
+        ctx.caustic_crossings(w_re, w_im, cn, grid, out=ncc)
+        ctx.caustic_distances(grid, ncc, out=(dist, bl))
+        return st
+
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {time.perf_counter() - t:.3f} s")
+
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        stats.append(step())
+        torch.cuda.synchronize()
+        log(f"step {i}: {time.perf_counter() - ts:.3f} s, {stats[-1]['sweeps']} sweeps")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    roots_per_step = m_steps * n_r
+    value = roots_per_step / (elapsed / args.steps)
+
+    flop = sum(s["algorithmic_flop"] for s in stats)
+    sweep_ms = sum(s["sweep_ms"] for s in stats)
+    launches = sum(s["sweeps"] for s in stats)
+    achieved = flop / (sweep_ms * 1e-3) / 1e12 if sweep_ms > 0 else None
+    s0 = stats[-1]
+    updates_per_root_row = s0["root_updates"] / float(n_r * (rows + s0["n_subchains"]))
+    ncc_h = ncc.cpu().numpy()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "roots/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
+                   "n_stars": n, "roots_per_row": n_r, "phase_steps": m_steps,
+                   "grid": [grid.nx, grid.ny], "precision": "fp64", "seed": args.seed},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "aberth_sweep_f64",
+            "achieved": achieved,
+            "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": (achieved / FP64_VECTOR_PEAK_TFLOPS) if achieved else None,
+            "traffic": None,
+            "avg_launch_ms": sweep_ms / launches if launches else None,
+            "launches": launches,
+            "flop_per_root_update": 29 * n + 10 * (n_r - 1),
+        },
+        "stats": {"sweeps_per_step": s0["sweeps"], "root_updates_per_step": s0["root_updates"],
+                  "updates_per_root_per_row": updates_per_root_row,
+                  "n_subchains": s0["n_subchains"], "cold_sweeps": s0["cold_sweeps"],
+                  "max_row_sweeps": s0["max_row_sweeps"], "match_maxdist": s0["match_maxdist"],
+                  "ncc_max": int(ncc_h.max()), "ncc_min": int(ncc_h.min())},
+    }
+    ctx.close()
+    del roots_re, roots_im, w_re, w_im
+    torch.cuda.empty_cache()
+
+    if args.cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(f, m_steps, updates_per_root_row, args.cpu_sweeps)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(f, m_steps, updates_per_root_row, sweeps):
+    """The oracle as it stands, timed on the host's cores, on a bounded
+    sample: `sweeps` Jacobi sweeps of the cold-started centre row (every root
+    active).  Its root-update rate divided by the workload's root updates per
+    root per row (same algorithm and cutoffs) gives roots/s."""
+    import numpy as np
+
+    import oracle
+    log(f"cpu baseline: {sweeps} oracle sweeps of the centre row on {oracle.num_threads()} threads")
+    t = time.perf_counter()
+    z, sw, up, rc = oracle.aberth_row(f, np.pi, max_iter=sweeps, polish=False,
+                                      allow_unconverged=True)
+    dt = time.perf_counter() - t
+    rate = up / dt
+    return {
+        "value": rate / updates_per_root_row,
+        "unit": "roots/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"{sw} cold Jacobi sweeps of the centre row ({up} root updates, "
+                   f"{2 * f.n} roots, {f.n} stars) in {dt:.1f} s = {rate:.3g} root updates/s, "
+                   f"divided by {updates_per_root_row:.3f} root updates per root per row "
+                   f"counted on the same workload"),
+    }
+
+
+if __name__ == "__main__":
+    main()

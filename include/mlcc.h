@@ -1,0 +1,201 @@
+/*
+ * mlcc.h -- C-ABI of the MI355X (gfx950) library that finds microlensing
+ * critical curves and caustics and reduces them to caustic-crossing and
+ * distance-to-caustic maps, after Weisenbach (2025), "A GPU Code for Finding
+ * Microlensing Critical Curves and Caustics" (arXiv 2506.02121).
+ *
+ * Conventions for every call:
+ *  - Array arguments are DEVICE pointers on the context's GPU (for example a
+ *    torch tensor's data_ptr()), unless a comment says host.  The library
+ *    checks each one with hipPointerGetAttributes and returns
+ *    MLCC_ERR_INVALID for host or foreign memory.
+ *  - Complex numbers are two float64 planes (structure of arrays): re[], im[].
+ *  - Units: theta_star = theta_E = 1; masses in units of M (Sec. 2.1).
+ *  - The caller owns every buffer it passes.  The library never frees or
+ *    retains caller memory; mlcc_set_lenses copies its inputs.
+ *  - Work is enqueued on the context's HIP stream.  Calls marked
+ *    "synchronous" return after the stream has drained; the others only
+ *    enqueue.  A context is not thread-safe: use one per host thread.
+ *  - Errors are return codes; no exception crosses the ABI.  A readable
+ *    message for the last failing call on this thread is given by
+ *    mlcc_last_error().  On error the outputs are unspecified, except that
+ *    MLCC_ERR_NOT_CONVERGED still writes every root it reached and reports
+ *    the rest in stats.
+ */
+#ifndef MLCC_H
+#define MLCC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mlcc_ctx mlcc_ctx;
+
+typedef enum {
+    MLCC_OK = 0,
+    MLCC_ERR_INVALID = -1,       /* bad argument; nothing was enqueued */
+    MLCC_ERR_HIP = -2,           /* a HIP runtime call failed */
+    MLCC_ERR_NOMEM = -3,         /* device or pinned allocation failed */
+    MLCC_ERR_NOT_CONVERGED = -4, /* an iteration cap was reached */
+    MLCC_ERR_STATE = -5,         /* call order violated (e.g. no lenses set) */
+    MLCC_ERR_MATCH = -7          /* two copies of one root set did not pair up */
+} mlcc_status;
+
+typedef enum {
+    MLCC_FP64 = 0 /* every step in IEEE double precision */
+} mlcc_precision;
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream` (a
+ * hipStream_t; NULL = the legacy default stream).  *out receives the context;
+ * release it with mlcc_destroy. */
+mlcc_status mlcc_create(mlcc_ctx **out, int device, void *hip_stream);
+void mlcc_destroy(mlcc_ctx *ctx);
+/* Replace the stream later calls enqueue on. */
+mlcc_status mlcc_set_stream(mlcc_ctx *ctx, void *hip_stream);
+/* Message for the last failing call on this thread (never NULL; valid until
+ * the next call on this thread). */
+const char *mlcc_last_error(void);
+
+/*
+ * set_lenses -- the lens model of Sec. 2.1 and Sec. 3.1 with the circular
+ * field's compensating sheet extended to an infinite sheet (App. A):
+ *   w(z)   = (1 - kappa_s) z + gamma conj(z) - sum_i m_i / conj(z - z_i)
+ *   F(z,p) = gamma + sum_i m_i / (z - z_i)^2 - (1 - kappa_s) e^{-i p}
+ * kappa_s = kappa - kappa_star is the smooth convergence; gamma the real
+ * external shear along x1.
+ *   n       number of point masses, >= 1
+ *   x, y, m device float64[n]: positions and masses (m > 0), all finite,
+ *           no two stars at the same position
+ * Rejected (MLCC_ERR_INVALID): any of the above, non-finite kappa_s or gamma,
+ * and |gamma| == |1 - kappa_s| (then gamma - (1-kappa_s) e^{-i p} vanishes on
+ * the phase circle and a critical curve runs off to infinity, App. A
+ * footnote).  Copies the inputs; synchronous.
+ */
+mlcc_status mlcc_set_lenses(mlcc_ctx *ctx, int64_t n, const double *x, const double *y,
+                            const double *m, double kappa_s, double gamma);
+
+typedef struct {
+    int64_t m_steps;       /* phase steps m, even, >= 2: row j <-> phi_j = 2 pi j / m,
+                              rows 0..m (Sec. 3.1, Sec. 4.3) */
+    int32_t n_subchains;   /* S subchains (Sec. 4.3), each grown from its centre row;
+                              must divide m/2.  0 = chosen by the library */
+    int32_t max_iter_cold; /* sweep cap for a cold-started row (0 = 500) */
+    int32_t max_iter_warm; /* sweep cap for a warm-started row (0 = 100) */
+    int32_t precision;     /* mlcc_precision */
+    double tol_step;       /* flag a root once |z^{a+1} - z^a| < tol_step; > 0 */
+    double tol_inv_mu;     /* ... or once the App. C bound |F|(|F| + 2|1-kappa_s|) on
+                              |1/mu| is below tol_inv_mu; 0 disables this test */
+    int32_t timing;        /* nonzero: time every sweep launch with HIP events */
+    int32_t reserved;
+} mlcc_cc_params;
+
+/* The paper's settings (Sec. 3.2 footnote: cutoffs 1e-9 and |mu| > 1e9),
+ * library-chosen subchains, FP64. */
+void mlcc_cc_params_default(mlcc_cc_params *p, int64_t m_steps);
+
+typedef struct {
+    int64_t sweeps;          /* sweep launches that did work */
+    int64_t root_updates;    /* root updates performed (sum over sweeps of active roots) */
+    int64_t unconverged;     /* roots still unflagged in rows that hit a cap */
+    int64_t rows_capped;     /* rows that hit an iteration cap */
+    int32_t n_subchains;     /* S actually used */
+    int32_t max_row_sweeps;  /* most sweeps any warm row needed */
+    int32_t cold_sweeps;     /* most sweeps any cold start needed */
+    int32_t polls;           /* host polls of the device-side front table */
+    double match_maxdist;    /* largest distance between paired duplicate roots */
+    double sweep_ms;         /* summed GPU time of sweep launches that did work
+                                (timing != 0 only) */
+    double algorithmic_flop; /* root_updates * (29 N + 10 (2N - 1)): FMA = 2,
+                                add/mul/reciprocal = 1 */
+} mlcc_cc_stats;
+
+/*
+ * find_critical_curves -- all n_r = 2N roots of F(., phi_j) for every row
+ * j = 0..m of the phase grid (Sec. 3.1), by parallel Aberth-Ehrlich iteration
+ * (Sec. 3.2): every unflagged root takes the step
+ *   z <- z - 1 / (F'/F + 2 sum_i 1/(z - z_i) - sum_{r != k} 1/(z - z_r))
+ * from the previous iterate of all roots at once, seeded with z_i +- 1 at the
+ * centre row of each subchain and with the neighbouring row's roots elsewhere
+ * (Sec. 3.2 warm start, Sec. 4.3 centre-out growth and subchains).
+ *   roots_re, roots_im  device float64[(m+1) * 2N], row-major: row j holds the
+ *                       roots at phi_j.  Column k is one continuous chain over
+ *                       rows 0..m (subchain blocks are relabelled through the
+ *                       nearest-neighbour pairing of their shared boundary row).
+ *   chain_next          device int32[2N] or NULL: chain_next[k] = the column
+ *                       whose row 0 continues column k's row m (phi = 2 pi and
+ *                       phi = 0 give the same roots; Sec. 4.3 footnote).
+ *   stats               host, or NULL.
+ * Synchronous.  MLCC_ERR_NOT_CONVERGED if any row hit its cap;
+ * MLCC_ERR_MATCH if duplicate rows did not pair one-to-one within 1e-6.
+ */
+mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *params,
+                                      double *roots_re, double *roots_im,
+                                      int32_t *chain_next, mlcc_cc_stats *stats);
+
+/*
+ * map_caustics -- the lens equation (Sec. 3.1, infinite sheet of App. A) at
+ * `count` points: w = (1 - kappa_s) z + gamma conj(z) - sum_i m_i / conj(z - z_i).
+ * Applied to the roots it gives the caustics.  z_re, z_im, w_re, w_im:
+ * device float64[count]; w may not alias z.  Enqueues only.
+ */
+mlcc_status mlcc_map_caustics(mlcc_ctx *ctx, int64_t count, const double *z_re,
+                              const double *z_im, double *w_re, double *w_im);
+
+/* Pixel grid of the source plane: pixel (r, c) has its centre at
+ * (center_re - half_width + (c + 0.5) hx, center_im - half_height + (r + 0.5) hy),
+ * hx = 2 half_width / nx, hy = 2 half_height / ny; row 0 is the lowest y. */
+typedef struct {
+    double center_re, center_im, half_width, half_height;
+    int32_t nx, ny;
+} mlcc_grid;
+
+/*
+ * caustic_crossings -- the number of caustic crossings N_cc at every pixel
+ * centre (Sec. 5.1): the winding number of the oriented caustic polygons
+ * about the centre, by Sunday's crossing rule evaluated edge by edge (the
+ * Sec. 5.1 footnote: loop over segments, not pixels).  Caustics run clockwise
+ * (Sec. 5.1), and each edge crossing the ray from the centre toward -x
+ * counts +1 when the edge runs upward and -1 when downward, so N_cc >= 0 for
+ * closed caustics.  An edge covers heights lo <= y < hi; a crossing counts
+ * when strictly left of the centre.  Vertices are put exactly on a lattice of
+ * 2^24 points per pixel, X = rint((x - x0) / hx * 2^24), so the predicate is
+ * exact integer arithmetic.
+ *   w_re, w_im   device float64[rows * n_r], row-major caustic vertices
+ *   edges        (row j, col k) -> (row j+1, col k) for j < rows-1, and the
+ *                closing edges (rows-1, k) -> (0, chain_next[k])
+ *   chain_next   device int32[n_r] or NULL (= identity)
+ *   ncc          device int32[ny * nx], row-major
+ * MLCC_ERR_INVALID if a vertex is not finite or lies more than 2^29 pixels
+ * from the grid, or chain_next holds an index outside [0, n_r).
+ * Synchronous.
+ */
+mlcc_status mlcc_caustic_crossings(mlcc_ctx *ctx, int64_t rows, int64_t n_r,
+                                   const double *w_re, const double *w_im,
+                                   const int32_t *chain_next, const mlcc_grid *grid,
+                                   int32_t *ncc);
+
+/*
+ * caustic_distances -- distance from every pixel centre to the nearest
+ * caustic pixel, for an expanding source (Sec. 5.2: Euclidean distance
+ * transform of the N_cc map).  A caustic pixel is one with a 4-neighbour of
+ * different N_cc; it gets 0.  The map border is not a caustic (Fig. 5
+ * caption), so a pixel may be nearer to the border than to any caustic in
+ * the map: border_limited marks those (distance > distance to the map edge).
+ * With no caustic pixel at all every distance is +inf and every mark 1.
+ * Pixels must be square: |hx - hy| <= 1e-9 hx; distances are in units of hx.
+ *   ncc             device int32[ny * nx]
+ *   dist            device float64[ny * nx]: sqrt(d2) * hx, d2 the exact
+ *                   integer squared pixel distance
+ *   border_limited  device uint8[ny * nx] or NULL
+ * Enqueues only.
+ */
+mlcc_status mlcc_caustic_distances(mlcc_ctx *ctx, const mlcc_grid *grid, const int32_t *ncc,
+                                   double *dist, uint8_t *border_limited);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLCC_H */

@@ -1,0 +1,316 @@
+// C-ABI entry points: argument validation, context and memory management.
+// The arithmetic lives in aberth.hip, chains.hip, caustics.hip,
+// crossings.hip and edt.hip.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <vector>
+
+#include "mlcc_internal.h"
+
+namespace mlcc {
+
+static thread_local std::string g_error = "no error";
+
+mlcc_status fail(mlcc_status s, const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return s;
+}
+
+void clear_error() { g_error = "no error"; }
+
+mlcc_status DevBuf::reserve(size_t n)
+{
+    if (n <= bytes && p) return MLCC_OK;
+    release();
+    size_t want = std::max<size_t>(n, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        return fail(MLCC_ERR_NOMEM, "hipMalloc(%zu bytes): %s", want, hipGetErrorString(e));
+    }
+    bytes = want;
+    return MLCC_OK;
+}
+
+void DevBuf::release()
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+mlcc_status check_device_ptr(const Ctx *c, const void *p, const char *what)
+{
+    if (!p) return fail(MLCC_ERR_INVALID, "%s is NULL", what);
+    hipPointerAttribute_t a;
+    memset(&a, 0, sizeof a);
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MLCC_ERR_INVALID, "%s (%p) is not device memory", what, p);
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+        return fail(MLCC_ERR_INVALID, "%s (%p) is not device memory (type %d)", what, p,
+                    (int)a.type);
+    if (a.device != c->device)
+        return fail(MLCC_ERR_INVALID, "%s lives on device %d, context on device %d", what,
+                    a.device, c->device);
+    return MLCC_OK;
+}
+
+mlcc_status ensure_pinned(Ctx *c, size_t bytes)
+{
+    if (c->pinned && c->pinned_bytes >= bytes) return MLCC_OK;
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    c->pinned_bytes = 0;
+    void *p = nullptr;
+    hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MLCC_ERR_NOMEM, "hipHostMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    c->pinned = p;
+    c->pinned_bytes = bytes;
+    return MLCC_OK;
+}
+
+static mlcc_status use_device(const Ctx *c)
+{
+    MLCC_HIP(hipSetDevice(c->device));
+    return MLCC_OK;
+}
+
+static mlcc_status check_grid(const mlcc_grid *g, bool square)
+{
+    if (!g) return fail(MLCC_ERR_INVALID, "grid is NULL");
+    if (g->nx < 1 || g->ny < 1) return fail(MLCC_ERR_INVALID, "grid needs nx, ny >= 1");
+    if (!(g->half_width > 0) || !(g->half_height > 0) || !std::isfinite(g->half_width) ||
+        !std::isfinite(g->half_height) || !std::isfinite(g->center_re) ||
+        !std::isfinite(g->center_im))
+        return fail(MLCC_ERR_INVALID, "grid extents must be finite and positive");
+    if ((int64_t)g->nx * g->ny > ((int64_t)1 << 31))
+        return fail(MLCC_ERR_INVALID, "grid larger than 2^31 pixels");
+    if (square) {
+        double hx = (2.0 * g->half_width) / g->nx, hy = (2.0 * g->half_height) / g->ny;
+        if (!(std::fabs(hx - hy) <= 1e-9 * hx))
+            return fail(MLCC_ERR_INVALID, "pixels must be square (hx=%.17g, hy=%.17g)", hx, hy);
+    }
+    return MLCC_OK;
+}
+
+} // namespace mlcc
+
+using namespace mlcc;
+
+extern "C" {
+
+const char *mlcc_last_error(void) { return g_error.c_str(); }
+
+mlcc_status mlcc_create(mlcc_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return fail(MLCC_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    MLCC_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev)
+        return fail(MLCC_ERR_INVALID, "device %d out of range (%d devices)", device, ndev);
+    MLCC_HIP(hipSetDevice(device));
+    mlcc_ctx *c = new (std::nothrow) mlcc_ctx();
+    if (!c) return fail(MLCC_ERR_NOMEM, "context allocation failed");
+    c->impl.device = device;
+    c->impl.stream = static_cast<hipStream_t>(hip_stream);
+    *out = c;
+    clear_error();
+    return MLCC_OK;
+}
+
+void mlcc_destroy(mlcc_ctx *ctx)
+{
+    if (!ctx) return;
+    Ctx &c = ctx->impl;
+    (void)hipSetDevice(c.device);
+    (void)hipStreamSynchronize(c.stream);
+    DevBuf *bufs[] = {&c.stars, &c.mass, &c.iter[0], &c.iter[1], &c.flagrow, &c.fronts,
+                      &c.counts, &c.control, &c.etab, &c.bnd, &c.perm, &c.match_aux,
+                      &c.relabel, &c.workflags, &c.diff, &c.err, &c.edt_col};
+    for (DevBuf *b : bufs) b->release();
+    if (c.pinned) (void)hipHostFree(c.pinned);
+    delete ctx;
+}
+
+mlcc_status mlcc_set_stream(mlcc_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return fail(MLCC_ERR_INVALID, "ctx is NULL");
+    ctx->impl.stream = static_cast<hipStream_t>(hip_stream);
+    return MLCC_OK;
+}
+
+void mlcc_cc_params_default(mlcc_cc_params *p, int64_t m_steps)
+{
+    if (!p) return;
+    memset(p, 0, sizeof *p);
+    p->m_steps = m_steps;
+    p->n_subchains = 0;
+    p->max_iter_cold = 500;
+    p->max_iter_warm = 100;
+    p->precision = MLCC_FP64;
+    p->tol_step = 1e-9;
+    p->tol_inv_mu = 1e-9;
+    p->timing = 0;
+}
+
+mlcc_status mlcc_set_lenses(mlcc_ctx *ctx, int64_t n, const double *x, const double *y,
+                            const double *m, double kappa_s, double gamma)
+{
+    if (!ctx) return fail(MLCC_ERR_INVALID, "ctx is NULL");
+    Ctx &c = ctx->impl;
+    MLCC_TRY(use_device(&c));
+    if (n < 1) return fail(MLCC_ERR_INVALID, "need at least one star (n=%lld)", (long long)n);
+    if (n > (int64_t)1 << 28) return fail(MLCC_ERR_INVALID, "too many stars (%lld)", (long long)n);
+    MLCC_TRY(check_device_ptr(&c, x, "x"));
+    MLCC_TRY(check_device_ptr(&c, y, "y"));
+    MLCC_TRY(check_device_ptr(&c, m, "m"));
+    if (!std::isfinite(kappa_s) || !std::isfinite(gamma))
+        return fail(MLCC_ERR_INVALID, "kappa_s and gamma must be finite");
+    if (std::fabs(gamma) == std::fabs(1.0 - kappa_s))
+        return fail(MLCC_ERR_INVALID,
+                    "|gamma| == |1 - kappa_s|: gamma - (1-kappa_s) e^{-i phi} vanishes on the "
+                    "phase circle");
+    std::vector<double> hx(n), hy(n), hm(n);
+    MLCC_HIP(hipMemcpyAsync(hx.data(), x, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    MLCC_HIP(hipMemcpyAsync(hy.data(), y, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    MLCC_HIP(hipMemcpyAsync(hm.data(), m, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    MLCC_HIP(hipStreamSynchronize(c.stream));
+    bool equal = true;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || !std::isfinite(hm[i]) || !(hm[i] > 0))
+            return fail(MLCC_ERR_INVALID, "star %lld: non-finite position or mass <= 0",
+                        (long long)i);
+        if (hm[i] != hm[0]) equal = false;
+    }
+    {
+        std::vector<int64_t> idx(n);
+        for (int64_t i = 0; i < n; ++i) idx[i] = i;
+        std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+            return hx[a] < hx[b] || (hx[a] == hx[b] && hy[a] < hy[b]);
+        });
+        for (int64_t i = 1; i < n; ++i)
+            if (hx[idx[i]] == hx[idx[i - 1]] && hy[idx[i]] == hy[idx[i - 1]])
+                return fail(MLCC_ERR_INVALID, "stars %lld and %lld share a position",
+                            (long long)idx[i - 1], (long long)idx[i]);
+    }
+    std::vector<double> xy(2 * n);
+    for (int64_t i = 0; i < n; ++i) {
+        xy[2 * i] = hx[i];
+        xy[2 * i + 1] = hy[i];
+    }
+    MLCC_TRY(c.stars.reserve(2 * n * sizeof(double)));
+    MLCC_TRY(c.mass.reserve(n * sizeof(double)));
+    MLCC_HIP(hipMemcpyAsync(c.stars.p, xy.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice,
+                            c.stream));
+    MLCC_HIP(hipMemcpyAsync(c.mass.p, hm.data(), n * sizeof(double), hipMemcpyHostToDevice,
+                            c.stream));
+    MLCC_HIP(hipStreamSynchronize(c.stream));
+    c.n = n;
+    c.kappa_s = kappa_s;
+    c.gamma = gamma;
+    c.equal_mass = equal;
+    c.mass0 = hm[0];
+    clear_error();
+    return MLCC_OK;
+}
+
+mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *params,
+                                      double *roots_re, double *roots_im, int32_t *chain_next,
+                                      mlcc_cc_stats *stats)
+{
+    if (!ctx || !params) return fail(MLCC_ERR_INVALID, "ctx or params is NULL");
+    Ctx &c = ctx->impl;
+    MLCC_TRY(use_device(&c));
+    if (c.n < 1) return fail(MLCC_ERR_STATE, "call mlcc_set_lenses first");
+    const mlcc_cc_params &p = *params;
+    if (p.m_steps < 2 || (p.m_steps & 1))
+        return fail(MLCC_ERR_INVALID, "m_steps must be even and >= 2 (got %lld)",
+                    (long long)p.m_steps);
+    if (p.m_steps > (int64_t)1 << 30) return fail(MLCC_ERR_INVALID, "m_steps too large");
+    if (p.n_subchains < 0 || (p.n_subchains > 0 && (p.m_steps / 2) % p.n_subchains))
+        return fail(MLCC_ERR_INVALID, "n_subchains=%d must divide m_steps/2=%lld",
+                    p.n_subchains, (long long)(p.m_steps / 2));
+    if (!(p.tol_step > 0) || !std::isfinite(p.tol_step))
+        return fail(MLCC_ERR_INVALID, "tol_step must be positive and finite");
+    if (!(p.tol_inv_mu >= 0) || !std::isfinite(p.tol_inv_mu))
+        return fail(MLCC_ERR_INVALID, "tol_inv_mu must be >= 0 and finite");
+    if (p.max_iter_cold < 0 || p.max_iter_warm < 0)
+        return fail(MLCC_ERR_INVALID, "iteration caps must be >= 0");
+    if (p.precision != MLCC_FP64)
+        return fail(MLCC_ERR_INVALID, "unknown precision %d", p.precision);
+    MLCC_TRY(check_device_ptr(&c, roots_re, "roots_re"));
+    MLCC_TRY(check_device_ptr(&c, roots_im, "roots_im"));
+    if (chain_next) MLCC_TRY(check_device_ptr(&c, chain_next, "chain_next"));
+    clear_error();
+    return find_critical_curves_fp64(&c, &p, roots_re, roots_im, chain_next, stats);
+}
+
+mlcc_status mlcc_map_caustics(mlcc_ctx *ctx, int64_t count, const double *z_re,
+                              const double *z_im, double *w_re, double *w_im)
+{
+    if (!ctx) return fail(MLCC_ERR_INVALID, "ctx is NULL");
+    Ctx &c = ctx->impl;
+    MLCC_TRY(use_device(&c));
+    if (c.n < 1) return fail(MLCC_ERR_STATE, "call mlcc_set_lenses first");
+    if (count < 0) return fail(MLCC_ERR_INVALID, "count < 0");
+    if (count == 0) return MLCC_OK;
+    MLCC_TRY(check_device_ptr(&c, z_re, "z_re"));
+    MLCC_TRY(check_device_ptr(&c, z_im, "z_im"));
+    MLCC_TRY(check_device_ptr(&c, w_re, "w_re"));
+    MLCC_TRY(check_device_ptr(&c, w_im, "w_im"));
+    if (w_re == z_re || w_re == z_im || w_im == z_re || w_im == z_im)
+        return fail(MLCC_ERR_INVALID, "w may not alias z");
+    clear_error();
+    return launch_map_caustics(&c, count, z_re, z_im, w_re, w_im);
+}
+
+mlcc_status mlcc_caustic_crossings(mlcc_ctx *ctx, int64_t rows, int64_t n_r, const double *w_re,
+                                   const double *w_im, const int32_t *chain_next,
+                                   const mlcc_grid *grid, int32_t *ncc)
+{
+    if (!ctx) return fail(MLCC_ERR_INVALID, "ctx is NULL");
+    Ctx &c = ctx->impl;
+    MLCC_TRY(use_device(&c));
+    if (rows < 1 || n_r < 1) return fail(MLCC_ERR_INVALID, "need rows >= 1 and n_r >= 1");
+    if (rows > ((int64_t)1 << 40) / n_r) return fail(MLCC_ERR_INVALID, "rows * n_r too large");
+    MLCC_TRY(check_grid(grid, false));
+    MLCC_TRY(check_device_ptr(&c, w_re, "w_re"));
+    MLCC_TRY(check_device_ptr(&c, w_im, "w_im"));
+    if (chain_next) MLCC_TRY(check_device_ptr(&c, chain_next, "chain_next"));
+    MLCC_TRY(check_device_ptr(&c, ncc, "ncc"));
+    clear_error();
+    return run_caustic_crossings(&c, rows, n_r, w_re, w_im, chain_next, grid, ncc);
+}
+
+mlcc_status mlcc_caustic_distances(mlcc_ctx *ctx, const mlcc_grid *grid, const int32_t *ncc,
+                                   double *dist, uint8_t *border_limited)
+{
+    if (!ctx) return fail(MLCC_ERR_INVALID, "ctx is NULL");
+    Ctx &c = ctx->impl;
+    MLCC_TRY(use_device(&c));
+    MLCC_TRY(check_grid(grid, true));
+    MLCC_TRY(check_device_ptr(&c, ncc, "ncc"));
+    MLCC_TRY(check_device_ptr(&c, dist, "dist"));
+    if (border_limited) MLCC_TRY(check_device_ptr(&c, border_limited, "border_limited"));
+    clear_error();
+    return launch_caustic_distances(&c, grid, ncc, dist, border_limited);
+}
+
+} // extern "C"

@@ -1,0 +1,156 @@
+// Caustic-crossing map (Sec. 5.1): N_cc at each pixel centre is the winding
+// number of the clockwise caustic polygons about it (Sunday's rule, signed so
+// that a clockwise loop counts +1).  Following the Sec. 5.1 footnote the work
+// is done per edge, not per pixel: for every pixel row whose centre height an
+// edge spans (half-open, lo <= y < hi), the first column whose centre lies
+// strictly right of the crossing receives the edge's sign (+1 upward,
+// -1 downward) in a per-row difference map; a prefix sum along each row then
+// yields N_cc.
+//
+// Exactness: vertices go on a lattice of 2^24 points per pixel; pixel centres
+// are lattice points; the crossing test is a 128-bit integer comparison, and
+// the first column is a floating-point estimate corrected by that exact test.
+#include "mlcc_internal.h"
+
+namespace mlcc {
+
+constexpr int QBITS = 24;
+constexpr int64_t HALF = (int64_t)1 << (QBITS - 1); // half a pixel on the lattice
+constexpr double QSCALE = 16777216.0;               // 2^QBITS
+constexpr double QLIMIT = 9007199254740992.0;       // 2^53
+
+__device__ __forceinline__ bool to_lattice(double v, double v0, double h, int64_t *q)
+{
+    const double s = (v - v0) / h * QSCALE;
+    if (!(fabs(s) < QLIMIT)) return false; // also rejects NaN
+    *q = (int64_t)rint(s);
+    return true;
+}
+
+// floor(a / b) for b > 0
+__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && (a < 0)) --q;
+    return q;
+}
+
+__global__ void __launch_bounds__(256)
+crossing_edges(int64_t rows, int64_t n_r, const double *__restrict__ wr,
+               const double *__restrict__ wi, const int32_t *__restrict__ chain_next,
+               double x0, double y0, double hx, double hy, int32_t nx, int32_t ny,
+               int32_t *__restrict__ diff, int32_t *__restrict__ err)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * n_r) return;
+    const int64_t j = e / n_r, k = e - j * n_r;
+    int64_t j2 = j + 1, k2 = k;
+    if (j2 == rows) {
+        j2 = 0;
+        k2 = chain_next ? chain_next[k] : k;
+        if (k2 < 0 || k2 >= n_r) {
+            atomicOr(err, 2);
+            return;
+        }
+    }
+    int64_t ax, ay, bx, by;
+    if (!to_lattice(wr[e], x0, hx, &ax) || !to_lattice(wi[e], y0, hy, &ay) ||
+        !to_lattice(wr[j2 * n_r + k2], x0, hx, &bx) || !to_lattice(wi[j2 * n_r + k2], y0, hy, &by)) {
+        atomicOr(err, 1);
+        return;
+    }
+    if (ay == by) return;
+    int s = 1;
+    if (ay > by) {   // order the ends by height; a downward edge counts -1
+        int64_t t = ax; ax = bx; bx = t;
+        t = ay; ay = by; by = t;
+        s = -1;
+    }
+    // rows r with (2r+1) HALF in [ay, by)
+    int64_t r0 = floor_div64(ay + HALF - 1, 2 * HALF);
+    int64_t r1 = floor_div64(by + HALF - 1, 2 * HALF);
+    if (r0 < 0) r0 = 0;
+    if (r1 > ny) r1 = ny;
+    const int64_t dy = by - ay, dx = bx - ax;
+    const double slope = (double)dx / (double)dy;
+    for (int64_t r = r0; r < r1; ++r) {
+        const int64_t yr = (2 * r + 1) * HALF;
+        // crossing x = ax + (yr - ay) dx / dy = num / dy
+        const __int128 num = (__int128)ax * dy + (__int128)(yr - ay) * dx;
+        // column c's centre (2c+1) HALF is strictly right of the crossing
+        // iff (2c+1) HALF dy > num
+        auto right = [&](int64_t c) {
+            return (__int128)(2 * c + 1) * HALF * dy > num;
+        };
+        const double xc = (double)ax + (double)(yr - ay) * slope;
+        double cest = floor((xc / (double)HALF - 1.0) * 0.5) + 1.0;
+        cest = fmin(fmax(cest, 0.0), (double)nx);
+        int64_t c = (int64_t)cest;
+        while (c > 0 && right(c - 1)) --c;
+        while (c < nx && !right(c)) ++c;
+        if (c < nx) atomicAdd(&diff[r * nx + c], s);
+    }
+}
+
+// Inclusive prefix sum along each row: one 256-lane work-group per row,
+// 64-lane wave scans joined through LDS, chunk by chunk.
+__global__ void __launch_bounds__(256)
+row_prefix(const int32_t *__restrict__ diff, int32_t *__restrict__ ncc, int32_t nx)
+{
+    __shared__ int32_t wave_tot[4];
+    __shared__ int32_t carry;
+    const int r = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nx; base += 256) {
+        const int c = base + tid;
+        int v = c < nx ? diff[(int64_t)r * nx + c] : 0;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(v, off, 64);
+            if (lane >= off) v += t;
+        }
+        if (lane == 63) wave_tot[w] = v;
+        __syncthreads();
+        int add = carry;
+        for (int q = 0; q < w; ++q) add += wave_tot[q];
+        v += add;
+        if (c < nx) ncc[(int64_t)r * nx + c] = v;
+        __syncthreads();
+        if (tid == 255) carry = v;
+        __syncthreads();
+    }
+}
+
+mlcc_status run_caustic_crossings(Ctx *c, int64_t rows, int64_t n_r, const double *wr,
+                                  const double *wi, const int32_t *chain_next,
+                                  const mlcc_grid *g, int32_t *ncc)
+{
+    const int64_t nx = g->nx, ny = g->ny;
+    const double x0 = g->center_re - g->half_width, y0 = g->center_im - g->half_height;
+    const double hx = (2.0 * g->half_width) / (double)nx, hy = (2.0 * g->half_height) / (double)ny;
+    MLCC_TRY(c->diff.reserve((size_t)nx * ny * sizeof(int32_t)));
+    MLCC_TRY(c->err.reserve(sizeof(int32_t)));
+    MLCC_HIP(hipMemsetAsync(c->diff.p, 0, (size_t)nx * ny * sizeof(int32_t), c->stream));
+    MLCC_HIP(hipMemsetAsync(c->err.p, 0, sizeof(int32_t), c->stream));
+    const int64_t ne = rows * n_r;
+    const int64_t blocks = ceil_div(ne, 256);
+    if (blocks > 0x7fffffff) return fail(MLCC_ERR_INVALID, "too many edges");
+    hipLaunchKernelGGL(crossing_edges, dim3((unsigned)blocks), dim3(256), 0, c->stream, rows, n_r,
+                       wr, wi, chain_next, x0, y0, hx, hy, (int32_t)nx, (int32_t)ny,
+                       c->diff.as<int32_t>(), c->err.as<int32_t>());
+    hipLaunchKernelGGL(row_prefix, dim3((unsigned)ny), dim3(256), 0, c->stream,
+                       c->diff.as<int32_t>(), ncc, (int32_t)nx);
+    MLCC_HIP(hipGetLastError());
+    int32_t herr = 0;
+    MLCC_HIP(hipMemcpyAsync(&herr, c->err.p, sizeof herr, hipMemcpyDeviceToHost, c->stream));
+    MLCC_HIP(hipStreamSynchronize(c->stream));
+    if (herr & 1)
+        return fail(MLCC_ERR_INVALID,
+                    "a caustic vertex is not finite or lies more than 2^29 pixels from the grid");
+    if (herr & 2) return fail(MLCC_ERR_INVALID, "chain_next holds an index outside [0, n_r)");
+    return MLCC_OK;
+}
+
+} // namespace mlcc

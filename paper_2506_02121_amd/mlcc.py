@@ -1,0 +1,246 @@
+"""Thin ctypes binding of libmlcc.so (the C-ABI declared in include/mlcc.h).
+
+Argument marshalling only: torch supplies device memory and the HIP stream,
+every computation runs in the library's HIP kernels.  If the library is not
+built this module raises on import; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmlcc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_02121_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MLCC_OK = 0
+MLCC_ERR_INVALID = -1
+MLCC_ERR_HIP = -2
+MLCC_ERR_NOMEM = -3
+MLCC_ERR_NOT_CONVERGED = -4
+MLCC_ERR_STATE = -5
+MLCC_ERR_MATCH = -7
+MLCC_FP64 = 0
+
+EXPORTED = [
+    "mlcc_create", "mlcc_destroy", "mlcc_set_stream", "mlcc_last_error", "mlcc_set_lenses",
+    "mlcc_cc_params_default", "mlcc_find_critical_curves", "mlcc_map_caustics",
+    "mlcc_caustic_crossings", "mlcc_caustic_distances",
+]
+
+
+class CCParams(ctypes.Structure):
+    _fields_ = [("m_steps", ctypes.c_int64), ("n_subchains", ctypes.c_int32),
+                ("max_iter_cold", ctypes.c_int32), ("max_iter_warm", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("tol_step", ctypes.c_double),
+                ("tol_inv_mu", ctypes.c_double), ("timing", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class CCStats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("root_updates", ctypes.c_int64),
+                ("unconverged", ctypes.c_int64), ("rows_capped", ctypes.c_int64),
+                ("n_subchains", ctypes.c_int32), ("max_row_sweeps", ctypes.c_int32),
+                ("cold_sweeps", ctypes.c_int32), ("polls", ctypes.c_int32),
+                ("match_maxdist", ctypes.c_double), ("sweep_ms", ctypes.c_double),
+                ("algorithmic_flop", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class GridC(ctypes.Structure):
+    _fields_ = [("center_re", ctypes.c_double), ("center_im", ctypes.c_double),
+                ("half_width", ctypes.c_double), ("half_height", ctypes.c_double),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_d = ctypes.c_double
+_SIG = {
+    "mlcc_create": ([ctypes.POINTER(_vp), ctypes.c_int, _vp], ctypes.c_int),
+    "mlcc_destroy": ([_vp], None),
+    "mlcc_set_stream": ([_vp, _vp], ctypes.c_int),
+    "mlcc_last_error": ([], ctypes.c_char_p),
+    "mlcc_set_lenses": ([_vp, _i64, _vp, _vp, _vp, _d, _d], ctypes.c_int),
+    "mlcc_cc_params_default": ([ctypes.POINTER(CCParams), _i64], None),
+    "mlcc_find_critical_curves": ([_vp, ctypes.POINTER(CCParams), _vp, _vp, _vp,
+                                   ctypes.POINTER(CCStats)], ctypes.c_int),
+    "mlcc_map_caustics": ([_vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "mlcc_caustic_crossings": ([_vp, _i64, _i64, _vp, _vp, _vp, ctypes.POINTER(GridC), _vp],
+                               ctypes.c_int),
+    "mlcc_caustic_distances": ([_vp, ctypes.POINTER(GridC), _vp, _vp, _vp], ctypes.c_int),
+}
+for _name, (_args, _res) in _SIG.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class MlccError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"mlcc error {code}: {message}")
+        self.code = code
+
+
+def _check(code: int):
+    if code != MLCC_OK:
+        raise MlccError(code, _lib.mlcc_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, device, what: str):
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != device or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous {dtype} tensor on {device}")
+
+
+@dataclass
+class Grid:
+    center_re: float
+    center_im: float
+    half_width: float
+    half_height: float
+    nx: int
+    ny: int
+
+    def c(self) -> GridC:
+        return GridC(float(self.center_re), float(self.center_im), float(self.half_width),
+                     float(self.half_height), int(self.nx), int(self.ny))
+
+
+def as_grid(g) -> Grid:
+    return Grid(g.center_re, g.center_im, g.half_width, g.half_height, g.nx, g.ny)
+
+
+class Context:
+    """One library context on one GPU.  Every call enqueues on torch's
+    current stream of that device."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        h = _vp()
+        _check(_lib.mlcc_create(ctypes.byref(h), int(device),
+                                _vp(torch.cuda.current_stream(self.device).cuda_stream)))
+        self._h = h
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.mlcc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        _check(_lib.mlcc_set_stream(self._h, _vp(torch.cuda.current_stream(self.device).cuda_stream)))
+
+    def set_lenses(self, x: torch.Tensor, y: torch.Tensor, m: torch.Tensor, kappa_s: float,
+                   gamma: float):
+        for t, w in ((x, "x"), (y, "y"), (m, "m")):
+            _need(t, torch.float64, self.device, w)
+        self._stream()
+        _check(_lib.mlcc_set_lenses(self._h, x.numel(), _ptr(x), _ptr(y), _ptr(m),
+                                    float(kappa_s), float(gamma)))
+        self.n = x.numel()
+
+    @staticmethod
+    def default_params(m_steps: int) -> CCParams:
+        p = CCParams()
+        _lib.mlcc_cc_params_default(ctypes.byref(p), int(m_steps))
+        return p
+
+    def find_critical_curves(self, m_steps: int, n_subchains: int = 0, tol_step: float = 1e-9,
+                             tol_inv_mu: float = 1e-9, max_iter_cold: int = 500,
+                             max_iter_warm: int = 100, timing: bool = False,
+                             chain_next: bool = True, out=None, raise_on_error: bool = True):
+        """Returns (roots_re, roots_im, chain_next, stats, status); roots are
+        (m_steps + 1, 2N) float64 device tensors."""
+        p = self.default_params(m_steps)
+        p.n_subchains = int(n_subchains)
+        p.tol_step = float(tol_step)
+        p.tol_inv_mu = float(tol_inv_mu)
+        p.max_iter_cold = int(max_iter_cold)
+        p.max_iter_warm = int(max_iter_warm)
+        p.timing = int(bool(timing))
+        n_r = 2 * self.n
+        if out is None:
+            rr = torch.empty((m_steps + 1, n_r), dtype=torch.float64, device=self.device)
+            ri = torch.empty_like(rr)
+        else:
+            rr, ri = out
+        cn = torch.empty(n_r, dtype=torch.int32, device=self.device) if chain_next else None
+        st = CCStats()
+        self._stream()
+        code = _lib.mlcc_find_critical_curves(self._h, ctypes.byref(p), _ptr(rr), _ptr(ri),
+                                              _ptr(cn), ctypes.byref(st))
+        if raise_on_error:
+            _check(code)
+        return rr, ri, cn, st.as_dict(), code
+
+    def map_caustics(self, z_re: torch.Tensor, z_im: torch.Tensor, out=None):
+        _need(z_re, torch.float64, self.device, "z_re")
+        _need(z_im, torch.float64, self.device, "z_im")
+        if out is None:
+            wr, wi = torch.empty_like(z_re), torch.empty_like(z_im)
+        else:
+            wr, wi = out
+        self._stream()
+        _check(_lib.mlcc_map_caustics(self._h, z_re.numel(), _ptr(z_re), _ptr(z_im), _ptr(wr),
+                                      _ptr(wi)))
+        return wr, wi
+
+    def caustic_crossings(self, w_re: torch.Tensor, w_im: torch.Tensor,
+                          chain_next: Optional[torch.Tensor], grid, out=None):
+        _need(w_re, torch.float64, self.device, "w_re")
+        _need(w_im, torch.float64, self.device, "w_im")
+        if w_re.dim() != 2 or w_re.shape != w_im.shape:
+            raise ValueError("w_re, w_im must be (rows, n_r)")
+        if chain_next is not None:
+            _need(chain_next, torch.int32, self.device, "chain_next")
+        g = as_grid(grid)
+        ncc = out if out is not None else torch.empty((g.ny, g.nx), dtype=torch.int32,
+                                                      device=self.device)
+        self._stream()
+        gc = g.c()
+        _check(_lib.mlcc_caustic_crossings(self._h, w_re.shape[0], w_re.shape[1], _ptr(w_re),
+                                           _ptr(w_im), _ptr(chain_next), ctypes.byref(gc),
+                                           _ptr(ncc)))
+        return ncc
+
+    def caustic_distances(self, grid, ncc: torch.Tensor, border_limited: bool = True, out=None):
+        _need(ncc, torch.int32, self.device, "ncc")
+        g = as_grid(grid)
+        if out is None:
+            dist = torch.empty((g.ny, g.nx), dtype=torch.float64, device=self.device)
+            bl = torch.empty((g.ny, g.nx), dtype=torch.uint8, device=self.device) if border_limited else None
+        else:
+            dist, bl = out
+        self._stream()
+        gc = g.c()
+        _check(_lib.mlcc_caustic_distances(self._h, ctypes.byref(gc), _ptr(ncc), _ptr(dist),
+                                           _ptr(bl)))
+        return dist, bl
+
+
+def last_error() -> str:
+    return _lib.mlcc_last_error().decode()
+
+
+def library():
+    return _lib
