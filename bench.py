@@ -3,9 +3,10 @@ distance-map path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload n10k]
 
-One step = set_lenses + find_critical_curves (all m+1 rows) + map_caustics
-(every root) + caustic_crossings + caustic_distances on one seeded synthetic
-field whose inputs are already in HBM.  Prints one JSON line:
+One step = set_lenses + find_critical_curves (all m+1 rows, with the caustic
+image of every root mapped in the same pass) + caustic_crossings +
+caustic_distances on one seeded synthetic field whose inputs are already in
+HBM.  Prints one JSON line:
   value           roots/s = m * 2N / (seconds per step)
   roofline        the root-finder sweep kernel: algorithmic FP64 FLOP per
                   sweep launch / its HIP-event-timed duration, against the
@@ -45,6 +46,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n10k", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--subchains", type=int, default=0, help="0 = library choice")
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-sweeps", type=int, default=2,
@@ -94,9 +96,10 @@ def main():
 
     def step():
         ctx.set_lenses(x, y, mm, f.kappa_s, f.gamma)
-        _, _, cn, st, _ = ctx.find_critical_curves(m_steps, timing=True,
-                                                   out=(roots_re, roots_im))
-        ctx.map_caustics(roots_re.view(-1), roots_im.view(-1), out=(w_re.view(-1), w_im.view(-1)))
+        # roots and, in the same pass, their caustic images
+        _, _, _, _, cn, st, _ = ctx.find_critical_curves(
+            m_steps, n_subchains=args.subchains, timing=True, caustics=True,
+            out=(roots_re, roots_im), caustics_out=(w_re, w_im))
         ctx.caustic_crossings(w_re, w_im, cn, grid, out=ncc)
         ctx.caustic_distances(grid, ncc, out=(dist, bl))
         return st

@@ -123,6 +123,14 @@ typedef struct {
  *                       roots at phi_j.  Column k is one continuous chain over
  *                       rows 0..m (subchain blocks are relabelled through the
  *                       nearest-neighbour pairing of their shared boundary row).
+ *   caustics_re, caustics_im
+ *                       device float64[(m+1) * 2N] or both NULL: the lens-equation
+ *                       image w of every root (the caustics, Sec. 3.1), same
+ *                       layout and chains.  Evaluated in the same pass from the
+ *                       star sums at the last iterate z and the final step D:
+ *                       sum m_i/(z - D - z_i) = sum m_i u_i + D sum m_i u_i^2
+ *                       + D^2 sum m_i u_i^3 + O(D^3), with |D| below the cutoffs;
+ *                       mlcc_map_caustics gives the same images directly.
  *   chain_next          device int32[2N] or NULL: chain_next[k] = the column
  *                       whose row 0 continues column k's row m (phi = 2 pi and
  *                       phi = 0 give the same roots; Sec. 4.3 footnote).
@@ -131,8 +139,9 @@ typedef struct {
  * MLCC_ERR_MATCH if duplicate rows did not pair one-to-one within 1e-6.
  */
 mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *params,
-                                      double *roots_re, double *roots_im,
-                                      int32_t *chain_next, mlcc_cc_stats *stats);
+                                      double *roots_re, double *roots_im, double *caustics_re,
+                                      double *caustics_im, int32_t *chain_next,
+                                      mlcc_cc_stats *stats);
 
 /*
  * map_caustics -- the lens equation (Sec. 3.1, infinite sheet of App. A) at

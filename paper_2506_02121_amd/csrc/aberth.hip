@@ -4,10 +4,13 @@
 //
 // Layout and scheduling (gfx950):
 //  * One lane per root, one 64-lane wavefront per work-group.  Each
-//    work-group owns 64*RPL consecutive roots of one "front" (a growing end
-//    of a subchain).  Star positions and the other roots are wave-uniform
-//    reads, so they arrive through scalar loads and feed the FP64 VALU as
-//    SGPR operands: no LDS, no barriers.
+//    work-group owns 64 consecutive roots of one "front" (a growing end of a
+//    subchain).  Star positions and the other roots stream through LDS in
+//    tiles and are read back as wave-uniform broadcasts.
+//  * A block with only a few unflagged roots left (the last sweep of a row)
+//    works on them one at a time with the whole wave, so such sweeps cost
+//    ~1/64 of a full one instead of the same latency.
+//  * Roots flagged converged are mapped to the caustic in the same kernel.
 //  * Jacobi double buffering: a sweep reads iterate `cur` and writes `nxt`;
 //    the host alternates the two on every launch.  A root flagged converged
 //    is copied forward unchanged.
@@ -17,6 +20,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "mlcc_internal.h"
@@ -44,17 +48,184 @@ __device__ __forceinline__ double rcp_refined(double x)
 constexpr int RCP_STAR = 2;
 constexpr int RCP_ROOT = 1;
 
-template <int RPL, bool EQUAL>
+// Streams the records p[0..n) through body(i, p[i]) for a one-wave work
+// group.  Tiles of 64 records (one per lane) are fetched with coalesced
+// vector loads, the next tile while the current one is consumed, parked in
+// LDS, and read back with one wave-uniform (broadcast) LDS read per record.
+// Vector loads retire in order, so waiting for the older tile never waits
+// for the prefetch behind it.  Indices past n-1 are clamped on load, so
+// nothing outside the array is read.  `lds` holds two tiles.
+template <class T, class Body>
+__device__ __forceinline__ void stream_tiles(const T *__restrict__ p, int n, T *lds, Body &&body)
+{
+    if (n <= 0) return;
+    const int lane = threadIdx.x;
+    const int ntiles = (n + 63) >> 6;
+    T reg = p[min(lane, n - 1)];
+    for (int t = 0; t < ntiles; ++t) {
+        T *buf = lds + ((t & 1) << 6);
+        buf[lane] = reg;
+        __syncthreads();
+        if (t + 1 < ntiles) reg = p[min(((t + 1) << 6) + lane, n - 1)];
+        const int base = t << 6;
+        const int cnt = min(64, n - base);
+        if (cnt == 64) {
+#pragma unroll 8
+            for (int k = 0; k < 64; ++k) body(base + k, buf[k]);
+        } else {
+            for (int k = 0; k < cnt; ++k) body(base + k, buf[k]);
+        }
+    }
+    __syncthreads();
+}
+
+// Star records: (x, y) when all masses are equal (the common mass is applied
+// once at the end), (x, y, m, 0) otherwise.
+template <bool EQUAL> struct StarRec;
+template <> struct StarRec<true> {
+    using T = double2;
+    static __device__ __forceinline__ double mass(const double2 &) { return 1.0; }
+};
+template <> struct StarRec<false> {
+    using T = double4;
+    static __device__ __forceinline__ double mass(const double4 &s) { return s.z; }
+};
+
+// Running sums for one root z, u_i = 1/(z - z_i):
+//   s1 = sum u_i                (for P'/P = F'/F + 2 s1)
+//   s0 = sum m_i u_i            (lens mapping; equals m0 s1 for equal masses)
+//   s2 = sum m_i u_i^2          (F = gamma + s2 - (1 - kappa_s) e^{-i phi})
+//   s3 = sum m_i u_i^3          (F' = -2 s3)
+//   R  = sum_{r != k} 1/(z - z_r)
+// For equal masses the m_i factors are left out and applied once at the end.
+struct Sums {
+    double s1r, s1i, s0r, s0i, s2r, s2i, s3r, s3i, Rr, Ri;
+};
+
+__device__ __forceinline__ void zero(Sums &S)
+{
+    S.s1r = S.s1i = S.s0r = S.s0i = S.s2r = S.s2i = S.s3r = S.s3i = S.Rr = S.Ri = 0.0;
+}
+
+template <bool EQUAL, class T>
+__device__ __forceinline__ void add_star(Sums &S, double zr, double zi, const T &s)
+{
+    const double dx = zr - s.x;
+    const double dy = zi - s.y;
+    const double inv = rcp_refined<RCP_STAR>(fma(dx, dx, dy * dy));
+    // u = ux - i uy = conj(d) / |d|^2
+    const double ux = dx * inv;
+    const double uy = dy * inv;
+    S.s1r += ux;
+    S.s1i -= uy;
+    // u^2 = vx + i vy
+    const double vx = fma(ux, ux, -uy * uy);
+    const double vy = -2.0 * ux * uy;
+    // u^3 = u^2 u
+    const double tx = fma(vx, ux, vy * uy);
+    const double ty = fma(vy, ux, -vx * uy);
+    if (EQUAL) {
+        S.s2r += vx;
+        S.s2i += vy;
+        S.s3r += tx;
+        S.s3i += ty;
+    } else {
+        const double mi = StarRec<EQUAL>::mass(s);
+        S.s0r = fma(mi, ux, S.s0r);
+        S.s0i = fma(-mi, uy, S.s0i);
+        S.s2r = fma(mi, vx, S.s2r);
+        S.s2i = fma(mi, vy, S.s2i);
+        S.s3r = fma(mi, tx, S.s3r);
+        S.s3i = fma(mi, ty, S.s3i);
+    }
+}
+
+__device__ __forceinline__ void add_root(Sums &S, double zr, double zi, const double2 &o)
+{
+    const double dx = zr - o.x, dy = zi - o.y;
+    const double inv = rcp_refined<RCP_ROOT>(fma(dx, dx, dy * dy));
+    S.Rr = fma(dx, inv, S.Rr);
+    S.Ri = fma(-dy, inv, S.Ri);
+}
+
+__device__ __forceinline__ void wave_sum(double &v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+}
+
+struct Update {
+    double zr, zi;   // new iterate
+    double wr, wi;   // its image under the lens map
+    bool flag;       // converged
+};
+
+// One Aberth-Ehrlich update from the sums at z (Sec. 3.2), the convergence
+// test of the Sec. 3.2 footnote with the App. C bound on |1/mu|, and the
+// lens map at the new iterate.  The map reuses the sums: with
+// z' = z - D, sum m_i/(z' - z_i) = s0 + D s2 + D^2 s3 + O(D^3 sum m_i u_i^4),
+// and D is below the convergence cutoffs once a root is flagged.
+template <bool EQUAL>
+__device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0, double2 e,
+                                         double gamma, double a, double a1, double tol_step2,
+                                         double tol_mu, int k)
+{
+    if (EQUAL) {   // every mass equals m0: the sums above left it out
+        S.s0r = m0 * S.s1r;
+        S.s0i = m0 * S.s1i;
+        S.s2r *= m0;
+        S.s2i *= m0;
+        S.s3r *= m0;
+        S.s3i *= m0;
+    }
+    // F = gamma + S2 - (1 - kappa_s) e^{-i phi}, F' = -2 S3
+    const double Fr = gamma + S.s2r - e.x, Fi = S.s2i - e.y;
+    const double Fpr = -2.0 * S.s3r, Fpi = -2.0 * S.s3i;
+    // Aberth step: 1 / (F'/F + 2 S1 - R) = F / (F' + F (2 S1 - R))
+    const double Gr = 2.0 * S.s1r - S.Rr, Gi = 2.0 * S.s1i - S.Ri;
+    const double Dr = Fpr + (Fr * Gr - Fi * Gi);
+    const double Di = Fpi + (Fr * Gi + Fi * Gr);
+    const double den = Dr * Dr + Di * Di;
+    const double stepr = (Fr * Dr + Fi * Di) / den;
+    const double stepi = (Fi * Dr - Fr * Di) / den;
+    Update u;
+    u.zr = zr - stepr;
+    u.zi = zi - stepi;
+    const double aF = sqrt(Fr * Fr + Fi * Fi);
+    u.flag = (stepr * stepr + stepi * stepi < tol_step2) || (aF * (aF + 2.0 * a1) < tol_mu);
+    if (!isfinite(u.zr) || !isfinite(u.zi)) {
+        // the iterate hit a star or two roots met: nudge it off, keep iterating
+        u.zr = zr + 1e-7 * (1 + (k & 7));
+        u.zi = zi + 1e-7 * (1 + (k >> 3 & 7));
+        u.flag = false;
+    }
+    // T = s0 + D s2 + D^2 s3 with D = step
+    const double d2r = stepr * stepr - stepi * stepi, d2i = 2.0 * stepr * stepi;
+    const double Tr = S.s0r + (stepr * S.s2r - stepi * S.s2i) + (d2r * S.s3r - d2i * S.s3i);
+    const double Ti = S.s0i + (stepr * S.s2i + stepi * S.s2r) + (d2r * S.s3i + d2i * S.s3r);
+    // w = (1 - kappa_s) z' + gamma conj(z') - conj(T)
+    u.wr = fma(a, u.zr, gamma * u.zr) - Tr;
+    u.wi = fma(a, u.zi, -gamma * u.zi) + Ti;
+    return u;
+}
+
+// Blocks with at most this many unflagged roots take the cooperative path.
+constexpr int SPARSE_MAX = 16;
+
+template <bool EQUAL>
 __global__ void __launch_bounds__(64)
-aberth_sweep_f64(const double2 *__restrict__ stars, const double *__restrict__ mass,
-                 double m0, int32_t n_stars, const double2 *__restrict__ cur, double2 *__restrict__ nxt,
+aberth_sweep_f64(const typename StarRec<EQUAL>::T *__restrict__ stars, double m0, int32_t n_stars,
+                 const double2 *__restrict__ cur, double2 *__restrict__ nxt,
                  int32_t *__restrict__ flagrow, const Front *__restrict__ fronts,
-                 const double2 *__restrict__ etab, double gamma, double a1, double tol_step2,
-                 double tol_mu, int32_t n_r, int32_t blocks_per_front,
+                 const double2 *__restrict__ etab, double gamma, double a, double a1,
+                 double tol_step2, double tol_mu, int32_t n_r, int32_t blocks_per_front,
                  double *__restrict__ out_re, double *__restrict__ out_im,
+                 double *__restrict__ caus_re, double *__restrict__ caus_im,
                  double2 *__restrict__ bnd, int32_t *__restrict__ counts,
                  unsigned long long *__restrict__ updates)
 {
+    using T = typename StarRec<EQUAL>::T;
+    __shared__ double4 tiles[128];   // two tiles of up to 32-byte records
     const int f = blockIdx.x / blocks_per_front;
     const int q = blockIdx.x - f * blocks_per_front;
     const int state = fronts[f].state;
@@ -64,169 +235,93 @@ aberth_sweep_f64(const double2 *__restrict__ stars, const double *__restrict__ m
     const int lane = threadIdx.x;
     const int64_t base_f = (int64_t)f * n_r;
     const double2 *__restrict__ zsrc = cur + (int64_t)src * n_r;
-    const int k0 = q * 64 * RPL;
-
-    double zr[RPL], zi[RPL];
-    bool act[RPL], valid[RPL];
-    bool any = false;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int k = k0 + r * 64 + lane;
-        valid[r] = k < n_r;
-        if (valid[r]) {
-            const double2 z = zsrc[k];
-            zr[r] = z.x;
-            zi[r] = z.y;
-            act[r] = flagrow[base_f + k] != row;
-        } else {
-            zr[r] = 0.0;
-            zi[r] = 0.0;
-            act[r] = false;
-        }
-        any = any || act[r];
+    const int k0 = q * 64;
+    const int k = k0 + lane;
+    const bool valid = k < n_r;
+    double zr = 0.0, zi = 0.0;
+    bool act = false;
+    if (valid) {
+        const double2 z = zsrc[k];
+        zr = z.x;
+        zi = z.y;
+        act = flagrow[base_f + k] != row;
     }
-    if (__ballot(any) == 0) {
-        // every root of this block already converged on this row: carry it
-#pragma unroll
-        for (int r = 0; r < RPL; ++r)
-            if (valid[r]) nxt[base_f + k0 + r * 64 + lane] = make_double2(zr[r], zi[r]);
-        return;
-    }
-
-    // S1 = sum u, S2 = sum m u^2, S3 = sum m u^3, u = 1/(z - z_i)
-    double s1r[RPL], s1i[RPL], s2r[RPL], s2i[RPL], s3r[RPL], s3i[RPL];
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) s1r[r] = s1i[r] = s2r[r] = s2i[r] = s3r[r] = s3i[r] = 0.0;
-
-#pragma unroll 2
-    for (int i = 0; i < n_stars; ++i) {
-        const double2 s = stars[i];
-        const double mi = EQUAL ? 0.0 : mass[i];
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const double dx = zr[r] - s.x;
-            const double dy = zi[r] - s.y;
-            const double inv = rcp_refined<RCP_STAR>(fma(dx, dx, dy * dy));
-            // u = ux - i uy = conj(d) / |d|^2
-            const double ux = dx * inv;
-            const double uy = dy * inv;
-            s1r[r] += ux;
-            s1i[r] -= uy;
-            // u^2 = vx + i vy
-            const double vx = fma(ux, ux, -uy * uy);
-            const double vy = -2.0 * ux * uy;
-            // u^3 = u^2 u
-            const double tx = fma(vx, ux, vy * uy);
-            const double ty = fma(vy, ux, -vx * uy);
-            if (EQUAL) {
-                s2r[r] += vx;
-                s2i[r] += vy;
-                s3r[r] += tx;
-                s3i[r] += ty;
-            } else {
-                s2r[r] = fma(mi, vx, s2r[r]);
-                s2i[r] = fma(mi, vy, s2i[r]);
-                s3r[r] = fma(mi, tx, s3r[r]);
-                s3i[r] = fma(mi, ty, s3i[r]);
-            }
-        }
-    }
-
-    // R = sum_{r != k} 1/(z_k - z_r) over the front's current iterate
-    double Rr[RPL], Ri[RPL];
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) Rr[r] = Ri[r] = 0.0;
-    const int own_lo = k0, own_hi = min(k0 + 64 * RPL, n_r);
-#pragma unroll 2
-    for (int j = 0; j < own_lo; ++j) {
-        const double2 o = zsrc[j];
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const double dx = zr[r] - o.x, dy = zi[r] - o.y;
-            const double inv = rcp_refined<RCP_ROOT>(fma(dx, dx, dy * dy));
-            Rr[r] = fma(dx, inv, Rr[r]);
-            Ri[r] = fma(-dy, inv, Ri[r]);
-        }
-    }
-    for (int j = own_lo; j < own_hi; ++j) {
-        const double2 o = zsrc[j];
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const double dx = zr[r] - o.x, dy = zi[r] - o.y;
-            const double inv = rcp_refined<RCP_ROOT>(fma(dx, dx, dy * dy));
-            const bool self = j == k0 + r * 64 + lane;
-            Rr[r] = self ? Rr[r] : fma(dx, inv, Rr[r]);
-            Ri[r] = self ? Ri[r] : fma(-dy, inv, Ri[r]);
-        }
-    }
-#pragma unroll 2
-    for (int j = own_hi; j < n_r; ++j) {
-        const double2 o = zsrc[j];
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const double dx = zr[r] - o.x, dy = zi[r] - o.y;
-            const double inv = rcp_refined<RCP_ROOT>(fma(dx, dx, dy * dy));
-            Rr[r] = fma(dx, inv, Rr[r]);
-            Ri[r] = fma(-dy, inv, Ri[r]);
-        }
-    }
+    const unsigned long long amask = __ballot(act);
+    const int n_act = __popcll(amask);
+    if (valid && !act) nxt[base_f + k] = make_double2(zr, zi);   // carried forward
+    if (n_act == 0) return;
 
     const double2 e = etab[row];
     const bool boundary = fronts[f].bnd_slot >= 0 && row == fronts[f].end_row;
     double2 *__restrict__ bnd_row = bnd + (int64_t)max(fronts[f].bnd_slot, 0) * n_r;
-    int n_after = 0, n_upd = 0;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int k = k0 + r * 64 + lane;
-        if (EQUAL) {   // every mass equals m0: the sums above left it out
-            s2r[r] *= m0;
-            s2i[r] *= m0;
-            s3r[r] *= m0;
-            s3i[r] *= m0;
-        }
-        // F = gamma + S2 - (1 - kappa_s) e^{-i phi}, F' = -2 S3
-        const double Fr = gamma + s2r[r] - e.x, Fi = s2i[r] - e.y;
-        const double Fpr = -2.0 * s3r[r], Fpi = -2.0 * s3i[r];
-        // Aberth step: 1 / (F'/F + 2 S1 - R) = F / (F' + F (2 S1 - R))
-        const double Gr = 2.0 * s1r[r] - Rr[r], Gi = 2.0 * s1i[r] - Ri[r];
-        const double Dr = Fpr + (Fr * Gr - Fi * Gi);
-        const double Di = Fpi + (Fr * Gi + Fi * Gr);
-        const double den = Dr * Dr + Di * Di;
-        const double stepr = (Fr * Dr + Fi * Di) / den;
-        const double stepi = (Fi * Dr - Fr * Di) / den;
-        double nr = zr[r] - stepr, ni = zi[r] - stepi;
-        const double aF = sqrt(Fr * Fr + Fi * Fi);
-        bool flag = (stepr * stepr + stepi * stepi < tol_step2) || (aF * (aF + 2.0 * a1) < tol_mu);
-        if (!isfinite(nr) || !isfinite(ni)) {
-            // the iterate hit a star or two roots met: nudge it off, keep iterating
-            nr = zr[r] + 1e-7 * (1 + (k & 7));
-            ni = zi[r] + 1e-7 * (1 + (k >> 3 & 7));
-            flag = false;
-        }
-        const bool upd = act[r];
-        const bool still = upd && !flag;
-        n_after += __popcll(__ballot(still));
-        n_upd += __popcll(__ballot(upd));
-        if (valid[r]) {
-            if (upd) {
-                nxt[base_f + k] = make_double2(nr, ni);
-                if (flag) {
-                    flagrow[base_f + k] = row;
-                    if (boundary) {
-                        bnd_row[k] = make_double2(nr, ni);
-                    } else {
-                        out_re[(int64_t)row * n_r + k] = nr;
-                        out_im[(int64_t)row * n_r + k] = ni;
-                    }
-                }
-            } else {
-                nxt[base_f + k] = make_double2(zr[r], zi[r]);
+    auto store = [&](int kk, const Update &u) {
+        nxt[base_f + kk] = make_double2(u.zr, u.zi);
+        if (!u.flag) return;
+        flagrow[base_f + kk] = row;
+        if (boundary) {
+            bnd_row[kk] = make_double2(u.zr, u.zi);
+        } else {
+            const int64_t o = (int64_t)row * n_r + kk;
+            out_re[o] = u.zr;
+            out_im[o] = u.zi;
+            if (caus_re) {
+                caus_re[o] = u.wr;
+                caus_im[o] = u.wi;
             }
         }
+    };
+
+    int n_after = 0;
+    if (n_act <= SPARSE_MAX) {
+        // Few roots left (a straggler sweep): the wave takes them one at a
+        // time, lanes splitting the star and root sums, then a butterfly
+        // reduction.  Latency per root drops ~64x against one lane doing it.
+        unsigned long long mm = amask;
+        while (mm) {
+            const int l = __ffsll((long long)mm) - 1;
+            mm &= mm - 1;
+            const double xk = __shfl(zr, l, 64), yk = __shfl(zi, l, 64);
+            Sums S;
+            zero(S);
+#pragma unroll 4
+            for (int i = lane; i < n_stars; i += 64) add_star<EQUAL>(S, xk, yk, stars[i]);
+            const int kk = k0 + l;
+#pragma unroll 4
+            for (int j = lane; j < n_r; j += 64)
+                if (j != kk) add_root(S, xk, yk, zsrc[j]);
+            wave_sum(S.s1r); wave_sum(S.s1i);
+            if (!EQUAL) { wave_sum(S.s0r); wave_sum(S.s0i); }
+            wave_sum(S.s2r); wave_sum(S.s2i);
+            wave_sum(S.s3r); wave_sum(S.s3i);
+            wave_sum(S.Rr); wave_sum(S.Ri);
+            const Update u = finish<EQUAL>(S, xk, yk, m0, e, gamma, a, a1, tol_step2, tol_mu, kk);
+            if (lane == l) store(kk, u);
+            n_after += u.flag ? 0 : 1;
+        }
+    } else {
+        Sums S;
+        zero(S);
+        stream_tiles(stars, n_stars, reinterpret_cast<T *>(tiles),
+                     [&](int, const T &s) { add_star<EQUAL>(S, zr, zi, s); });
+        double2 *rtiles = reinterpret_cast<double2 *>(tiles);
+        auto other = [&](int, const double2 &o) { add_root(S, zr, zi, o); };
+        const int own_hi = min(k0 + 64, n_r);
+        stream_tiles(zsrc, k0, rtiles, other);
+        stream_tiles(zsrc + k0, own_hi - k0, rtiles, [&](int j, const double2 &o) {
+            Sums T2 = S;
+            add_root(T2, zr, zi, o);
+            const bool self = j == lane;
+            S.Rr = self ? S.Rr : T2.Rr;
+            S.Ri = self ? S.Ri : T2.Ri;
+        });
+        stream_tiles(zsrc + own_hi, n_r - own_hi, rtiles, other);
+        const Update u = finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k);
+        if (act) store(k, u);
+        n_after = __popcll(__ballot(act && !u.flag));
     }
     if (lane == 0) {
         if (n_after) atomicAdd(&counts[f], n_after);
-        if (n_upd) atomicAdd(updates, (unsigned long long)n_upd);
+        atomicAdd(updates, (unsigned long long)n_act);
     }
 }
 
@@ -332,7 +427,7 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
 static int choose_subchains(int64_t n_r, int64_t m, int rpl)
 {
     const int64_t waves_per_front = ceil_div(n_r, 64 * rpl);
-    const int64_t target_waves = 1024 * 8;
+    const int64_t target_waves = 1024 * 10;
     int64_t want = ceil_div(target_waves, 2 * waves_per_front);
     want = std::min<int64_t>(want, std::max<int64_t>(1, m / 150));
     want = std::min<int64_t>(want, MAX_FRONTS / 2);
@@ -343,22 +438,25 @@ static int choose_subchains(int64_t n_r, int64_t m, int rpl)
     return 1;
 }
 
-template <int RPL, bool EQUAL>
+template <bool EQUAL>
 static void launch_sweep(Ctx *c, int n_fronts, int bpf, const double2 *cur, double2 *nxt,
-                         const double2 *etab, double a1, double tol_step2, double tol_mu,
-                         int32_t n_r, double *out_re, double *out_im)
+                         const double2 *etab, double a, double a1, double tol_step2,
+                         double tol_mu, int32_t n_r, double *out_re, double *out_im,
+                         double *caus_re, double *caus_im)
 {
-    hipLaunchKernelGGL((aberth_sweep_f64<RPL, EQUAL>), dim3(n_fronts * bpf), dim3(64), 0,
-                       c->stream, c->stars.as<double2>(), c->mass.as<double>(), c->mass0,
-                       (int32_t)c->n, cur, nxt, c->flagrow.as<int32_t>(), c->fronts.as<Front>(), etab, c->gamma,
-                       a1, tol_step2, tol_mu, n_r, bpf, out_re, out_im, c->bnd.as<double2>(),
-                       c->counts.as<int32_t>(),
-                       &c->control.as<Control>()->updates);
+    using T = typename StarRec<EQUAL>::T;
+    const T *stars = EQUAL ? reinterpret_cast<const T *>(c->stars.p)
+                           : reinterpret_cast<const T *>(c->stars4.p);
+    hipLaunchKernelGGL((aberth_sweep_f64<EQUAL>), dim3(n_fronts * bpf), dim3(64), 0, c->stream,
+                       stars, c->mass0, (int32_t)c->n, cur, nxt, c->flagrow.as<int32_t>(),
+                       c->fronts.as<Front>(), etab, c->gamma, a, a1, tol_step2, tol_mu, n_r, bpf,
+                       out_re, out_im, caus_re, caus_im, c->bnd.as<double2>(),
+                       c->counts.as<int32_t>(), &c->control.as<Control>()->updates);
 }
 
 mlcc_status find_critical_curves_fp64(Ctx *c, const mlcc_cc_params *p, double *roots_re,
-                                      double *roots_im, int32_t *chain_next,
-                                      mlcc_cc_stats *stats)
+                                      double *roots_im, double *caus_re, double *caus_im,
+                                      int32_t *chain_next, mlcc_cc_stats *stats)
 {
     constexpr int RPL = 1;
     const int64_t n = c->n, n_r = 2 * n, m = p->m_steps;
@@ -464,11 +562,11 @@ mlcc_status find_critical_curves_fp64(Ctx *c, const mlcc_cc_params *p, double *r
             double2 *nxt = c->iter[parity ^ 1].as<double2>();
             if (p->timing) MLCC_HIP(hipEventRecord(evs[(slot * MAX_BATCH + i) * 2], c->stream));
             if (c->equal_mass)
-                launch_sweep<RPL, true>(c, F, bpf, cur, nxt, etab, a1, tol_step2, p->tol_inv_mu,
-                                        (int32_t)n_r, roots_re, roots_im);
+                launch_sweep<true>(c, F, bpf, cur, nxt, etab, a, a1, tol_step2, p->tol_inv_mu,
+                                   (int32_t)n_r, roots_re, roots_im, caus_re, caus_im);
             else
-                launch_sweep<RPL, false>(c, F, bpf, cur, nxt, etab, a1, tol_step2, p->tol_inv_mu,
-                                         (int32_t)n_r, roots_re, roots_im);
+                launch_sweep<false>(c, F, bpf, cur, nxt, etab, a, a1, tol_step2, p->tol_inv_mu,
+                                    (int32_t)n_r, roots_re, roots_im, caus_re, caus_im);
             if (p->timing) MLCC_HIP(hipEventRecord(evs[(slot * MAX_BATCH + i) * 2 + 1], c->stream));
             hipLaunchKernelGGL(aberth_control, dim3(1), dim3(CONTROL_THREADS), 0, c->stream,
                                c->fronts.as<Front>(), c->counts.as<int32_t>(), F, dctl, max_cold,
@@ -575,9 +673,13 @@ mlcc_status find_critical_curves_fp64(Ctx *c, const mlcc_cc_params *p, double *r
                     lab[s * n_r + k] = lab[(s - 1) * n_r + hp[s * n_r + k]];
             MLCC_HIP(hipMemcpy(perm, lab.data(), (size_t)S * n_r * sizeof(int32_t),
                                hipMemcpyHostToDevice));
-            for (int s = 1; s < S; ++s)
+            for (int s = 1; s < S; ++s) {
                 MLCC_TRY(relabel_rows(c, roots_re, roots_im, n_r, s * L + 1, (s + 1) * L + 1,
                                       perm + (int64_t)s * n_r));
+                if (caus_re)
+                    MLCC_TRY(relabel_rows(c, caus_re, caus_im, n_r, s * L + 1, (s + 1) * L + 1,
+                                          perm + (int64_t)s * n_r));
+            }
         }
         if (chain_next) {
             double md = 0.0;

@@ -141,7 +141,7 @@ void mlcc_destroy(mlcc_ctx *ctx)
     Ctx &c = ctx->impl;
     (void)hipSetDevice(c.device);
     (void)hipStreamSynchronize(c.stream);
-    DevBuf *bufs[] = {&c.stars, &c.mass, &c.iter[0], &c.iter[1], &c.flagrow, &c.fronts,
+    DevBuf *bufs[] = {&c.stars, &c.mass, &c.stars4, &c.iter[0], &c.iter[1], &c.flagrow, &c.fronts,
                       &c.counts, &c.control, &c.etab, &c.bnd, &c.perm, &c.match_aux,
                       &c.relabel, &c.workflags, &c.diff, &c.err, &c.edt_col};
     for (DevBuf *b : bufs) b->release();
@@ -215,6 +215,16 @@ mlcc_status mlcc_set_lenses(mlcc_ctx *ctx, int64_t n, const double *x, const dou
         xy[2 * i] = hx[i];
         xy[2 * i + 1] = hy[i];
     }
+    std::vector<double> xym(4 * n);
+    for (int64_t i = 0; i < n; ++i) {
+        xym[4 * i] = hx[i];
+        xym[4 * i + 1] = hy[i];
+        xym[4 * i + 2] = hm[i];
+        xym[4 * i + 3] = 0.0;
+    }
+    MLCC_TRY(c.stars4.reserve(4 * n * sizeof(double)));
+    MLCC_HIP(hipMemcpyAsync(c.stars4.p, xym.data(), 4 * n * sizeof(double), hipMemcpyHostToDevice,
+                            c.stream));
     MLCC_TRY(c.stars.reserve(2 * n * sizeof(double)));
     MLCC_TRY(c.mass.reserve(n * sizeof(double)));
     MLCC_HIP(hipMemcpyAsync(c.stars.p, xy.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice,
@@ -232,7 +242,8 @@ mlcc_status mlcc_set_lenses(mlcc_ctx *ctx, int64_t n, const double *x, const dou
 }
 
 mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *params,
-                                      double *roots_re, double *roots_im, int32_t *chain_next,
+                                      double *roots_re, double *roots_im, double *caustics_re,
+                                      double *caustics_im, int32_t *chain_next,
                                       mlcc_cc_stats *stats)
 {
     if (!ctx || !params) return fail(MLCC_ERR_INVALID, "ctx or params is NULL");
@@ -257,9 +268,16 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
         return fail(MLCC_ERR_INVALID, "unknown precision %d", p.precision);
     MLCC_TRY(check_device_ptr(&c, roots_re, "roots_re"));
     MLCC_TRY(check_device_ptr(&c, roots_im, "roots_im"));
+    if ((caustics_re == nullptr) != (caustics_im == nullptr))
+        return fail(MLCC_ERR_INVALID, "caustics_re and caustics_im must both be given or both NULL");
+    if (caustics_re) {
+        MLCC_TRY(check_device_ptr(&c, caustics_re, "caustics_re"));
+        MLCC_TRY(check_device_ptr(&c, caustics_im, "caustics_im"));
+    }
     if (chain_next) MLCC_TRY(check_device_ptr(&c, chain_next, "chain_next"));
     clear_error();
-    return find_critical_curves_fp64(&c, &p, roots_re, roots_im, chain_next, stats);
+    return find_critical_curves_fp64(&c, &p, roots_re, roots_im, caustics_re, caustics_im,
+                                     chain_next, stats);
 }
 
 mlcc_status mlcc_map_caustics(mlcc_ctx *ctx, int64_t count, const double *z_re,

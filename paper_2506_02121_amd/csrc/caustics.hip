@@ -4,6 +4,8 @@
 //   w = (1 - kappa_s) z + gamma conj(z) - sum_i m_i / conj(z - z_i),
 // and m_i / conj(d) = m_i d / |d|^2.  One lane per point; stars arrive as
 // wave-uniform scalar loads.
+#include <type_traits>
+
 #include "mlcc_internal.h"
 
 namespace mlcc {
@@ -17,27 +19,52 @@ __device__ __forceinline__ double rcp_full(double x)
     return fma(y, e, y);
 }
 
+// Same streaming scheme as the root finder: tiles of 64 star records fetched
+// with coalesced vector loads one tile ahead, parked in LDS, read back with
+// broadcast LDS reads (one-wave work groups).
+template <class T, class Body>
+__device__ __forceinline__ void stream_star_tiles(const T *__restrict__ p, int n, T *lds,
+                                                  Body &&body)
+{
+    const int lane = threadIdx.x;
+    const int ntiles = (n + 63) >> 6;
+    T reg = p[min(lane, n - 1)];
+    for (int t = 0; t < ntiles; ++t) {
+        T *buf = lds + ((t & 1) << 6);
+        buf[lane] = reg;
+        __syncthreads();
+        if (t + 1 < ntiles) reg = p[min(((t + 1) << 6) + lane, n - 1)];
+        const int cnt = min(64, n - (t << 6));
+        if (cnt == 64) {
+#pragma unroll 8
+            for (int k = 0; k < 64; ++k) body(buf[k]);
+        } else {
+            for (int k = 0; k < cnt; ++k) body(buf[k]);
+        }
+    }
+}
+
 template <bool EQUAL>
 __global__ void __launch_bounds__(64)
-map_caustics_f64(const double2 *__restrict__ stars, const double *__restrict__ mass,
+map_caustics_f64(const typename std::conditional<EQUAL, double2, double4>::type *__restrict__ stars,
                  double m0, int32_t n_stars, int64_t count, const double *__restrict__ zr,
                  const double *__restrict__ zi, double *__restrict__ wr,
                  double *__restrict__ wi, double a, double gamma)
 {
+    using T = typename std::conditional<EQUAL, double2, double4>::type;
+    __shared__ T tiles[128];
     const int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const bool valid = k < count;
     const double x = valid ? zr[k] : 0.0;
     const double y = valid ? zi[k] : 0.0;
     double sr = 0.0, si = 0.0;
-#pragma unroll 4
-    for (int i = 0; i < n_stars; ++i) {
-        const double2 s = stars[i];
+    stream_star_tiles(stars, n_stars, tiles, [&](const T &s) {
         const double dx = x - s.x, dy = y - s.y;
         double q = rcp_full(fma(dx, dx, dy * dy));
-        if (!EQUAL) q *= mass[i];
+        if constexpr (!EQUAL) q *= s.z;
         sr = fma(q, dx, sr);
         si = fma(q, dy, si);
-    }
+    });
     if (EQUAL) {   // every mass equals m0
         sr *= m0;
         si *= m0;
@@ -56,12 +83,12 @@ mlcc_status launch_map_caustics(Ctx *c, int64_t count, const double *zr, const d
     const double a = 1.0 - c->kappa_s;
     if (c->equal_mass)
         hipLaunchKernelGGL(map_caustics_f64<true>, dim3((unsigned)blocks), dim3(64), 0, c->stream,
-                           c->stars.as<double2>(), c->mass.as<double>(), c->mass0, (int32_t)c->n, count,
-                           zr, zi, wr, wi, a, c->gamma);
+                           c->stars.as<double2>(), c->mass0, (int32_t)c->n, count, zr, zi, wr, wi,
+                           a, c->gamma);
     else
         hipLaunchKernelGGL(map_caustics_f64<false>, dim3((unsigned)blocks), dim3(64), 0,
-                           c->stream, c->stars.as<double2>(), c->mass.as<double>(),
-                           c->mass0, (int32_t)c->n, count, zr, zi, wr, wi, a, c->gamma);
+                           c->stream, c->stars4.as<double4>(), c->mass0, (int32_t)c->n, count,
+                           zr, zi, wr, wi, a, c->gamma);
     MLCC_HIP(hipGetLastError());
     return MLCC_OK;
 }

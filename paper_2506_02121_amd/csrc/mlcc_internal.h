@@ -81,6 +81,7 @@ struct Ctx {
     double mass0 = 1.0; // the common mass when equal_mass
     DevBuf stars;  // double2[n]: (x, y)
     DevBuf mass;   // double[n]
+    DevBuf stars4; // double4[n]: (x, y, m, 0)
 
     // root-finder workspace
     DevBuf iter[2];   // double2[F * n_r]: Jacobi iterates, ping-pong
@@ -110,8 +111,8 @@ mlcc_status ensure_pinned(Ctx *c, size_t bytes);
 // Entry points implemented per translation unit (argument checks done by the
 // caller in api.hip).
 mlcc_status find_critical_curves_fp64(Ctx *c, const mlcc_cc_params *p, double *roots_re,
-                                      double *roots_im, int32_t *chain_next,
-                                      mlcc_cc_stats *stats);
+                                      double *roots_im, double *caus_re, double *caus_im,
+                                      int32_t *chain_next, mlcc_cc_stats *stats);
 mlcc_status launch_map_caustics(Ctx *c, int64_t count, const double *zr, const double *zi,
                                 double *wr, double *wi);
 mlcc_status run_caustic_crossings(Ctx *c, int64_t rows, int64_t n_r, const double *wr,

@@ -73,7 +73,7 @@ _SIG = {
     "mlcc_last_error": ([], ctypes.c_char_p),
     "mlcc_set_lenses": ([_vp, _i64, _vp, _vp, _vp, _d, _d], ctypes.c_int),
     "mlcc_cc_params_default": ([ctypes.POINTER(CCParams), _i64], None),
-    "mlcc_find_critical_curves": ([_vp, ctypes.POINTER(CCParams), _vp, _vp, _vp,
+    "mlcc_find_critical_curves": ([_vp, ctypes.POINTER(CCParams), _vp, _vp, _vp, _vp, _vp,
                                    ctypes.POINTER(CCStats)], ctypes.c_int),
     "mlcc_map_caustics": ([_vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
     "mlcc_caustic_crossings": ([_vp, _i64, _i64, _vp, _vp, _vp, ctypes.POINTER(GridC), _vp],
@@ -168,9 +168,11 @@ class Context:
     def find_critical_curves(self, m_steps: int, n_subchains: int = 0, tol_step: float = 1e-9,
                              tol_inv_mu: float = 1e-9, max_iter_cold: int = 500,
                              max_iter_warm: int = 100, timing: bool = False,
-                             chain_next: bool = True, out=None, raise_on_error: bool = True):
-        """Returns (roots_re, roots_im, chain_next, stats, status); roots are
-        (m_steps + 1, 2N) float64 device tensors."""
+                             chain_next: bool = True, caustics: bool = False, out=None,
+                             caustics_out=None, raise_on_error: bool = True):
+        """Returns (roots_re, roots_im, chain_next, stats, status), or with
+        caustics=True (roots_re, roots_im, caus_re, caus_im, chain_next, stats,
+        status); arrays are (m_steps + 1, 2N) float64 device tensors."""
         p = self.default_params(m_steps)
         p.n_subchains = int(n_subchains)
         p.tol_step = float(tol_step)
@@ -184,13 +186,21 @@ class Context:
             ri = torch.empty_like(rr)
         else:
             rr, ri = out
+        cr = ci = None
+        if caustics:
+            if caustics_out is None:
+                cr, ci = torch.empty_like(rr), torch.empty_like(ri)
+            else:
+                cr, ci = caustics_out
         cn = torch.empty(n_r, dtype=torch.int32, device=self.device) if chain_next else None
         st = CCStats()
         self._stream()
         code = _lib.mlcc_find_critical_curves(self._h, ctypes.byref(p), _ptr(rr), _ptr(ri),
-                                              _ptr(cn), ctypes.byref(st))
+                                              _ptr(cr), _ptr(ci), _ptr(cn), ctypes.byref(st))
         if raise_on_error:
             _check(code)
+        if caustics:
+            return rr, ri, cr, ci, cn, st.as_dict(), code
         return rr, ri, cn, st.as_dict(), code
 
     def map_caustics(self, z_re: torch.Tensor, z_im: torch.Tensor, out=None):

@@ -46,8 +46,9 @@ def host_c(re, im):
 
 def gpu_roots(ctx, f, m_steps, **kw):
     set_field(ctx, f)
-    rr, ri, cn, st, code = ctx.find_critical_curves(m_steps, **kw)
+    rr, ri, cr, ci, cn, st, code = ctx.find_critical_curves(m_steps, caustics=True, **kw)
     torch.cuda.synchronize()
+    gpu_roots.caustics = host_c(cr, ci)
     return host_c(rr, ri), cn.cpu().numpy(), st, (rr, ri, cn)
 
 
@@ -159,15 +160,20 @@ def test_critical_curves_match_oracle(ctx, case):
     print(f"[{name}] column-wise distance to the oracle with S={st['n_subchains']}: {colwise:.3e}")
     assert colwise < 1e-8
     assert np.array_equal(cn, cn_s)
-    # caustics
+    # caustics: fused into the root finder, and by the standalone mapping
+    W_fused = gpu_roots.caustics
     wr, wi = ctx.map_caustics(rr.flatten(), ri.flatten())
     W = host_c(wr, wi).reshape(R.shape)
     W_ref = oracle.lens_map(f, R_ref)
-    for j in range(0, R.shape[0], max(1, R.shape[0] // 50)):
+    worst = 0.0
+    for j in range(R.shape[0]):
         idx, d = parity.pair(R_ref[j], R[j])
         Fp = oracle.eval_F(f, oracle.phase(j, m_steps), R_ref[j])[1]
         bw = 2 * abs(1 - f.kappa_s) * parity.root_bound(f, Fp) + 1e-11 * (1 + np.abs(W_ref[j]))
         assert np.all(np.abs(W[j][idx] - W_ref[j]) <= bw)
+        assert np.all(np.abs(W_fused[j][idx] - W_ref[j]) <= bw)
+        worst = max(worst, float(np.abs(W_fused[j][idx] - W_ref[j]).max()))
+    print(f"[{name}] max caustic distance (fused) {worst:.3e}", flush=True)
 
 
 def test_determinism_bitwise(ctx):
