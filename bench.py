@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-sweeps", type=int, default=2,
                     help="oracle Jacobi sweeps timed for the CPU baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (to scale "
+                         "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
@@ -68,6 +71,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8}), flush=True)
+        return
 
     from paper_2506_02121_amd import fields, mlcc
 
@@ -155,7 +168,8 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": (achieved / FP64_VECTOR_PEAK_TFLOPS) if achieved else None,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": sweep_ms / launches if launches else None,
             "launches": launches,
             "flop_per_root_update": 29 * n + 10 * (n_r - 1),
@@ -173,6 +187,29 @@ def main():
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(f, m_steps, updates_per_root_row, args.cpu_sweeps)
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(workload):
+    """HBM bytes per sweep launch from the committed counter summary, or None
+    when the workload differs or the kernel source changed since the counters
+    were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "aberth_sweep_f64_n10k_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", " ")):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    try:
+        src = os.path.join(ROOT, vals["kernel_source"])
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if vals.get("workload") != workload or h != vals["source_sha256"]:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
 
 
 def cpu_baseline(f, m_steps, updates_per_root_row, sweeps):

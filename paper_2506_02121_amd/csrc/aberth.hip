@@ -41,12 +41,14 @@ __device__ __forceinline__ double rcp_refined(double x)
     return y;
 }
 
-// Star-sum steps per root: 2 refinement steps give a fully accurate
-// reciprocal, as F itself must be exact to the last bits.  The root-root sum
-// only enters the step through F * R, which vanishes at convergence, so one
-// step (relative error ~1e-14) suffices there.
+// The hardware estimate v_rcp_f64 has relative error ~2^-24.4.  Star terms
+// take 2 refinement steps (fully accurate): F itself must be exact to the
+// last bits.  The root-root sum R only enters the step as F * (2 S1 - R);
+// that factor vanishes at a zero of F, so an error in R cannot move a
+// converged root, it only perturbs the path at second order in the error
+// of the iterate.  R therefore uses the unrefined estimate.
 constexpr int RCP_STAR = 2;
-constexpr int RCP_ROOT = 1;
+constexpr int RCP_ROOT = 0;
 
 // Streams the records p[0..n) through body(i, p[i]) for a one-wave work
 // group.  Tiles of 64 records (one per lane) are fetched with coalesced
