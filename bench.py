@@ -26,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FLOP/clk
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # packed-FP32 peak; unpacked FP32 issues at the FP64 rate
 METRIC = "critical-curve roots/s at N=1e4 stars, % FP64 VALU peak; mixed vs FP64"
 
 WORKLOAD_TEXT = {
@@ -34,8 +35,14 @@ WORKLOAD_TEXT = {
             "FP64 distance map over 40x40 theta_E",
     "n1k": "N=1,000 Salpeter stars on [0.08,1], kappa_star=0.4, kappa_s=0.2, gamma=0.45; "
            "10,000 phase steps (2,000 roots each); caustics; N_cc 1024^2 over 20x20 theta_E",
+    "n10k_mixed": "the n10k field and grids in mixed precision: one FP32 Aberth sweep per warm "
+                  "row, FP64 Newton polish with an a-posteriori acceptance test and a Vieta row "
+                  "check, FP64 sweeps for anything not accepted, FP64 lens mapping",
     "tiny": "N=10 equal-mass stars, kappa_star=0.3, kappa_s=0, gamma=0.3; 1,000 phase steps; "
             "caustics; N_cc 256^2 over 16x16 theta_E",
+    "batched": "256 independent fields, N log-uniform in [50, 5000], kappa_star U[0.1, 0.8], "
+               "gamma U[0, 0.6], kappa_s=0, Salpeter masses on [0.08,1]; 4,000 phase steps "
+               "each; one root-finder call over all fields in mixed precision; caustics",
 }
 
 
@@ -47,6 +54,8 @@ def parse():
     ap.add_argument("--workload", default="n10k", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--subchains", type=int, default=0, help="0 = library choice")
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="default: the workload's own (mixed for n10k_mixed)")
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-sweeps", type=int, default=2,
@@ -85,6 +94,9 @@ def main():
     from paper_2506_02121_amd import fields, mlcc
 
     wl = fields.workload(args.workload, args.seed)
+    precision = args.precision or wl.precision
+    if wl.fields:
+        return bench_batched(args, wl, precision)
     f = wl.field
     if wl.grid is None:
         wl.grid = fields.Grid(0.0, 0.0, 8.0, 8.0, 256, 256)
@@ -112,7 +124,7 @@ def main():
         # roots and, in the same pass, their caustic images
         _, _, _, _, cn, st, _ = ctx.find_critical_curves(
             m_steps, n_subchains=args.subchains, timing=True, caustics=True,
-            out=(roots_re, roots_im), caustics_out=(w_re, w_im))
+            out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=precision)
         ctx.caustic_crossings(w_re, w_im, cn, grid, out=ncc)
         ctx.caustic_distances(grid, ncc, out=(dist, bl))
         return st
@@ -137,12 +149,11 @@ def main():
     roots_per_step = m_steps * n_r
     value = roots_per_step / (elapsed / args.steps)
 
-    flop = sum(s["algorithmic_flop"] for s in stats)
-    sweep_ms = sum(s["sweep_ms"] for s in stats)
-    launches = sum(s["sweeps"] for s in stats)
-    achieved = flop / (sweep_ms * 1e-3) / 1e12 if sweep_ms > 0 else None
+    kernels = root_kernels(stats, precision)
+    dominant = max(kernels, key=lambda k: k["time_s"])
     s0 = stats[-1]
-    updates_per_root_row = s0["root_updates"] / float(n_r * (rows + s0["n_subchains"]))
+    updates_per_root_row = (s0["root_updates"] + s0["root_updates_f32"] + s0["polish_updates"]) \
+        / float(n_r * (rows + s0["n_subchains"]))
     ncc_h = ncc.cpu().numpy()
 
     out = {
@@ -156,25 +167,29 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "n_stars": n, "roots_per_row": n_r, "phase_steps": m_steps,
-                   "grid": [grid.nx, grid.ny], "precision": "fp64", "seed": args.seed},
+                   "grid": [grid.nx, grid.ny], "precision": precision, "seed": args.seed},
         "roofline": {
             "bound": "alu",
-            "kernel": "aberth_sweep_f64",
-            "achieved": achieved,
-            "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "kernel": dominant["kernel"],
+            "achieved": dominant["achieved"],
+            "peak": dominant["peak"],
             "unit": "TFLOP/s",
-            "frac": (achieved / FP64_VECTOR_PEAK_TFLOPS) if achieved else None,
-            "traffic": measured_traffic(args.workload),
+            "frac": dominant["frac"],
+            "traffic": measured_traffic(args.workload) if dominant["kernel"] == "aberth_sweep_f64" else None,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "avg_launch_ms": sweep_ms / launches if launches else None,
-            "launches": launches,
+            "avg_launch_ms": dominant["avg_launch_ms"],
+            "launches": dominant["launches"],
             "flop_per_root_update": 29 * n + 10 * (n_r - 1),
+            "kernels": kernels,
         },
         "stats": {"sweeps_per_step": s0["sweeps"], "root_updates_per_step": s0["root_updates"],
+                  "root_updates_f32_per_step": s0["root_updates_f32"],
+                  "polish_updates_per_step": s0["polish_updates"],
+                  "rows_fallback": s0["rows_fallback"],
                   "updates_per_root_per_row": updates_per_root_row,
                   "n_subchains": s0["n_subchains"], "cold_sweeps": s0["cold_sweeps"],
                   "max_row_sweeps": s0["max_row_sweeps"], "match_maxdist": s0["match_maxdist"],
@@ -186,6 +201,104 @@ def main():
 
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(f, m_steps, updates_per_root_row, args.cpu_sweeps)
+    print(json.dumps(out), flush=True)
+
+
+def kernel_line(stats, name, flop_key, ms_key, n_key, peak, dtype):
+    """Roofline of one root-finder kernel: algorithmic FLOP of the launches
+    that did work over their HIP-event time."""
+    flop = sum(s[flop_key] for s in stats)
+    ms = sum(s[ms_key] for s in stats)
+    launches = sum(s[n_key] for s in stats)
+    achieved = flop / (ms * 1e-3) / 1e12 if ms > 0 else None
+    return {"kernel": name, "dtype": dtype, "achieved": achieved, "peak": peak,
+            "frac": achieved / peak if achieved else None, "time_s": ms * 1e-3,
+            "avg_launch_ms": ms / launches if launches else None, "launches": launches}
+
+
+def root_kernels(stats, precision):
+    ks = [kernel_line(stats, "aberth_sweep_f64", "algorithmic_flop", "sweep_ms",
+                      "sweep_launches", FP64_VECTOR_PEAK_TFLOPS, "f64")]
+    if precision == "mixed":
+        ks.append(kernel_line(stats, "aberth_sweep_f32", "algorithmic_flop_f32", "sweep_f32_ms",
+                              "sweep_f32_launches", FP32_VECTOR_PEAK_TFLOPS, "f32"))
+        ks.append(kernel_line(stats, "newton_polish_f64", "algorithmic_flop_polish", "polish_ms",
+                              "polish_launches", FP64_VECTOR_PEAK_TFLOPS, "f64"))
+    return ks
+
+
+def bench_batched(args, wl, precision):
+    """Many independent fields in one root-finder call: roots and caustics of
+    every field; value = phase steps x total roots per row / seconds."""
+    import numpy as np
+    import torch
+
+    from paper_2506_02121_amd import mlcc
+
+    fs = wl.fields
+    m_steps = wl.m_steps
+    dev = torch.device("cuda", 0)
+    off = np.concatenate([[0], np.cumsum([f.n for f in fs])]).astype(np.int64)
+    n_tot = int(off[-1])
+    x = torch.as_tensor(np.concatenate([f.x for f in fs]), device=dev)
+    y = torch.as_tensor(np.concatenate([f.y for f in fs]), device=dev)
+    mm = torch.as_tensor(np.concatenate([f.m for f in fs]), device=dev)
+    ks = [f.kappa_s for f in fs]
+    gs = [f.gamma for f in fs]
+    total = (m_steps + 1) * 2 * n_tot
+    log(f"{len(fs)} fields, {n_tot} stars, {2 * n_tot} roots per row, "
+        f"{4 * total * 8 / 2**30:.1f} GiB of roots and caustics")
+    roots_re = torch.empty(total, dtype=torch.float64, device=dev)
+    roots_im = torch.empty_like(roots_re)
+    w_re = torch.empty_like(roots_re)
+    w_im = torch.empty_like(roots_re)
+    ctx = mlcc.Context(0)
+    torch.cuda.synchronize()
+
+    def step():
+        ctx.set_lenses_batched(off, x, y, mm, ks, gs)
+        _, _, _, _, cn, st, _ = ctx.find_critical_curves(
+            m_steps, n_subchains=args.subchains, timing=True, caustics=True,
+            out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=precision)
+        return st
+
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {time.perf_counter() - t:.3f} s")
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        stats.append(step())
+        torch.cuda.synchronize()
+        log(f"step {i}: {time.perf_counter() - ts:.3f} s, {stats[-1]['sweeps']} rounds")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    roots_per_step = m_steps * 2 * n_tot
+    kernels = root_kernels(stats, precision)
+    dominant = max(kernels, key=lambda k: k["time_s"])
+    s0 = stats[-1]
+    out = {
+        "metric": METRIC, "value": roots_per_step / (elapsed / args.steps), "unit": "roots/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {WORKLOAD_TEXT['batched']}", "fields": len(fs),
+                   "total_stars": n_tot, "roots_per_row": 2 * n_tot, "phase_steps": m_steps,
+                   "precision": precision, "seed": args.seed},
+        "roofline": {"bound": "alu", "kernel": dominant["kernel"],
+                     "achieved": dominant["achieved"], "peak": dominant["peak"],
+                     "unit": "TFLOP/s", "frac": dominant["frac"], "traffic": None,
+                     "avg_launch_ms": dominant["avg_launch_ms"],
+                     "launches": dominant["launches"], "kernels": kernels},
+        "stats": {k: s0[k] for k in ("sweeps", "root_updates", "root_updates_f32",
+                                     "polish_updates", "rows_fallback", "n_subchains",
+                                     "cold_sweeps", "max_row_sweeps", "match_maxdist")},
+    }
     print(json.dumps(out), flush=True)
 
 

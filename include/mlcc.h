@@ -44,7 +44,10 @@ typedef enum {
 } mlcc_status;
 
 typedef enum {
-    MLCC_FP64 = 0 /* every step in IEEE double precision */
+    MLCC_FP64 = 0, /* every step in IEEE double precision */
+    MLCC_MIXED = 1 /* warm rows: one FP32 Aberth sweep, then FP64 Newton polish with an
+                      a-posteriori acceptance test and a Vieta check of the row, FP64
+                      Aberth sweeps for anything not accepted; cold starts FP64 */
 } mlcc_precision;
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream` (a
@@ -76,6 +79,24 @@ const char *mlcc_last_error(void);
 mlcc_status mlcc_set_lenses(mlcc_ctx *ctx, int64_t n, const double *x, const double *y,
                             const double *m, double kappa_s, double gamma);
 
+/*
+ * set_lenses_batched -- several independent star fields, each with its own
+ * stars, kappa_s and gamma (the model of mlcc_set_lenses per field), solved
+ * together by one mlcc_find_critical_curves call.  Field r holds stars
+ * star_offsets[r] .. star_offsets[r+1]-1 of the concatenated arrays.
+ *   n_fields          1 .. 65536
+ *   star_offsets      host int64[n_fields + 1]: 0 = star_offsets[0] <
+ *                     star_offsets[1] < ... ; total stars <= 2^28
+ *   x, y, m           device float64[star_offsets[n_fields]]
+ *   kappa_s, gamma    host float64[n_fields]
+ * Rejected as for mlcc_set_lenses, field by field (duplicate positions are
+ * checked within a field).  Copies the inputs; synchronous.  After it,
+ * mlcc_map_caustics refuses (it maps through one field).
+ */
+mlcc_status mlcc_set_lenses_batched(mlcc_ctx *ctx, int32_t n_fields, const int64_t *star_offsets,
+                                    const double *x, const double *y, const double *m,
+                                    const double *kappa_s, const double *gamma);
+
 typedef struct {
     int64_t m_steps;       /* phase steps m, even, >= 2: row j <-> phi_j = 2 pi j / m,
                               rows 0..m (Sec. 3.1, Sec. 4.3) */
@@ -96,19 +117,26 @@ typedef struct {
 void mlcc_cc_params_default(mlcc_cc_params *p, int64_t m_steps);
 
 typedef struct {
-    int64_t sweeps;          /* sweep launches that did work */
-    int64_t root_updates;    /* root updates performed (sum over sweeps of active roots) */
+    int64_t sweeps;          /* rounds that did work (one round = every pass kind once) */
+    int64_t root_updates;    /* FP64 Aberth root updates */
+    int64_t root_updates_f32;/* FP32 Aberth root updates (MLCC_MIXED) */
+    int64_t polish_updates;  /* FP64 Newton polish updates (MLCC_MIXED) */
     int64_t unconverged;     /* roots still unflagged in rows that hit a cap */
     int64_t rows_capped;     /* rows that hit an iteration cap */
+    int64_t rows_fallback;   /* rows that fell back to FP64 Aberth sweeps (MLCC_MIXED) */
     int32_t n_subchains;     /* S actually used */
-    int32_t max_row_sweeps;  /* most sweeps any warm row needed */
+    int32_t max_row_sweeps;  /* most FP64 sweeps any warm row needed */
     int32_t cold_sweeps;     /* most sweeps any cold start needed */
     int32_t polls;           /* host polls of the device-side front table */
     double match_maxdist;    /* largest distance between paired duplicate roots */
-    double sweep_ms;         /* summed GPU time of sweep launches that did work
-                                (timing != 0 only) */
-    double algorithmic_flop; /* root_updates * (29 N + 10 (2N - 1)): FMA = 2,
+    double sweep_ms;         /* GPU time of FP64 sweep launches that did work (timing != 0) */
+    double sweep_f32_ms;     /* same, FP32 sweep launches */
+    double polish_ms;        /* same, polish launches */
+    int64_t sweep_launches, sweep_f32_launches, polish_launches;   /* launches that did work */
+    double algorithmic_flop; /* FP64 sweeps: root_updates * (29 N + 10 (2N - 1)); FMA = 2,
                                 add/mul/reciprocal = 1 */
+    double algorithmic_flop_f32;    /* FP32 sweeps: root_updates_f32 * (29 N + 10 (2N - 1)) */
+    double algorithmic_flop_polish; /* polish: polish_updates * 36 N */
 } mlcc_cc_stats;
 
 /*
@@ -135,6 +163,13 @@ typedef struct {
  *                       whose row 0 continues column k's row m (phi = 2 pi and
  *                       phi = 0 give the same roots; Sec. 4.3 footnote).
  *   stats               host, or NULL.
+ * With several fields (mlcc_set_lenses_batched), field r with N_r stars and
+ * star offset o_r owns the block of (m+1) * 2N_r elements starting at
+ * (m+1) * 2 o_r of roots_* and caustics_* (row-major within the block, as
+ * above) and the 2N_r entries starting at 2 o_r of chain_next (column
+ * indices within the field); the arrays hold (m+1) * 2 * (total stars) and
+ * 2 * (total stars) elements.  All fields share one phase grid and one set
+ * of parameters; n_subchains = 0 picks one S for all of them.
  * Synchronous.  MLCC_ERR_NOT_CONVERGED if any row hit its cap;
  * MLCC_ERR_MATCH if duplicate rows did not pair one-to-one within 1e-6.
  */

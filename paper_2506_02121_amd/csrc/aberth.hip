@@ -1,26 +1,29 @@
 // Critical-curve root finder: parallel Aberth-Ehrlich sweeps (Sec. 3.2)
 // over the phase grid, warm-started along phi and grown centre-out in
-// subchains (Sec. 4.3).
+// subchains (Sec. 4.3), in plain FP64 or in a mixed-precision form.
 //
 // Layout and scheduling (gfx950):
 //  * One lane per root, one 64-lane wavefront per work-group.  Each
 //    work-group owns 64 consecutive roots of one "front" (a growing end of a
 //    subchain).  Star positions and the other roots stream through LDS in
 //    tiles and are read back as wave-uniform broadcasts.
-//  * A block with only a few unflagged roots left (the last sweep of a row)
-//    works on them one at a time with the whole wave, so such sweeps cost
-//    ~1/64 of a full one instead of the same latency.
-//  * Roots flagged converged are mapped to the caustic in the same kernel.
-//  * Jacobi double buffering: a sweep reads iterate `cur` and writes `nxt`;
-//    the host alternates the two on every launch.  A root flagged converged
-//    is copied forward unchanged.
-//  * A single-work-group control kernel after every sweep advances the
-//    fronts whose rows have converged (device-side, so the host only polls
-//    a small status block every few launches, one batch ahead).
+//  * A block with only a few unconverged roots left (the last sweep of a row)
+//    works on them one at a time with the whole wave.
+//  * Jacobi double buffering: every kernel of a launch round reads iterate
+//    `cur` and writes `nxt`; the host alternates the two.
+//  * Each front carries a phase.  FP64 mode: every row is FP64 Aberth sweeps.
+//    Mixed mode, warm rows: one FP32 Aberth sweep, then FP64 Newton polish
+//    passes with an a-posteriori acceptance test and a Vieta check of the
+//    row, then FP64 Aberth sweeps for whatever was not accepted.  Cold starts
+//    are FP64 in both modes.
+//  * A single-work-group control kernel after every round advances the
+//    fronts (device-side; the host polls a status block one batch ahead).
+//  * Converged roots are mapped to the caustic in the same kernel.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 #include <vector>
 
 #include "mlcc_internal.h"
@@ -50,23 +53,25 @@ __device__ __forceinline__ double rcp_refined(double x)
 constexpr int RCP_STAR = 2;
 constexpr int RCP_ROOT = 0;
 
-// Streams the records p[0..n) through body(i, p[i]) for a one-wave work
+// Streams the records p[0..n) through body(i, rec) for a one-wave work
 // group.  Tiles of 64 records (one per lane) are fetched with coalesced
-// vector loads, the next tile while the current one is consumed, parked in
-// LDS, and read back with one wave-uniform (broadcast) LDS read per record.
-// Vector loads retire in order, so waiting for the older tile never waits
-// for the prefetch behind it.  Indices past n-1 are clamped on load, so
-// nothing outside the array is read.  `lds` holds two tiles.
-template <class T, class Body>
-__device__ __forceinline__ void stream_tiles(const T *__restrict__ p, int n, T *lds, Body &&body)
+// vector loads, the next tile while the current one is consumed, converted
+// by cvt and parked in LDS, and read back with one wave-uniform (broadcast)
+// LDS read per record; tile_end() runs after each tile.  Vector loads retire
+// in order, so waiting for the older tile never waits for the prefetch
+// behind it.  Indices past n-1 are clamped on load, so nothing outside the
+// array is read.  `lds` holds two tiles.
+template <class T, class L, class Cvt, class Body, class End>
+__device__ __forceinline__ void stream_tiles_ex(const T *__restrict__ p, int n, L *lds, Cvt &&cvt,
+                                                Body &&body, End &&tile_end)
 {
     if (n <= 0) return;
     const int lane = threadIdx.x;
     const int ntiles = (n + 63) >> 6;
     T reg = p[min(lane, n - 1)];
     for (int t = 0; t < ntiles; ++t) {
-        T *buf = lds + ((t & 1) << 6);
-        buf[lane] = reg;
+        L *buf = lds + ((t & 1) << 6);
+        buf[lane] = cvt(reg);
         __syncthreads();
         if (t + 1 < ntiles) reg = p[min(((t + 1) << 6) + lane, n - 1)];
         const int base = t << 6;
@@ -77,8 +82,22 @@ __device__ __forceinline__ void stream_tiles(const T *__restrict__ p, int n, T *
         } else {
             for (int k = 0; k < cnt; ++k) body(base + k, buf[k]);
         }
+        tile_end();
     }
     __syncthreads();
+}
+
+struct Same {
+    template <class T> __device__ __forceinline__ T operator()(const T &v) const { return v; }
+};
+struct NoEnd {
+    __device__ __forceinline__ void operator()() const {}
+};
+
+template <class T, class Body>
+__device__ __forceinline__ void stream_tiles(const T *__restrict__ p, int n, T *lds, Body &&body)
+{
+    stream_tiles_ex(p, n, lds, Same{}, body, NoEnd{});
 }
 
 // Star records: (x, y) when all masses are equal (the common mass is applied
@@ -92,6 +111,16 @@ template <> struct StarRec<false> {
     using T = double4;
     static __device__ __forceinline__ double mass(const double4 &s) { return s.z; }
 };
+
+__device__ __forceinline__ void wave_sum(double &v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Aberth sweep
+// ---------------------------------------------------------------------------
 
 // Running sums for one root z, u_i = 1/(z - z_i):
 //   s1 = sum u_i                (for P'/P = F'/F + 2 s1)
@@ -150,17 +179,19 @@ __device__ __forceinline__ void add_root(Sums &S, double zr, double zi, const do
     S.Ri = fma(-dy, inv, S.Ri);
 }
 
-__device__ __forceinline__ void wave_sum(double &v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-}
-
 struct Update {
     double zr, zi;   // new iterate
     double wr, wi;   // its image under the lens map
     bool flag;       // converged
 };
+
+// Degenerate iterate (on a star, or two iterates equal): nudge it off.
+__device__ __forceinline__ void nudge(Update &u, double zr, double zi, int k)
+{
+    u.zr = zr + 1e-7 * (1 + (k & 7));
+    u.zi = zi + 1e-7 * (1 + (k >> 3 & 7));
+    u.flag = false;
+}
 
 // One Aberth-Ehrlich update from the sums at z (Sec. 3.2), the convergence
 // test of the Sec. 3.2 footnote with the App. C bound on |1/mu|, and the
@@ -195,12 +226,7 @@ __device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0
     u.zi = zi - stepi;
     const double aF = sqrt(Fr * Fr + Fi * Fi);
     u.flag = (stepr * stepr + stepi * stepi < tol_step2) || (aF * (aF + 2.0 * a1) < tol_mu);
-    if (!isfinite(u.zr) || !isfinite(u.zi)) {
-        // the iterate hit a star or two roots met: nudge it off, keep iterating
-        u.zr = zr + 1e-7 * (1 + (k & 7));
-        u.zi = zi + 1e-7 * (1 + (k >> 3 & 7));
-        u.flag = false;
-    }
+    if (!isfinite(u.zr) || !isfinite(u.zi)) nudge(u, zr, zi, k);
     // T = s0 + D s2 + D^2 s3 with D = step
     const double d2r = stepr * stepr - stepi * stepi, d2i = 2.0 * stepr * stepi;
     const double Tr = S.s0r + (stepr * S.s2r - stepi * S.s2i) + (d2r * S.s3r - d2i * S.s3i);
@@ -211,66 +237,127 @@ __device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0
     return u;
 }
 
-// Blocks with at most this many unflagged roots take the cooperative path.
+// Blocks with at most this many unconverged roots take the cooperative path.
 constexpr int SPARSE_MAX = 16;
+
+// Arguments shared by the kernels of a round.  Stars of every realisation
+// are concatenated; each front names its realisation, and the grid maps a
+// block to (front, block within the front) through bmap.
+template <class T> struct RoundArgs {
+    const T *stars;
+    const Real *reals;
+    const int2 *bmap;
+    const Front *fronts;
+    int32_t *flagrow;
+    const double2 *cur;
+    double2 *nxt;
+    const double2 *unit;   // (cos phi_j, -sin phi_j)
+    double tol_step, tol_step2, tol_mu;
+    double *out_re, *out_im, *caus_re, *caus_im;
+    double2 *bnd;
+    int32_t *counts;
+    Control *ctl;
+    double4 *vieta;
+};
+
+// What one block knows about its front and star field.
+template <class T> struct BlockCtx {
+    int f, q, k0, k, lane, n_r, n_stars, row, stamp;
+    bool valid, boundary;
+    int64_t base_f, out_off, bnd_row_off;
+    const T *stars;
+    const double2 *zsrc;
+    double m0, gamma, a, a1;
+    double2 e;   // (1 - kappa_s) e^{-i phi} of the front's row
+};
+
+template <class T>
+__device__ __forceinline__ bool enter(const RoundArgs<T> &A, int phase, BlockCtx<T> &B)
+{
+    const int2 fq = A.bmap[blockIdx.x];
+    B.f = fq.x;
+    B.q = fq.y;
+    const Front *F = A.fronts + B.f;
+    if (F->state != FRONT_ACTIVE || F->phase != phase) return false;
+    const Real *R = A.reals + F->real;
+    B.row = F->row;
+    B.stamp = F->stamp;
+    B.n_r = R->n_r;
+    B.n_stars = R->n_stars;
+    B.stars = A.stars + R->star_off;
+    B.m0 = R->m0;
+    B.gamma = R->gamma;
+    B.a = R->a;
+    B.a1 = R->a1;
+    B.base_f = F->it_off;
+    B.zsrc = A.cur + A.fronts[F->src].it_off;
+    B.out_off = R->out_off;
+    B.boundary = F->bnd_slot >= 0 && B.row == F->end_row;
+    B.bnd_row_off = R->bnd_off + (int64_t)max(F->bnd_slot, 0) * R->n_r;
+    const double2 u = A.unit[B.row];
+    B.e = make_double2(B.a * u.x, B.a * u.y);
+    B.lane = threadIdx.x;
+    B.k0 = B.q * 64;
+    B.k = B.k0 + B.lane;
+    B.valid = B.k < B.n_r;
+    return true;
+}
+
+// Write-back of a converged root: its row of the output (or the duplicate
+// boundary row of a subchain) and its caustic image.
+template <class T>
+__device__ __forceinline__ void put(const RoundArgs<T> &A, const BlockCtx<T> &B, int k,
+                                    const Update &u)
+{
+    if (B.boundary) {
+        A.bnd[B.bnd_row_off + k] = make_double2(u.zr, u.zi);
+        return;
+    }
+    const int64_t o = B.out_off + (int64_t)B.row * B.n_r + k;
+    A.out_re[o] = u.zr;
+    A.out_im[o] = u.zi;
+    if (A.caus_re) {
+        A.caus_re[o] = u.wr;
+        A.caus_im[o] = u.wi;
+    }
+}
 
 template <bool EQUAL>
 __global__ void __launch_bounds__(64)
-aberth_sweep_f64(const typename StarRec<EQUAL>::T *__restrict__ stars, double m0, int32_t n_stars,
-                 const double2 *__restrict__ cur, double2 *__restrict__ nxt,
-                 int32_t *__restrict__ flagrow, const Front *__restrict__ fronts,
-                 const double2 *__restrict__ etab, double gamma, double a, double a1,
-                 double tol_step2, double tol_mu, int32_t n_r, int32_t blocks_per_front,
-                 double *__restrict__ out_re, double *__restrict__ out_im,
-                 double *__restrict__ caus_re, double *__restrict__ caus_im,
-                 double2 *__restrict__ bnd, int32_t *__restrict__ counts,
-                 unsigned long long *__restrict__ updates)
+aberth_sweep_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
 {
     using T = typename StarRec<EQUAL>::T;
     __shared__ double4 tiles[128];   // two tiles of up to 32-byte records
-    const int f = blockIdx.x / blocks_per_front;
-    const int q = blockIdx.x - f * blocks_per_front;
-    const int state = fronts[f].state;
-    if (state != FRONT_ACTIVE) return;
-    const int row = fronts[f].row;
-    const int src = fronts[f].src;
-    const int lane = threadIdx.x;
-    const int64_t base_f = (int64_t)f * n_r;
-    const double2 *__restrict__ zsrc = cur + (int64_t)src * n_r;
-    const int k0 = q * 64;
-    const int k = k0 + lane;
-    const bool valid = k < n_r;
+    BlockCtx<T> B;
+    if (!enter(A, PH_F64, B)) return;
+    const int lane = B.lane, k0 = B.k0, k = B.k, n_r = B.n_r, n_stars = B.n_stars;
+    const bool valid = B.valid;
+    const int64_t base_f = B.base_f;
+    const double2 *__restrict__ zsrc = B.zsrc;
+    const T *__restrict__ stars = B.stars;
+    double2 *__restrict__ nxt = A.nxt;
+    int32_t *__restrict__ flagrow = A.flagrow;
+    const double m0 = B.m0, gamma = B.gamma, a = B.a, a1 = B.a1;
+    const double tol_step2 = A.tol_step2, tol_mu = A.tol_mu;
     double zr = 0.0, zi = 0.0;
     bool act = false;
     if (valid) {
         const double2 z = zsrc[k];
         zr = z.x;
         zi = z.y;
-        act = flagrow[base_f + k] != row;
+        act = flagrow[base_f + k] != B.stamp;
     }
     const unsigned long long amask = __ballot(act);
     const int n_act = __popcll(amask);
     if (valid && !act) nxt[base_f + k] = make_double2(zr, zi);   // carried forward
     if (n_act == 0) return;
 
-    const double2 e = etab[row];
-    const bool boundary = fronts[f].bnd_slot >= 0 && row == fronts[f].end_row;
-    double2 *__restrict__ bnd_row = bnd + (int64_t)max(fronts[f].bnd_slot, 0) * n_r;
+    const double2 e = B.e;
     auto store = [&](int kk, const Update &u) {
         nxt[base_f + kk] = make_double2(u.zr, u.zi);
         if (!u.flag) return;
-        flagrow[base_f + kk] = row;
-        if (boundary) {
-            bnd_row[kk] = make_double2(u.zr, u.zi);
-        } else {
-            const int64_t o = (int64_t)row * n_r + kk;
-            out_re[o] = u.zr;
-            out_im[o] = u.zi;
-            if (caus_re) {
-                caus_re[o] = u.wr;
-                caus_im[o] = u.wi;
-            }
-        }
+        flagrow[base_f + kk] = B.stamp;
+        put(A, B, kk, u);
     };
 
     int n_after = 0;
@@ -322,54 +409,401 @@ aberth_sweep_f64(const typename StarRec<EQUAL>::T *__restrict__ stars, double m0
         n_after = __popcll(__ballot(act && !u.flag));
     }
     if (lane == 0) {
-        if (n_after) atomicAdd(&counts[f], n_after);
-        atomicAdd(updates, (unsigned long long)n_act);
+        if (n_after) atomicAdd(&A.counts[B.f], n_after);
+        atomicAdd(&A.ctl->updates, (unsigned long long)n_act);
+        atomicAdd(&A.ctl->star_updates, (unsigned long long)n_act * (unsigned)B.n_stars);
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 Aberth sweep (mixed mode, first pass of a warm row)
+// ---------------------------------------------------------------------------
+
+// One Aberth step for every root of the row with the sums in FP32.  The
+// distance to each star is formed in FP64 and rounded, so no precision is
+// lost to the size of the coordinates; each 64-star tile is summed in FP32
+// and the tile sums are carried in FP64, which keeps the large near-star
+// terms from swamping the accumulation.  The other roots enter in FP32
+// coordinates (they only steer the step).  The step itself and the new
+// iterate are FP64.
+template <bool EQUAL>
+__global__ void __launch_bounds__(64)
+aberth_sweep_f32(RoundArgs<typename StarRec<EQUAL>::T> A)
+{
+    using T = typename StarRec<EQUAL>::T;
+    __shared__ double4 tiles[128];
+    BlockCtx<T> B;
+    if (!enter(A, PH_F32, B)) return;
+    const int lane = B.lane, k0 = B.k0, k = B.k, n_r = B.n_r, n_stars = B.n_stars;
+    const bool valid = B.valid;
+    const int64_t base_f = B.base_f;
+    const double2 *__restrict__ zsrc = B.zsrc;
+    const T *__restrict__ stars = B.stars;
+    const double m0 = B.m0, gamma = B.gamma;
+    double zr = 0.0, zi = 0.0;
+    if (valid) {
+        const double2 z = zsrc[k];
+        zr = z.x;
+        zi = z.y;
+    }
+    // star sums: FP32 within a tile, FP64 across tiles
+    double S1r = 0, S1i = 0, S2r = 0, S2i = 0, S3r = 0, S3i = 0;
+    float p1r = 0, p1i = 0, p2r = 0, p2i = 0, p3r = 0, p3i = 0;
+    stream_tiles_ex(
+        stars, n_stars, reinterpret_cast<T *>(tiles), Same{},
+        [&](int, const T &s) {
+            const float dx = (float)(zr - s.x), dy = (float)(zi - s.y);
+            const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, dy * dy));
+            const float ux = dx * inv, uy = dy * inv;
+            const float vx = fmaf(ux, ux, -uy * uy), vy = -2.0f * ux * uy;
+            const float tx = fmaf(vx, ux, vy * uy), ty = fmaf(vy, ux, -vx * uy);
+            p1r += ux;
+            p1i -= uy;
+            if (EQUAL) {
+                p2r += vx; p2i += vy;
+                p3r += tx; p3i += ty;
+            } else {
+                const float mi = (float)StarRec<EQUAL>::mass(s);
+                p2r = fmaf(mi, vx, p2r); p2i = fmaf(mi, vy, p2i);
+                p3r = fmaf(mi, tx, p3r); p3i = fmaf(mi, ty, p3i);
+            }
+        },
+        [&]() {
+            S1r += p1r; S1i += p1i; S2r += p2r; S2i += p2i; S3r += p3r; S3i += p3i;
+            p1r = p1i = p2r = p2i = p3r = p3i = 0.f;
+        });
+    // root-root sum in FP32 coordinates
+    const float zr32 = (float)zr, zi32 = (float)zi;
+    double Rr = 0, Ri = 0;
+    float qr = 0, qi = 0;
+    float2 *rt = reinterpret_cast<float2 *>(tiles);
+    auto to32 = [](const double2 &o) { return make_float2((float)o.x, (float)o.y); };
+    auto flush = [&]() { Rr += qr; Ri += qi; qr = qi = 0.f; };
+    auto other = [&](int, const float2 &o) {
+        const float dx = zr32 - o.x, dy = zi32 - o.y;
+        const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, dy * dy));
+        qr = fmaf(dx, inv, qr);
+        qi = fmaf(-dy, inv, qi);
+    };
+    const int own_hi = min(k0 + 64, n_r);
+    stream_tiles_ex(zsrc, k0, rt, to32, other, flush);
+    stream_tiles_ex(zsrc + k0, own_hi - k0, rt, to32,
+                    [&](int j, const float2 &o) {
+                        const float dx = zr32 - o.x, dy = zi32 - o.y;
+                        const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, dy * dy));
+                        const bool self = j == lane;
+                        qr = self ? qr : fmaf(dx, inv, qr);
+                        qi = self ? qi : fmaf(-dy, inv, qi);
+                    },
+                    flush);
+    stream_tiles_ex(zsrc + own_hi, n_r - own_hi, rt, to32, other, flush);
+
+    if (EQUAL) {
+        S2r *= m0; S2i *= m0; S3r *= m0; S3i *= m0;
+    }
+    const double2 e = B.e;
+    const double Fr = gamma + S2r - e.x, Fi = S2i - e.y;
+    const double Fpr = -2.0 * S3r, Fpi = -2.0 * S3i;
+    const double Gr = 2.0 * S1r - Rr, Gi = 2.0 * S1i - Ri;
+    const double Dr = Fpr + (Fr * Gr - Fi * Gi);
+    const double Di = Fpi + (Fr * Gi + Fi * Gr);
+    const double den = Dr * Dr + Di * Di;
+    Update u;
+    u.zr = zr - (Fr * Dr + Fi * Di) / den;
+    u.zi = zi - (Fi * Dr - Fr * Di) / den;
+    if (!isfinite(u.zr) || !isfinite(u.zi)) nudge(u, zr, zi, k);
+    if (valid) A.nxt[base_f + k] = make_double2(u.zr, u.zi);
+    const int n_valid = __popcll(__ballot(valid));
+    if (lane == 0) {
+        atomicAdd(&A.ctl->updates_f32, (unsigned long long)n_valid);
+        atomicAdd(&A.ctl->star_updates_f32, (unsigned long long)n_valid * (unsigned)B.n_stars);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Newton polish (mixed mode)
+// ---------------------------------------------------------------------------
+
+// Sums for the Newton polish: s0 = sum m u, s2 = sum m u^2, s3 = sum m u^3,
+// s4 = sum m u^4 (F'' = 6 s4).
+struct PSums {
+    double s0r, s0i, s2r, s2i, s3r, s3i, s4r, s4i;
+};
+
+__device__ __forceinline__ void zero(PSums &S)
+{
+    S.s0r = S.s0i = S.s2r = S.s2i = S.s3r = S.s3i = S.s4r = S.s4i = 0.0;
+}
+
+template <bool EQUAL, class T>
+__device__ __forceinline__ void add_star_polish(PSums &S, double zr, double zi, const T &s)
+{
+    const double dx = zr - s.x;
+    const double dy = zi - s.y;
+    const double inv = rcp_refined<RCP_STAR>(fma(dx, dx, dy * dy));
+    const double ux = dx * inv;
+    const double uy = dy * inv;
+    const double vx = fma(ux, ux, -uy * uy);
+    const double vy = -2.0 * ux * uy;
+    const double tx = fma(vx, ux, vy * uy);
+    const double ty = fma(vy, ux, -vx * uy);
+    const double qx = fma(vx, vx, -vy * vy);
+    const double qy = 2.0 * vx * vy;
+    if (EQUAL) {
+        S.s0r += ux; S.s0i -= uy;
+        S.s2r += vx; S.s2i += vy;
+        S.s3r += tx; S.s3i += ty;
+        S.s4r += qx; S.s4i += qy;
+    } else {
+        const double mi = StarRec<EQUAL>::mass(s);
+        S.s0r = fma(mi, ux, S.s0r); S.s0i = fma(-mi, uy, S.s0i);
+        S.s2r = fma(mi, vx, S.s2r); S.s2i = fma(mi, vy, S.s2i);
+        S.s3r = fma(mi, tx, S.s3r); S.s3i = fma(mi, ty, S.s3i);
+        S.s4r = fma(mi, qx, S.s4r); S.s4i = fma(mi, qy, S.s4i);
+    }
+}
+
+// Newton step z' = z - F/F' and its acceptance: after the step the error is
+// about |F''| |D|^2 / (2 |F'|) (quadratic convergence), trusted only while
+// |D| |F''/F'| stays small.  The caustic of z' reuses the sums through
+// sum m/(z' - z_i) = s0 + D s2 + D^2 s3 + D^3 s4 + O(D^4).
+template <bool EQUAL>
+__device__ __forceinline__ Update polish_finish(PSums S, double zr, double zi, double m0,
+                                                double2 e, double gamma, double a, double tol,
+                                                int k)
+{
+    if (EQUAL) {
+        S.s0r *= m0; S.s0i *= m0; S.s2r *= m0; S.s2i *= m0;
+        S.s3r *= m0; S.s3i *= m0; S.s4r *= m0; S.s4i *= m0;
+    }
+    const double Fr = gamma + S.s2r - e.x, Fi = S.s2i - e.y;
+    const double Fpr = -2.0 * S.s3r, Fpi = -2.0 * S.s3i;
+    const double den = Fpr * Fpr + Fpi * Fpi;
+    const double Dr = (Fr * Fpr + Fi * Fpi) / den;
+    const double Di = (Fi * Fpr - Fr * Fpi) / den;
+    Update u;
+    u.zr = zr - Dr;
+    u.zi = zi - Di;
+    const double aD = sqrt(Dr * Dr + Di * Di);
+    const double ratio = 6.0 * sqrt(S.s4r * S.s4r + S.s4i * S.s4i) / sqrt(den); // |F''/F'|
+    const double err = 0.5 * ratio * aD * aD;
+    u.flag = err <= tol && aD * ratio < 0.1 && aD < 1e-3;
+    if (!isfinite(u.zr) || !isfinite(u.zi)) nudge(u, zr, zi, k);
+    const double d2r = Dr * Dr - Di * Di, d2i = 2.0 * Dr * Di;
+    const double d3r = d2r * Dr - d2i * Di, d3i = d2r * Di + d2i * Dr;
+    const double Tr = S.s0r + (Dr * S.s2r - Di * S.s2i) + (d2r * S.s3r - d2i * S.s3i) +
+                      (d3r * S.s4r - d3i * S.s4i);
+    const double Ti = S.s0i + (Dr * S.s2i + Di * S.s2r) + (d2r * S.s3i + d2i * S.s3r) +
+                      (d3r * S.s4i + d3i * S.s4r);
+    u.wr = fma(a, u.zr, gamma * u.zr) - Tr;
+    u.wi = fma(a, u.zi, -gamma * u.zi) + Ti;
+    return u;
+}
+
+template <bool EQUAL>
+__global__ void __launch_bounds__(64)
+newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
+{
+    using T = typename StarRec<EQUAL>::T;
+    __shared__ double4 tiles[128];
+    BlockCtx<T> B;
+    if (!enter(A, PH_POLISH, B)) return;
+    const int lane = B.lane, k0 = B.k0, k = B.k, n_stars = B.n_stars;
+    const bool valid = B.valid;
+    const int64_t base_f = B.base_f;
+    const double2 *__restrict__ zsrc = B.zsrc;
+    const T *__restrict__ stars = B.stars;
+    double2 *__restrict__ nxt = A.nxt;
+    int32_t *__restrict__ flagrow = A.flagrow;
+    const double m0 = B.m0, gamma = B.gamma, a = B.a, tol = A.tol_step;
+    double zr = 0.0, zi = 0.0;
+    bool act = false;
+    if (valid) {
+        const double2 z = zsrc[k];
+        zr = z.x;
+        zi = z.y;
+        act = flagrow[base_f + k] != B.stamp;
+    }
+    const unsigned long long amask = __ballot(act);
+    const int n_act = __popcll(amask);
+    const double2 e = B.e;
+    double fr_ = zr, fi_ = zi;   // value this root ends the pass with
+    int n_after = 0;
+    if (n_act > 0 && n_act <= SPARSE_MAX) {
+        unsigned long long mm = amask;
+        while (mm) {
+            const int l = __ffsll((long long)mm) - 1;
+            mm &= mm - 1;
+            const double xk = __shfl(zr, l, 64), yk = __shfl(zi, l, 64);
+            PSums S;
+            zero(S);
+#pragma unroll 4
+            for (int i = lane; i < n_stars; i += 64) add_star_polish<EQUAL>(S, xk, yk, stars[i]);
+            wave_sum(S.s0r); wave_sum(S.s0i); wave_sum(S.s2r); wave_sum(S.s2i);
+            wave_sum(S.s3r); wave_sum(S.s3i); wave_sum(S.s4r); wave_sum(S.s4i);
+            const int kk = k0 + l;
+            const Update u = polish_finish<EQUAL>(S, xk, yk, m0, e, gamma, a, tol, kk);
+            if (lane == l) {
+                nxt[base_f + kk] = make_double2(u.zr, u.zi);
+                fr_ = u.zr;
+                fi_ = u.zi;
+                if (u.flag) {
+                    flagrow[base_f + kk] = B.stamp;
+                    put(A, B, kk, u);
+                }
+            }
+            n_after += u.flag ? 0 : 1;
+        }
+    } else if (n_act > 0) {
+        PSums S;
+        zero(S);
+        stream_tiles(stars, n_stars, reinterpret_cast<T *>(tiles),
+                     [&](int, const T &s) { add_star_polish<EQUAL>(S, zr, zi, s); });
+        const Update u = polish_finish<EQUAL>(S, zr, zi, m0, e, gamma, a, tol, k);
+        if (act) {
+            nxt[base_f + k] = make_double2(u.zr, u.zi);
+            fr_ = u.zr;
+            fi_ = u.zi;
+            if (u.flag) {
+                flagrow[base_f + k] = B.stamp;
+                put(A, B, k, u);
+            }
+        }
+        n_after = __popcll(__ballot(act && !u.flag));
+    }
+    if (valid && !act) nxt[base_f + k] = make_double2(zr, zi);
+    // this block's share of sum z and sum z^2 over the row (Vieta check)
+    double s1r = valid ? fr_ : 0.0, s1i = valid ? fi_ : 0.0;
+    double s2r = valid ? fr_ * fr_ - fi_ * fi_ : 0.0, s2i = valid ? 2.0 * fr_ * fi_ : 0.0;
+    wave_sum(s1r); wave_sum(s1i); wave_sum(s2r); wave_sum(s2i);
+    if (lane == 0) {
+        A.vieta[blockIdx.x] = make_double4(s1r, s1i, s2r, s2i);
+        if (n_after) atomicAdd(&A.counts[B.f], n_after);
+        if (n_act) {
+            atomicAdd(&A.ctl->polish_updates, (unsigned long long)n_act);
+            atomicAdd(&A.ctl->star_updates_polish, (unsigned long long)n_act * (unsigned)B.n_stars);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Seeds and front control
+// ---------------------------------------------------------------------------
+
 // Cold-start seeds at the centre row of each subchain: root 2i <- z_i + 1,
-// root 2i+1 <- z_i - 1 (Sec. 3.2).
-__global__ void seed_centres(const double2 *__restrict__ stars, int32_t n_r, int32_t n_sub,
+// root 2i+1 <- z_i - 1 (Sec. 3.2).  One thread per root of every front that
+// starts cold (the downward front of each subchain).
+template <class T>
+__global__ void seed_centres(const T *__restrict__ stars, const Real *__restrict__ reals,
+                             const Front *__restrict__ fronts, const int2 *__restrict__ bmap,
                              double2 *__restrict__ iter)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)n_sub * n_r) return;
-    const int s = (int)(t / n_r);
-    const int k = (int)(t - (int64_t)s * n_r);
-    const double2 z = stars[k >> 1];
-    iter[(int64_t)(2 * s) * n_r + k] = make_double2(z.x + ((k & 1) ? -1.0 : 1.0), z.y);
+    const int2 fq = bmap[blockIdx.x];
+    const Front *F = fronts + fq.x;
+    if (F->dir != 0) return;
+    const Real *R = reals + F->real;
+    const int k = fq.y * 64 + threadIdx.x;
+    if (k >= R->n_r) return;
+    const T z = stars[R->star_off + (k >> 1)];
+    iter[F->it_off + k] = make_double2(z.x + ((k & 1) ? -1.0 : 1.0), z.y);
 }
 
 constexpr int CONTROL_THREADS = 256;
-constexpr int MAX_FRONTS = 4096;
+constexpr int MAX_FRONTS = 1 << 16;
+constexpr int MAX_POLISH = 3;
 
-// Advances every front whose row converged in the sweep just run: a cold
-// start at a subchain centre hands the upward half to its partner front and
-// turns downward itself; a warm row moves one row on, or finishes at its end
-// row.  A front that reaches its sweep cap stops and is counted as failed,
-// together with a partner it can no longer start.
+__device__ __forceinline__ void row_done(Front &fr, int32_t *st, int f)
+{
+    if (fr.row == fr.end_row) {
+        fr.state = FRONT_DONE;
+        st[f] = FRONT_DONE;
+    } else {
+        fr.row += fr.dir;
+        fr.sweeps = 0;
+        fr.passes = 0;
+        fr.phase = fr.mode;
+        fr.stamp = 4 * fr.row;
+    }
+}
+
+// Advances every front after a round.  FP64 phase: a converged cold start
+// hands the upward half to its partner front and turns downward itself; a
+// converged warm row moves one row on or finishes at its end row; a front
+// that reaches its sweep cap stops and is counted as failed (with a partner
+// it can no longer start).  FP32 phase: always followed by the polish.
+// Polish phase: a row whose roots were all accepted and whose sums satisfy
+// the row identities is done; otherwise more polish passes, then FP64 sweeps
+// for the rest (all roots of the row again if an identity failed).
+//
+// Row identities: the rationalised polynomial has leading coefficient
+// c = gamma - (1 - kappa_s) e^{-i phi} and next coefficient -2 c sum z_i, so
+// sum r = 2 sum z_i and sum r^2 = 2 sum z_i^2 - 2 M / c (M = sum m_i).  A
+// root found twice and one missed shifts them by about their distance.
+//
+// `st` keeps the states in LDS so that a partner activated by one thread is
+// not processed by another in the same pass; with more fronts than fit, the
+// kernel runs as several work groups over disjoint ranges that keep each
+// subchain's two fronts together.
 __global__ void __launch_bounds__(CONTROL_THREADS)
 aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t n_fronts,
                Control *__restrict__ ctl, int32_t max_cold, int32_t max_warm,
-               int32_t *__restrict__ workflag)
+               int32_t *__restrict__ workflag, const double4 *__restrict__ vieta,
+               const Real *__restrict__ reals, const double2 *__restrict__ unit,
+               int32_t fronts_per_group)
 {
-    __shared__ int32_t st[MAX_FRONTS];
+    __shared__ int32_t st[4096];
     __shared__ int32_t s_active, s_live;
     const int tid = threadIdx.x;
+    const int f0 = blockIdx.x * fronts_per_group;
+    const int f1 = min(n_fronts, f0 + fronts_per_group);
     if (tid == 0) {
         s_active = 0;
         s_live = 0;
     }
-    for (int f = tid; f < n_fronts; f += CONTROL_THREADS) st[f] = fronts[f].state;
+    for (int f = f0 + tid; f < f1; f += CONTROL_THREADS) st[f - f0] = fronts[f].state;
     __syncthreads();
-    for (int f = tid; f < n_fronts; f += CONTROL_THREADS) {
-        if (st[f] != FRONT_ACTIVE) continue;
-        atomicOr(&s_live, 1);
+    for (int f = f0 + tid; f < f1; f += CONTROL_THREADS) {
+        if (st[f - f0] != FRONT_ACTIVE) continue;
         Front fr = fronts[f];
+        atomicOr(&s_live, 1 << fr.phase);
         const int32_t c = counts[f];
         counts[f] = 0;
         fr.src = f;
-        if (c == 0) {
+        if (fr.phase == PH_F32) {
+            fr.phase = PH_POLISH;
+            fr.passes = 0;
+        } else if (fr.phase == PH_POLISH) {
+            if (c == 0) {
+                const Real R = reals[fr.real];
+                const int bpf = (R.n_r + 63) / 64;
+                double a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+                for (int b = 0; b < bpf; ++b) {
+                    const double4 t = vieta[fr.blk0 + b];
+                    a1r += t.x; a1i += t.y; a2r += t.z; a2i += t.w;
+                }
+                const double2 u = unit[fr.row];
+                const double cr = R.gamma - R.a * u.x, ci = -R.a * u.y;   // c(phi)
+                const double cc = cr * cr + ci * ci;
+                const double mcr = R.M * cr / cc, mci = -R.M * ci / cc;   // M / c
+                const double e1r = a1r - 2.0 * R.sz_r, e1i = a1i - 2.0 * R.sz_i;
+                const double e2r = a2r - (2.0 * R.sz2_r - 2.0 * mcr);
+                const double e2i = a2i - (2.0 * R.sz2_i - 2.0 * mci);
+                const bool ok = sqrt(e1r * e1r + e1i * e1i) <= R.tol1 &&
+                                sqrt(e2r * e2r + e2i * e2i) <= R.tol2;
+                if (ok) {
+                    row_done(fr, st, f - f0);
+                } else {
+                    fr.stamp += 1;   // every root of the row active again
+                    fr.phase = PH_F64;
+                    fr.sweeps = 0;
+                    atomicAdd((unsigned long long *)&ctl->rows_fallback, 1ull);
+                }
+            } else if (++fr.passes >= MAX_POLISH) {
+                fr.phase = PH_F64;
+                fr.sweeps = 0;
+                atomicAdd((unsigned long long *)&ctl->rows_fallback, 1ull);
+            }
+        } else if (c == 0) {
             if (fr.dir == 0) {
                 fr.cold = fr.sweeps + 1;
                 const int p = fr.partner;
@@ -378,33 +812,33 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
                 pr.state = FRONT_ACTIVE;
                 pr.row = centre + 1;
                 pr.dir = 1;
-                pr.src = f;   // first sweep reads the converged centre row
+                pr.src = f;   // first pass reads the converged centre row
                 pr.sweeps = 0;
+                pr.passes = 0;
+                pr.phase = pr.mode;
+                pr.stamp = 4 * pr.row;
                 fronts[p] = pr;
-                st[p] = FRONT_ACTIVE;
+                st[p - f0] = FRONT_ACTIVE;
                 fr.dir = -1;
                 fr.row = centre - 1;
                 fr.sweeps = 0;
+                fr.passes = 0;
+                fr.phase = fr.mode;
+                fr.stamp = 4 * fr.row;
             } else {
                 fr.max_warm = max(fr.max_warm, fr.sweeps + 1);
-                if (fr.row == fr.end_row) {
-                    fr.state = FRONT_DONE;
-                    st[f] = FRONT_DONE;
-                } else {
-                    fr.row += fr.dir;
-                    fr.sweeps = 0;
-                }
+                row_done(fr, st, f - f0);
             }
         } else {
             fr.sweeps += 1;
             if (fr.sweeps >= (fr.dir == 0 ? max_cold : max_warm)) {
                 fr.state = FRONT_FAILED;
-                st[f] = FRONT_FAILED;
+                st[f - f0] = FRONT_FAILED;
                 atomicAdd(&ctl->failed_rows, 1);
                 atomicAdd((unsigned long long *)&ctl->unconverged, (unsigned long long)c);
                 if (fr.dir == 0) {
                     fronts[fr.partner].state = FRONT_FAILED;
-                    st[fr.partner] = FRONT_FAILED;
+                    st[fr.partner - f0] = FRONT_FAILED;
                 }
             }
         }
@@ -412,120 +846,263 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
     }
     __syncthreads();
     int mine = 0;
-    for (int f = tid; f < n_fronts; f += CONTROL_THREADS)
-        mine += (st[f] == FRONT_ACTIVE || st[f] == FRONT_IDLE);
+    for (int f = f0 + tid; f < f1; f += CONTROL_THREADS)
+        mine += (st[f - f0] == FRONT_ACTIVE || st[f - f0] == FRONT_IDLE);
     if (mine) atomicAdd(&s_active, mine);
     __syncthreads();
     if (tid == 0) {
-        ctl->active_fronts = s_active;
-        if (s_live) ctl->live_sweeps += 1;
-        *workflag = s_live;
+        // several groups: each adds its share; the first round of counting is
+        // reset by the host-side clear kernel below
+        atomicAdd(&ctl->active_fronts, s_active);
+        if (s_live) atomicOr(workflag, s_live);
     }
 }
 
-// Library choice of S: enough fronts to give every SIMD several waves, few
-// enough that the S cold starts stay a small share of the work, and S must
-// divide m/2 so that every subchain has an integer centre row.
-static int choose_subchains(int64_t n_r, int64_t m, int rpl)
+// Clears the per-round totals the control groups add into, and counts the
+// round as live if any group saw an active front (runs after them).
+__global__ void control_begin(Control *__restrict__ ctl, int32_t *__restrict__ workflag)
 {
-    const int64_t waves_per_front = ceil_div(n_r, 64 * rpl);
-    const int64_t target_waves = 1024 * 10;
-    int64_t want = ceil_div(target_waves, 2 * waves_per_front);
-    want = std::min<int64_t>(want, std::max<int64_t>(1, m / 150));
-    want = std::min<int64_t>(want, MAX_FRONTS / 2);
-    want = std::max<int64_t>(want, 1);
+    if (threadIdx.x == 0) {
+        ctl->active_fronts = 0;
+        *workflag = 0;
+    }
+}
+
+__global__ void control_end(Control *__restrict__ ctl, const int32_t *__restrict__ workflag)
+{
+    if (threadIdx.x == 0 && *workflag) ctl->live_sweeps += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Subchains and the autotuner
+// ---------------------------------------------------------------------------
+
+// Subchain counts must divide m/2 (integer centre rows).
+// Cost model of one field's run with S subchains, in units of one root
+// update's star-and-root work (N + 2N terms): every subchain pays a cold
+// start (~cold sweeps of all 2N roots) on top of the ~u updates per root and
+// row that the rows need whatever S is; the critical path is the longest
+// front, (m / 2S) rows of ~rounds_per_row rounds each, and a round costs at
+// least one wave's full pass.
+struct TuneModel {
+    double cold_sweeps = 25.0, updates_per_row = 2.05, rounds_per_row = 3.0;
+};
+
+// Picks S for every field of a call.  All fields share one round clock, so a
+// common S keeps their fronts in step; it is the divisor of m/2 that
+// minimises max(total work / machine, critical path) under the model above,
+// with the machine taken as 1024 SIMDs x 10 resident waves, among the
+// divisors that leave every subchain at least 64 rows.
+static int autotune_subchains(const std::vector<RealHost> &reals, int64_t m, const TuneModel &tm)
+{
     const int64_t half = m / 2;
-    for (int64_t s = want; s >= 1; --s)
-        if (half % s == 0) return (int)s;
-    return 1;
+    double best = 1e300;
+    int best_s = 1;
+    double max_pass = 0.0;   // one wave's pass over the largest field
+    for (const RealHost &r : reals) max_pass = std::max(max_pass, 3.0 * (double)r.n);
+    const double slots = 1024.0 * 10.0;
+    // at least 64 rows per subchain: shorter ones are mostly cold start
+    const int64_t s_max = std::max<int64_t>(
+        1, std::min<int64_t>(MAX_FRONTS / (2 * (int64_t)reals.size()), m / 64));
+    for (int64_t s = 1; s <= std::min<int64_t>(half, std::min<int64_t>(s_max, 2048)); ++s) {
+        if (half % s) continue;
+        double work = 0.0, waves = 0.0;
+        for (const RealHost &r : reals) {
+            const double n_r = 2.0 * (double)r.n, terms = 3.0 * (double)r.n;
+            const double blocks = std::ceil(n_r / 64.0);
+            work += terms * blocks * (tm.updates_per_row * (double)(m + s) +
+                                      tm.cold_sweeps * (double)s);
+            waves += 2.0 * (double)s * blocks;
+        }
+        const double rounds = tm.rounds_per_row * (double)half / (double)s + tm.cold_sweeps;
+        const double occupancy = std::min(1.0, waves / slots);
+        const double t = std::max(work / (slots * std::max(occupancy, 1e-3)), rounds * max_pass);
+        if (t < best * 0.999) {
+            best = t;
+            best_s = (int)s;
+        }
+    }
+    return best_s;
 }
 
-template <bool EQUAL>
-static void launch_sweep(Ctx *c, int n_fronts, int bpf, const double2 *cur, double2 *nxt,
-                         const double2 *etab, double a, double a1, double tol_step2,
-                         double tol_mu, int32_t n_r, double *out_re, double *out_im,
-                         double *caus_re, double *caus_im)
-{
-    using T = typename StarRec<EQUAL>::T;
-    const T *stars = EQUAL ? reinterpret_cast<const T *>(c->stars.p)
-                           : reinterpret_cast<const T *>(c->stars4.p);
-    hipLaunchKernelGGL((aberth_sweep_f64<EQUAL>), dim3(n_fronts * bpf), dim3(64), 0, c->stream,
-                       stars, c->mass0, (int32_t)c->n, cur, nxt, c->flagrow.as<int32_t>(),
-                       c->fronts.as<Front>(), etab, c->gamma, a, a1, tol_step2, tol_mu, n_r, bpf,
-                       out_re, out_im, caus_re, caus_im, c->bnd.as<double2>(),
-                       c->counts.as<int32_t>(), &c->control.as<Control>()->updates);
-}
+// ---------------------------------------------------------------------------
+// Host driver
+// ---------------------------------------------------------------------------
 
-mlcc_status find_critical_curves_fp64(Ctx *c, const mlcc_cc_params *p, double *roots_re,
+mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *roots_re,
                                       double *roots_im, double *caus_re, double *caus_im,
                                       int32_t *chain_next, mlcc_cc_stats *stats)
 {
-    constexpr int RPL = 1;
-    const int64_t n = c->n, n_r = 2 * n, m = p->m_steps;
-    if (n_r > ((int64_t)1 << 30)) return fail(MLCC_ERR_INVALID, "too many roots");
-    const int S = p->n_subchains > 0 ? p->n_subchains : choose_subchains(n_r, m, RPL);
-    if (S > MAX_FRONTS / 2) return fail(MLCC_ERR_INVALID, "n_subchains > %d", MAX_FRONTS / 2);
+    const bool mixed = p->precision == MLCC_MIXED;
+    const int64_t m = p->m_steps;
+    const int n_real = (int)c->reals.size();
+    // one field with equal masses: (x, y) records, the mass applied once
+    const bool equal = !c->batched && c->equal_mass;
+    int S = p->n_subchains;
+    if (S <= 0) S = autotune_subchains(c->reals, m, TuneModel{});
+    if ((m / 2) % S) return fail(MLCC_ERR_INVALID, "n_subchains=%d must divide m/2", S);
     const int64_t L = m / S;
-    const int F = 2 * S;
-    const int bpf = (int)ceil_div(n_r, 64 * RPL);
-    if ((int64_t)F * bpf > 0x7fffffff) return fail(MLCC_ERR_INVALID, "launch too large");
     const int max_cold = p->max_iter_cold > 0 ? p->max_iter_cold : 500;
     const int max_warm = p->max_iter_warm > 0 ? p->max_iter_warm : 100;
     constexpr int MAX_BATCH = 256;
+    constexpr int KINDS = 3;   // timed kernels per round: FP64 sweep, FP32 sweep, polish
 
-    MLCC_TRY(c->iter[0].reserve((size_t)F * n_r * sizeof(double2)));
-    MLCC_TRY(c->iter[1].reserve((size_t)F * n_r * sizeof(double2)));
-    MLCC_TRY(c->flagrow.reserve((size_t)F * n_r * sizeof(int32_t)));
+    // fronts, blocks and offsets of every field
+    std::vector<Real> rd(n_real);
+    std::vector<Front> fr;
+    std::vector<int2> bmap;
+    int64_t it_total = 0, bnd_total = 0, max_nr = 0;
+    const int32_t warm_phase = mixed ? PH_F32 : PH_F64;
+    for (int r = 0; r < n_real; ++r) {
+        const RealHost &h = c->reals[r];
+        const int64_t n_r = 2 * h.n;
+        if (n_r > ((int64_t)1 << 30)) return fail(MLCC_ERR_INVALID, "too many roots");
+        max_nr = std::max(max_nr, n_r);
+        Real &R = rd[r];
+        R.star_off = h.star_off;
+        R.out_off = (m + 1) * 2 * h.star_off;
+        R.bnd_off = bnd_total;
+        bnd_total += (int64_t)(S - 1) * n_r;
+        R.n_stars = (int32_t)h.n;
+        R.n_r = (int32_t)n_r;
+        R.m0 = h.m0;
+        R.gamma = h.gamma;
+        R.a = 1.0 - h.kappa_s;
+        R.a1 = std::fabs(R.a);
+        R.sz_r = h.sum_z.x;
+        R.sz_i = h.sum_z.y;
+        R.sz2_r = h.sum_z2.x;
+        R.sz2_i = h.sum_z2.y;
+        R.M = h.mass_total;
+        // every root carries up to tol_step of error, and the sums round
+        R.tol1 = (double)n_r * p->tol_step + 1e-12 * (2.0 * h.sum_abs_z + (double)n_r);
+        R.tol2 = 2.0 * (h.max_abs_z + 2.0) * (double)n_r * p->tol_step +
+                 1e-12 * (2.0 * h.sum_abs_z2 + (double)n_r + h.mass_total);
+        const int bpf = (int)ceil_div(n_r, 64);
+        for (int s = 0; s < S; ++s) {
+            const int32_t lo = (int32_t)(s * L), hi = (int32_t)(lo + L), cen = (int32_t)(lo + L / 2);
+            const int fd = (int)fr.size();
+            Front d{};
+            d.row = cen; d.dir = 0; d.end_row = lo; d.state = FRONT_ACTIVE;
+            d.src = fd; d.partner = fd + 1; d.bnd_slot = s >= 1 ? s - 1 : -1;
+            d.lo = lo; d.hi = hi;
+            d.phase = PH_F64; d.mode = warm_phase; d.stamp = 4 * cen;
+            d.real = r;
+            Front u{};
+            u.row = cen + 1; u.dir = 1; u.end_row = hi; u.state = FRONT_IDLE;
+            u.src = fd + 1; u.partner = -1; u.bnd_slot = -1; u.lo = lo; u.hi = hi;
+            u.phase = warm_phase; u.mode = warm_phase; u.stamp = 4 * (cen + 1);
+            u.real = r;
+            for (Front *x : {&d, &u}) {
+                x->it_off = it_total;
+                it_total += n_r;
+                x->blk0 = (int32_t)bmap.size();
+                const int fi = (int)fr.size();
+                for (int q = 0; q < bpf; ++q) bmap.push_back(make_int2(fi, q));
+                fr.push_back(*x);
+            }
+        }
+    }
+    const int F = (int)fr.size();
+    const int64_t nblocks = (int64_t)bmap.size();
+    if (F > MAX_FRONTS || nblocks > 0x7fffffff)
+        return fail(MLCC_ERR_INVALID, "too many fronts (%d) for one call", F);
+    // the control kernel's groups hold whole subchains (two fronts) in LDS
+    const int fronts_per_group = 4096;
+    const int control_groups = (int)ceil_div(F, fronts_per_group);
+
+    MLCC_TRY(c->iter[0].reserve((size_t)it_total * sizeof(double2)));
+    MLCC_TRY(c->iter[1].reserve((size_t)it_total * sizeof(double2)));
+    MLCC_TRY(c->flagrow.reserve((size_t)it_total * sizeof(int32_t)));
     MLCC_TRY(c->fronts.reserve((size_t)F * sizeof(Front)));
     MLCC_TRY(c->counts.reserve((size_t)F * sizeof(int32_t)));
     MLCC_TRY(c->control.reserve(sizeof(Control)));
     MLCC_TRY(c->etab.reserve((size_t)(m + 1) * sizeof(double2)));
-    MLCC_TRY(c->bnd.reserve((size_t)std::max(S - 1, 1) * n_r * sizeof(double2)));
+    MLCC_TRY(c->bnd.reserve((size_t)std::max<int64_t>(bnd_total, 1) * sizeof(double2)));
+    MLCC_TRY(c->vieta.reserve((size_t)nblocks * sizeof(double4)));
+    MLCC_TRY(c->reals_d.reserve((size_t)n_real * sizeof(Real)));
+    MLCC_TRY(c->bmap.reserve((size_t)nblocks * sizeof(int2)));
     MLCC_TRY(c->workflags.reserve(2 * MAX_BATCH * sizeof(int32_t)));
     MLCC_TRY(ensure_pinned(c, 2 * (sizeof(Control) + MAX_BATCH * sizeof(int32_t))));
 
-    // phase table: (1 - kappa_s) e^{-i phi_j}, phi_j = 2 pi j / m (host libm)
-    std::vector<double2> et(m + 1);
-    const double a = 1.0 - c->kappa_s;
+    // unit phase table (cos phi_j, -sin phi_j), phi_j = 2 pi j / m (host libm);
+    // each field scales it by its own 1 - kappa_s
+    std::vector<double2> unit(m + 1);
     for (int64_t j = 0; j <= m; ++j) {
         const double phi = (2.0 * M_PI * (double)j) / (double)m;
-        et[j] = make_double2(a * std::cos(phi), a * -std::sin(phi));
-    }
-    std::vector<Front> fr(F);
-    for (int s = 0; s < S; ++s) {
-        const int32_t lo = (int32_t)(s * L), hi = (int32_t)(lo + L), cen = (int32_t)(lo + L / 2);
-        Front &d = fr[2 * s];
-        d = Front{};
-        d.row = cen; d.dir = 0; d.end_row = lo; d.state = FRONT_ACTIVE; d.sweeps = 0;
-        d.src = 2 * s; d.partner = 2 * s + 1; d.bnd_slot = s >= 1 ? s - 1 : -1;
-        d.lo = lo; d.hi = hi;
-        Front &u = fr[2 * s + 1];
-        u = Front{};
-        u.row = cen + 1; u.dir = 1; u.end_row = hi; u.state = FRONT_IDLE; u.sweeps = 0;
-        u.src = 2 * s + 1; u.partner = -1; u.bnd_slot = -1; u.lo = lo; u.hi = hi;
+        unit[j] = make_double2(std::cos(phi), -std::sin(phi));
     }
     Control ctl0{};
     ctl0.active_fronts = F;
-    MLCC_HIP(hipMemcpyAsync(c->etab.p, et.data(), (m + 1) * sizeof(double2),
+    MLCC_HIP(hipMemcpyAsync(c->etab.p, unit.data(), (m + 1) * sizeof(double2),
                             hipMemcpyHostToDevice, c->stream));
     MLCC_HIP(hipMemcpyAsync(c->fronts.p, fr.data(), F * sizeof(Front), hipMemcpyHostToDevice,
                             c->stream));
+    MLCC_HIP(hipMemcpyAsync(c->reals_d.p, rd.data(), n_real * sizeof(Real), hipMemcpyHostToDevice,
+                            c->stream));
+    MLCC_HIP(hipMemcpyAsync(c->bmap.p, bmap.data(), nblocks * sizeof(int2), hipMemcpyHostToDevice,
+                            c->stream));
     MLCC_HIP(hipMemcpyAsync(c->control.p, &ctl0, sizeof ctl0, hipMemcpyHostToDevice, c->stream));
-    MLCC_HIP(hipMemsetAsync(c->flagrow.p, 0xff, (size_t)F * n_r * sizeof(int32_t), c->stream));
+    MLCC_HIP(hipMemsetAsync(c->flagrow.p, 0xff, (size_t)it_total * sizeof(int32_t), c->stream));
     MLCC_HIP(hipMemsetAsync(c->counts.p, 0, F * sizeof(int32_t), c->stream));
-    {
-        const int64_t tot = (int64_t)S * n_r;
-        hipLaunchKernelGGL(seed_centres, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0,
-                           c->stream, c->stars.as<double2>(), (int32_t)n_r, S,
-                           c->iter[0].as<double2>());
-        MLCC_HIP(hipGetLastError());
-    }
+    if (equal)
+        hipLaunchKernelGGL(seed_centres<double2>, dim3((unsigned)nblocks), dim3(64), 0, c->stream,
+                           c->stars.as<double2>(), c->reals_d.as<Real>(), c->fronts.as<Front>(),
+                           c->bmap.as<int2>(), c->iter[0].as<double2>());
+    else
+        hipLaunchKernelGGL(seed_centres<double4>, dim3((unsigned)nblocks), dim3(64), 0, c->stream,
+                           c->stars4.as<double4>(), c->reals_d.as<Real>(), c->fronts.as<Front>(),
+                           c->bmap.as<int2>(), c->iter[0].as<double2>());
+    MLCC_HIP(hipGetLastError());
     // Host copies must finish before the vectors above go out of scope.
     MLCC_HIP(hipStreamSynchronize(c->stream));
+    // The rounds run on the caller's stream, or, when that is the legacy null
+    // stream (which cannot be captured into a graph), on a stream of the
+    // context's own; the call is synchronous either way.
+    hipStream_t rs = c->stream;
+    if (!rs) {
+        if (!c->own_stream) MLCC_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+        rs = c->own_stream;
+    }
 
-    const double tol_step2 = p->tol_step * p->tol_step;
-    const double a1 = std::fabs(a);
-    const double2 *etab = c->etab.as<double2>();
+    RoundArgs<double2> A2{};
+    RoundArgs<double4> A4{};
+    auto fill = [&](auto &A, auto stars, const double2 *cur, double2 *nxt) {
+        A.stars = stars;
+        A.reals = c->reals_d.as<Real>();
+        A.bmap = c->bmap.as<int2>();
+        A.fronts = c->fronts.as<Front>();
+        A.flagrow = c->flagrow.as<int32_t>();
+        A.cur = cur;
+        A.nxt = nxt;
+        A.unit = c->etab.as<double2>();
+        A.tol_step = p->tol_step;
+        A.tol_step2 = p->tol_step * p->tol_step;
+        A.tol_mu = p->tol_inv_mu;
+        A.out_re = roots_re;
+        A.out_im = roots_im;
+        A.caus_re = caus_re;
+        A.caus_im = caus_im;
+        A.bnd = c->bnd.as<double2>();
+        A.counts = c->counts.as<int32_t>();
+        A.ctl = c->control.as<Control>();
+        A.vieta = c->vieta.as<double4>();
+    };
+    const dim3 grid((unsigned)nblocks);
+    auto launch_kind = [&](int kind, const double2 *cur, double2 *nxt) {
+        if (equal) {
+            fill(A2, c->stars.as<double2>(), cur, nxt);
+            if (kind == 0) hipLaunchKernelGGL(aberth_sweep_f64<true>, grid, dim3(64), 0, rs, A2);
+            if (kind == 1) hipLaunchKernelGGL(aberth_sweep_f32<true>, grid, dim3(64), 0, rs, A2);
+            if (kind == 2) hipLaunchKernelGGL(newton_polish_f64<true>, grid, dim3(64), 0, rs, A2);
+        } else {
+            fill(A4, c->stars4.as<double4>(), cur, nxt);
+            if (kind == 0) hipLaunchKernelGGL(aberth_sweep_f64<false>, grid, dim3(64), 0, rs, A4);
+            if (kind == 1) hipLaunchKernelGGL(aberth_sweep_f32<false>, grid, dim3(64), 0, rs, A4);
+            if (kind == 2) hipLaunchKernelGGL(newton_polish_f64<false>, grid, dim3(64), 0, rs, A4);
+        }
+    };
+
     Control *dctl = c->control.as<Control>();
     char *pin = static_cast<char *>(c->pinned);
     auto pin_ctl = [&](int slot) {
@@ -536,54 +1113,121 @@ mlcc_status find_critical_curves_fp64(Ctx *c, const mlcc_cc_params *p, double *r
                                            sizeof(Control));
     };
 
+    // event pairs: [slot][round][kind][begin, end]
     std::vector<hipEvent_t> evs;
+    auto ev = [&](int slot, int i, int kind, int end) -> hipEvent_t & {
+        return evs[(((size_t)slot * MAX_BATCH + i) * KINDS + kind) * 2 + end];
+    };
     if (p->timing) {
-        evs.resize(4 * MAX_BATCH);
+        evs.resize((size_t)2 * MAX_BATCH * KINDS * 2);
         for (auto &e : evs) MLCC_HIP(hipEventCreate(&e));
     }
-    auto cleanup = [&]() {
-        for (auto &e : evs) (void)hipEventDestroy(e);
-        evs.clear();
-    };
     hipEvent_t done_ev[2];
     MLCC_HIP(hipEventCreateWithFlags(&done_ev[0], hipEventDisableTiming));
     MLCC_HIP(hipEventCreateWithFlags(&done_ev[1], hipEventDisableTiming));
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int graph_len = 0;
+    auto cleanup = [&]() {
+        for (auto &e : evs) (void)hipEventDestroy(e);
+        evs.clear();
+        for (auto &g : gexec)
+            if (g) (void)hipGraphExecDestroy(g);
+        (void)hipEventDestroy(done_ev[0]);
+        (void)hipEventDestroy(done_ev[1]);
+    };
 
+    const bool use_graphs = !p->timing;
     int parity = 0;
     int batch_len[2] = {0, 0};
     int G = 4;
-    double sweep_ms = 0.0;
+    double kind_ms[KINDS] = {0.0, 0.0, 0.0};
+    int64_t kind_launches[KINDS] = {0, 0, 0};
     int32_t polls = 0;
-    // Every front finishes within max_cold + (L/2 + 1) * max_warm sweeps; the
-    // extra margin covers the batches enqueued ahead of the last poll.
-    const int64_t launch_cap = (int64_t)max_cold + (L / 2 + 2) * (int64_t)max_warm + 4 * MAX_BATCH;
+    // Every front finishes within max_cold + (L/2 + 1) * (max_warm + polish
+    // rounds) rounds; the extra margin covers the batches enqueued ahead of
+    // the last poll.
+    const int64_t launch_cap =
+        (int64_t)max_cold + (L / 2 + 2) * (int64_t)(max_warm + MAX_POLISH + 2) + 4 * MAX_BATCH;
     int64_t launched = 0;
-    auto enqueue_batch = [&](int slot, int g) -> mlcc_status {
+    // One round: every pass kind once over every block (blocks whose front is
+    // in another phase return at once), then the control kernel.
+    auto enqueue_rounds = [&](int slot, int g, bool timed) -> mlcc_status {
         for (int i = 0; i < g; ++i) {
             const double2 *cur = c->iter[parity].as<double2>();
             double2 *nxt = c->iter[parity ^ 1].as<double2>();
-            if (p->timing) MLCC_HIP(hipEventRecord(evs[(slot * MAX_BATCH + i) * 2], c->stream));
-            if (c->equal_mass)
-                launch_sweep<true>(c, F, bpf, cur, nxt, etab, a, a1, tol_step2, p->tol_inv_mu,
-                                   (int32_t)n_r, roots_re, roots_im, caus_re, caus_im);
-            else
-                launch_sweep<false>(c, F, bpf, cur, nxt, etab, a, a1, tol_step2, p->tol_inv_mu,
-                                    (int32_t)n_r, roots_re, roots_im, caus_re, caus_im);
-            if (p->timing) MLCC_HIP(hipEventRecord(evs[(slot * MAX_BATCH + i) * 2 + 1], c->stream));
-            hipLaunchKernelGGL(aberth_control, dim3(1), dim3(CONTROL_THREADS), 0, c->stream,
-                               c->fronts.as<Front>(), c->counts.as<int32_t>(), F, dctl, max_cold,
-                               max_warm, c->workflags.as<int32_t>() + slot * MAX_BATCH + i);
+            for (int kind = 0; kind < (mixed ? KINDS : 1); ++kind) {
+                if (timed) MLCC_HIP(hipEventRecord(ev(slot, i, kind, 0), rs));
+                launch_kind(kind, cur, nxt);
+                if (timed) MLCC_HIP(hipEventRecord(ev(slot, i, kind, 1), rs));
+            }
+            int32_t *wf = c->workflags.as<int32_t>() + slot * MAX_BATCH + i;
+            hipLaunchKernelGGL(control_begin, dim3(1), dim3(64), 0, rs, dctl, wf);
+            hipLaunchKernelGGL(aberth_control, dim3(control_groups), dim3(CONTROL_THREADS), 0,
+                               rs, c->fronts.as<Front>(), c->counts.as<int32_t>(), F, dctl,
+                               max_cold, max_warm, wf, c->vieta.as<double4>(),
+                               c->reals_d.as<Real>(), c->etab.as<double2>(), fronts_per_group);
+            hipLaunchKernelGGL(control_end, dim3(1), dim3(64), 0, rs, dctl, wf);
             parity ^= 1;
         }
         MLCC_HIP(hipGetLastError());
         MLCC_HIP(hipMemcpyAsync(pin_ctl(slot), dctl, sizeof(Control), hipMemcpyDeviceToHost,
-                                c->stream));
+                                rs));
         MLCC_HIP(hipMemcpyAsync(pin_flags(slot), c->workflags.as<int32_t>() + slot * MAX_BATCH,
-                                g * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-        MLCC_HIP(hipEventRecord(done_ev[slot], c->stream));
+                                g * sizeof(int32_t), hipMemcpyDeviceToHost, rs));
+        return MLCC_OK;
+    };
+    auto enqueue_batch = [&](int slot, int g) -> mlcc_status {
+        if (gexec[slot]) {
+            MLCC_HIP(hipGraphLaunch(gexec[slot], rs));
+            g = graph_len;
+        } else {
+            MLCC_TRY(enqueue_rounds(slot, g, p->timing != 0));
+        }
+        MLCC_HIP(hipEventRecord(done_ev[slot], rs));
         batch_len[slot] = g;
         launched += g;
         return MLCC_OK;
+    };
+    // Without per-kernel timing the rounds of a batch are captured once per
+    // slot into a hipGraph (an even number of rounds, so the ping-pong buffers
+    // line up) and replayed until the fronts are done.
+    auto build_graphs = [&](int g) -> mlcc_status {
+        g = std::max(2, g & ~1);
+        for (int slot = 0; slot < 2; ++slot) {
+            hipGraph_t graph = nullptr;
+            const int saved = parity;
+            parity = 0;
+            MLCC_HIP(hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal));
+            mlcc_status s = enqueue_rounds(slot, g, false);
+            hipError_t e = hipStreamEndCapture(rs, &graph);
+            parity = saved;
+            if (s != MLCC_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return s;
+            }
+            MLCC_HIP(e);
+            e = hipGraphInstantiate(&gexec[slot], graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            MLCC_HIP(e);
+        }
+        graph_len = g;
+        return MLCC_OK;
+    };
+    auto harvest = [&](int slot) {
+        // live bits per round: 1 << phase of every front that was active
+        const int kind_phase[KINDS] = {PH_F64, PH_F32, PH_POLISH};
+        for (int i = 0; i < batch_len[slot]; ++i) {
+            const int32_t live = pin_flags(slot)[i];
+            for (int kind = 0; kind < KINDS; ++kind) {
+                if (!(live & (1 << kind_phase[kind]))) continue;
+                kind_launches[kind] += 1;
+                if (p->timing && !gexec[slot]) {
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, ev(slot, i, kind, 0), ev(slot, i, kind, 1));
+                    kind_ms[kind] += ms;
+                }
+            }
+        }
     };
 
     mlcc_status st = MLCC_OK;
@@ -593,6 +1237,11 @@ mlcc_status find_critical_curves_fp64(Ctx *c, const mlcc_cc_params *p, double *r
     while (st == MLCC_OK) {
         // keep one batch queued behind the one being polled
         const int next = slot ^ 1;
+        if (use_graphs && !gexec[0] && polls == 1 && parity == 0) {
+            // G now holds the batch length that takes ~4 ms
+            st = build_graphs(std::min(G, 64));
+            if (st != MLCC_OK) break;
+        }
         st = enqueue_batch(next, G);
         if (st != MLCC_OK) break;
         if (hipEventSynchronize(done_ev[slot]) != hipSuccess) {
@@ -601,31 +1250,18 @@ mlcc_status find_critical_curves_fp64(Ctx *c, const mlcc_cc_params *p, double *r
         }
         ++polls;
         const Control h = *pin_ctl(slot);
-        if (p->timing) {
-            for (int i = 0; i < batch_len[slot]; ++i) {
-                if (!pin_flags(slot)[i]) continue;
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, evs[(slot * MAX_BATCH + i) * 2],
-                                          evs[(slot * MAX_BATCH + i) * 2 + 1]);
-                sweep_ms += ms;
-            }
-        }
+        harvest(slot);
         if (h.active_fronts == 0) {
             // drain the batch queued ahead (it found nothing to do)
-            MLCC_HIP(hipEventSynchronize(done_ev[next]));
-            if (p->timing) {
-                for (int i = 0; i < batch_len[next]; ++i) {
-                    if (!pin_flags(next)[i]) continue;
-                    float ms = 0.f;
-                    (void)hipEventElapsedTime(&ms, evs[(next * MAX_BATCH + i) * 2],
-                                              evs[(next * MAX_BATCH + i) * 2 + 1]);
-                    sweep_ms += ms;
-                }
+            if (hipEventSynchronize(done_ev[next]) != hipSuccess) {
+                st = fail(MLCC_ERR_HIP, "sweep batch failed");
+                break;
             }
+            harvest(next);
             break;
         }
         if (launched > launch_cap) {
-            st = fail(MLCC_ERR_HIP, "root finder exceeded %lld launches", (long long)launch_cap);
+            st = fail(MLCC_ERR_HIP, "root finder exceeded %lld rounds", (long long)launch_cap);
             break;
         }
         // poll roughly every 4 ms of GPU work
@@ -634,18 +1270,19 @@ mlcc_status find_critical_curves_fp64(Ctx *c, const mlcc_cc_params *p, double *r
         t_last = now;
         const double per = dt / std::max(1, batch_len[slot]);
         G = (int)std::min<double>(MAX_BATCH, std::max<double>(2.0, 4.0 / std::max(per, 1e-3)));
+        G &= ~1;   // even batches keep the ping-pong parity at 0 between batches
         slot = next;
     }
-    (void)hipStreamSynchronize(c->stream);
-    (void)hipEventDestroy(done_ev[0]);
-    (void)hipEventDestroy(done_ev[1]);
+    (void)hipStreamSynchronize(rs);
     cleanup();
     if (st != MLCC_OK) return st;
 
     Control h{};
-    MLCC_HIP(hipMemcpy(&h, dctl, sizeof h, hipMemcpyDeviceToHost));
+    MLCC_HIP(hipMemcpyAsync(&h, dctl, sizeof h, hipMemcpyDeviceToHost, c->stream));
     std::vector<Front> fin(F);
-    MLCC_HIP(hipMemcpy(fin.data(), c->fronts.p, F * sizeof(Front), hipMemcpyDeviceToHost));
+    MLCC_HIP(hipMemcpyAsync(fin.data(), c->fronts.p, F * sizeof(Front), hipMemcpyDeviceToHost,
+                            c->stream));
+    MLCC_HIP(hipStreamSynchronize(c->stream));
 
     mlcc_status result = MLCC_OK;
     double maxdist = 0.0;
@@ -654,39 +1291,75 @@ mlcc_status find_critical_curves_fp64(Ctx *c, const mlcc_cc_params *p, double *r
                       h.failed_rows, (long long)h.unconverged);
     } else {
         // join subchains: pair each duplicate boundary row with the stored
-        // copy, compose the pairings into global labels, relabel the blocks
+        // copy, compose the pairings into global labels, relabel the blocks;
+        // then pair row m with row 0 for chain_next
+        std::vector<PairJob> jobs;
+        int64_t perm_total = 0;
+        for (int r = 0; r < n_real; ++r) perm_total += (int64_t)S * rd[r].n_r;
+        MLCC_TRY(c->perm.reserve((size_t)std::max<int64_t>(perm_total, 1) * sizeof(int32_t)));
+        int32_t *perm = c->perm.as<int32_t>();
+        std::vector<int64_t> perm_off(n_real);
+        int64_t po = 0;
+        for (int r = 0; r < n_real; ++r) {
+            perm_off[r] = po;
+            const int64_t n_r = rd[r].n_r;
+            double *ore = roots_re + rd[r].out_off, *oim = roots_im + rd[r].out_off;
+            for (int s = 1; s < S; ++s) {
+                PairJob j{};
+                j.a2 = c->bnd.as<double2>() + rd[r].bnd_off + (int64_t)(s - 1) * n_r;
+                j.b_re = ore + s * L * n_r;
+                j.b_im = oim + s * L * n_r;
+                j.perm = perm + po + s * n_r;
+                j.n = n_r;
+                jobs.push_back(j);
+            }
+            po += (int64_t)S * n_r;
+        }
+        double md = 0.0;
+        MLCC_TRY(pair_all(c, jobs, 1e-6, &md));
+        maxdist = std::max(maxdist, md);
         if (S > 1) {
-            MLCC_TRY(c->perm.reserve((size_t)(S + 1) * n_r * sizeof(int32_t)));
-            int32_t *perm = c->perm.as<int32_t>();
-            for (int s = 1; s < S; ++s) {
-                double md = 0.0;
-                const int64_t lo = s * L;
-                MLCC_TRY(pair_rows(c, n_r, c->bnd.as<double2>() + (int64_t)(s - 1) * n_r,
-                                   roots_re + lo * n_r, roots_im + lo * n_r,
-                                   perm + (int64_t)s * n_r, 1e-6, &md));
-                maxdist = std::max(maxdist, md);
+            std::vector<int32_t> hp((size_t)perm_total), lab((size_t)perm_total);
+            MLCC_HIP(hipMemcpyAsync(hp.data(), perm, (size_t)perm_total * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, c->stream));
+            MLCC_HIP(hipStreamSynchronize(c->stream));
+            for (int r = 0; r < n_real; ++r) {
+                const int64_t n_r = rd[r].n_r, b = perm_off[r];
+                for (int64_t k = 0; k < n_r; ++k) lab[b + k] = (int32_t)k;
+                for (int s = 1; s < S; ++s)
+                    for (int64_t k = 0; k < n_r; ++k)
+                        lab[b + s * n_r + k] = lab[b + (s - 1) * n_r + hp[b + s * n_r + k]];
             }
-            std::vector<int32_t> hp((size_t)S * n_r), lab((size_t)S * n_r);
-            MLCC_HIP(hipMemcpy(hp.data(), perm, (size_t)S * n_r * sizeof(int32_t),
-                               hipMemcpyDeviceToHost));
-            for (int64_t k = 0; k < n_r; ++k) lab[k] = (int32_t)k;
-            for (int s = 1; s < S; ++s)
-                for (int64_t k = 0; k < n_r; ++k)
-                    lab[s * n_r + k] = lab[(s - 1) * n_r + hp[s * n_r + k]];
-            MLCC_HIP(hipMemcpy(perm, lab.data(), (size_t)S * n_r * sizeof(int32_t),
-                               hipMemcpyHostToDevice));
-            for (int s = 1; s < S; ++s) {
-                MLCC_TRY(relabel_rows(c, roots_re, roots_im, n_r, s * L + 1, (s + 1) * L + 1,
-                                      perm + (int64_t)s * n_r));
-                if (caus_re)
-                    MLCC_TRY(relabel_rows(c, caus_re, caus_im, n_r, s * L + 1, (s + 1) * L + 1,
-                                          perm + (int64_t)s * n_r));
+            MLCC_HIP(hipMemcpyAsync(perm, lab.data(), (size_t)perm_total * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, c->stream));
+            for (int r = 0; r < n_real; ++r) {
+                const int64_t n_r = rd[r].n_r;
+                for (int s = 1; s < S; ++s) {
+                    const int32_t *lb = perm + perm_off[r] + s * n_r;
+                    MLCC_TRY(relabel_rows(c, roots_re + rd[r].out_off, roots_im + rd[r].out_off,
+                                          n_r, s * L + 1, (s + 1) * L + 1, lb));
+                    if (caus_re)
+                        MLCC_TRY(relabel_rows(c, caus_re + rd[r].out_off, caus_im + rd[r].out_off,
+                                              n_r, s * L + 1, (s + 1) * L + 1, lb));
+                }
             }
+            MLCC_HIP(hipStreamSynchronize(c->stream));
         }
         if (chain_next) {
-            double md = 0.0;
-            MLCC_TRY(pair_rows_soa(c, n_r, roots_re + m * n_r, roots_im + m * n_r, roots_re,
-                                   roots_im, chain_next, 1e-6, &md));
+            jobs.clear();
+            for (int r = 0; r < n_real; ++r) {
+                const int64_t n_r = rd[r].n_r;
+                double *ore = roots_re + rd[r].out_off, *oim = roots_im + rd[r].out_off;
+                PairJob j{};
+                j.a_re = ore + m * n_r;
+                j.a_im = oim + m * n_r;
+                j.b_re = ore;
+                j.b_im = oim;
+                j.perm = chain_next + 2 * c->reals[r].star_off;
+                j.n = n_r;
+                jobs.push_back(j);
+            }
+            MLCC_TRY(pair_all(c, jobs, 1e-6, &md));
             maxdist = std::max(maxdist, md);
         }
         MLCC_HIP(hipStreamSynchronize(c->stream));
@@ -696,8 +1369,11 @@ mlcc_status find_critical_curves_fp64(Ctx *c, const mlcc_cc_params *p, double *r
         *stats = mlcc_cc_stats{};
         stats->sweeps = h.live_sweeps;
         stats->root_updates = (int64_t)h.updates;
+        stats->root_updates_f32 = (int64_t)h.updates_f32;
+        stats->polish_updates = (int64_t)h.polish_updates;
         stats->unconverged = h.unconverged;
         stats->rows_capped = h.failed_rows;
+        stats->rows_fallback = h.rows_fallback;
         stats->n_subchains = S;
         int32_t mw = 0, mc = 0;
         for (const Front &x : fin) {
@@ -708,9 +1384,19 @@ mlcc_status find_critical_curves_fp64(Ctx *c, const mlcc_cc_params *p, double *r
         stats->cold_sweeps = mc;
         stats->polls = polls;
         stats->match_maxdist = maxdist;
-        stats->sweep_ms = sweep_ms;
-        stats->algorithmic_flop =
-            (double)h.updates * (29.0 * (double)n + 10.0 * (double)(n_r - 1));
+        stats->sweep_ms = kind_ms[0];
+        stats->sweep_f32_ms = kind_ms[1];
+        stats->polish_ms = kind_ms[2];
+        stats->sweep_launches = kind_launches[0];
+        stats->sweep_f32_launches = kind_launches[1];
+        stats->polish_launches = kind_launches[2];
+        // algorithmic FLOP of one update of a root of a field of N stars:
+        // 29 N + 10 (2N - 1) (Aberth sweep), 36 N (polish); the device counts
+        // updates and updates x N, which gives the sums over mixed fields
+        stats->algorithmic_flop = 49.0 * (double)h.star_updates - 10.0 * (double)h.updates;
+        stats->algorithmic_flop_f32 =
+            49.0 * (double)h.star_updates_f32 - 10.0 * (double)h.updates_f32;
+        stats->algorithmic_flop_polish = 36.0 * (double)h.star_updates_polish;
     }
     return result;
 }

@@ -143,8 +143,10 @@ void mlcc_destroy(mlcc_ctx *ctx)
     (void)hipStreamSynchronize(c.stream);
     DevBuf *bufs[] = {&c.stars, &c.mass, &c.stars4, &c.iter[0], &c.iter[1], &c.flagrow, &c.fronts,
                       &c.counts, &c.control, &c.etab, &c.bnd, &c.perm, &c.match_aux,
-                      &c.relabel, &c.workflags, &c.diff, &c.err, &c.edt_col};
+                      &c.relabel, &c.workflags, &c.vieta, &c.reals_d, &c.bmap, &c.diff,
+                      &c.err, &c.edt_col};
     for (DevBuf *b : bufs) b->release();
+    if (c.own_stream) (void)hipStreamDestroy(c.own_stream);
     if (c.pinned) (void)hipHostFree(c.pinned);
     delete ctx;
 }
@@ -170,75 +172,130 @@ void mlcc_cc_params_default(mlcc_cc_params *p, int64_t m_steps)
     p->timing = 0;
 }
 
-mlcc_status mlcc_set_lenses(mlcc_ctx *ctx, int64_t n, const double *x, const double *y,
-                            const double *m, double kappa_s, double gamma)
+// Loads one or several star fields (concatenated; field r holds stars
+// [off[r], off[r+1])) and the per-field sums the root finder checks rows
+// against.
+static mlcc_status load_fields(Ctx &c, int32_t n_fields, const int64_t *off, const double *x,
+                               const double *y, const double *m, const double *kappa_s,
+                               const double *gamma, bool batched)
 {
-    if (!ctx) return fail(MLCC_ERR_INVALID, "ctx is NULL");
-    Ctx &c = ctx->impl;
     MLCC_TRY(use_device(&c));
-    if (n < 1) return fail(MLCC_ERR_INVALID, "need at least one star (n=%lld)", (long long)n);
+    if (n_fields < 1 || n_fields > 65536)
+        return fail(MLCC_ERR_INVALID, "need 1..65536 fields (got %d)", n_fields);
+    if (off[0] != 0) return fail(MLCC_ERR_INVALID, "star_offsets[0] must be 0");
+    for (int32_t r = 0; r < n_fields; ++r)
+        if (off[r + 1] - off[r] < 1)
+            return fail(MLCC_ERR_INVALID, "field %d: need at least one star", r);
+    const int64_t n = off[n_fields];
     if (n > (int64_t)1 << 28) return fail(MLCC_ERR_INVALID, "too many stars (%lld)", (long long)n);
     MLCC_TRY(check_device_ptr(&c, x, "x"));
     MLCC_TRY(check_device_ptr(&c, y, "y"));
     MLCC_TRY(check_device_ptr(&c, m, "m"));
-    if (!std::isfinite(kappa_s) || !std::isfinite(gamma))
-        return fail(MLCC_ERR_INVALID, "kappa_s and gamma must be finite");
-    if (std::fabs(gamma) == std::fabs(1.0 - kappa_s))
-        return fail(MLCC_ERR_INVALID,
-                    "|gamma| == |1 - kappa_s|: gamma - (1-kappa_s) e^{-i phi} vanishes on the "
-                    "phase circle");
+    for (int32_t r = 0; r < n_fields; ++r) {
+        if (!std::isfinite(kappa_s[r]) || !std::isfinite(gamma[r]))
+            return fail(MLCC_ERR_INVALID, "field %d: kappa_s and gamma must be finite", r);
+        if (std::fabs(gamma[r]) == std::fabs(1.0 - kappa_s[r]))
+            return fail(MLCC_ERR_INVALID,
+                        "field %d: |gamma| == |1 - kappa_s|: gamma - (1-kappa_s) e^{-i phi} "
+                        "vanishes on the phase circle", r);
+    }
     std::vector<double> hx(n), hy(n), hm(n);
     MLCC_HIP(hipMemcpyAsync(hx.data(), x, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
     MLCC_HIP(hipMemcpyAsync(hy.data(), y, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
     MLCC_HIP(hipMemcpyAsync(hm.data(), m, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
     MLCC_HIP(hipStreamSynchronize(c.stream));
-    bool equal = true;
-    for (int64_t i = 0; i < n; ++i) {
-        if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || !std::isfinite(hm[i]) || !(hm[i] > 0))
-            return fail(MLCC_ERR_INVALID, "star %lld: non-finite position or mass <= 0",
-                        (long long)i);
-        if (hm[i] != hm[0]) equal = false;
-    }
-    {
-        std::vector<int64_t> idx(n);
-        for (int64_t i = 0; i < n; ++i) idx[i] = i;
+    std::vector<RealHost> reals(n_fields);
+    for (int32_t r = 0; r < n_fields; ++r) {
+        const int64_t i0 = off[r], i1 = off[r + 1];
+        RealHost &h = reals[r];
+        h.star_off = i0;
+        h.n = i1 - i0;
+        h.kappa_s = kappa_s[r];
+        h.gamma = gamma[r];
+        h.m0 = hm[i0];
+        h.equal = true;
+        for (int64_t i = i0; i < i1; ++i) {
+            if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || !std::isfinite(hm[i]) ||
+                !(hm[i] > 0))
+                return fail(MLCC_ERR_INVALID, "star %lld: non-finite position or mass <= 0",
+                            (long long)i);
+            if (hm[i] != hm[i0]) h.equal = false;
+        }
+        std::vector<int64_t> idx(h.n);
+        for (int64_t i = 0; i < h.n; ++i) idx[i] = i0 + i;
         std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
             return hx[a] < hx[b] || (hx[a] == hx[b] && hy[a] < hy[b]);
         });
-        for (int64_t i = 1; i < n; ++i)
+        for (int64_t i = 1; i < h.n; ++i)
             if (hx[idx[i]] == hx[idx[i - 1]] && hy[idx[i]] == hy[idx[i - 1]])
                 return fail(MLCC_ERR_INVALID, "stars %lld and %lld share a position",
                             (long long)idx[i - 1], (long long)idx[i]);
+        // row identities of the root finder: sum z_i, sum z_i^2, total mass
+        for (int64_t i = i0; i < i1; ++i) {
+            h.sum_z.x += hx[i];
+            h.sum_z.y += hy[i];
+            h.sum_z2.x += hx[i] * hx[i] - hy[i] * hy[i];
+            h.sum_z2.y += 2.0 * hx[i] * hy[i];
+            const double r2 = hx[i] * hx[i] + hy[i] * hy[i];
+            h.sum_abs_z += std::sqrt(r2);
+            h.sum_abs_z2 += r2;
+            h.max_abs_z = std::max(h.max_abs_z, std::sqrt(r2));
+            h.mass_total += hm[i];
+        }
     }
-    std::vector<double> xy(2 * n);
+    std::vector<double> xy(2 * n), xym(4 * n);
     for (int64_t i = 0; i < n; ++i) {
         xy[2 * i] = hx[i];
         xy[2 * i + 1] = hy[i];
-    }
-    std::vector<double> xym(4 * n);
-    for (int64_t i = 0; i < n; ++i) {
         xym[4 * i] = hx[i];
         xym[4 * i + 1] = hy[i];
         xym[4 * i + 2] = hm[i];
         xym[4 * i + 3] = 0.0;
     }
     MLCC_TRY(c.stars4.reserve(4 * n * sizeof(double)));
-    MLCC_HIP(hipMemcpyAsync(c.stars4.p, xym.data(), 4 * n * sizeof(double), hipMemcpyHostToDevice,
-                            c.stream));
     MLCC_TRY(c.stars.reserve(2 * n * sizeof(double)));
     MLCC_TRY(c.mass.reserve(n * sizeof(double)));
+    MLCC_HIP(hipMemcpyAsync(c.stars4.p, xym.data(), 4 * n * sizeof(double), hipMemcpyHostToDevice,
+                            c.stream));
     MLCC_HIP(hipMemcpyAsync(c.stars.p, xy.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice,
                             c.stream));
     MLCC_HIP(hipMemcpyAsync(c.mass.p, hm.data(), n * sizeof(double), hipMemcpyHostToDevice,
                             c.stream));
     MLCC_HIP(hipStreamSynchronize(c.stream));
+    c.reals = std::move(reals);
+    c.batched = batched;
     c.n = n;
-    c.kappa_s = kappa_s;
-    c.gamma = gamma;
-    c.equal_mass = equal;
+    c.kappa_s = kappa_s[0];
+    c.gamma = gamma[0];
+    c.equal_mass = c.reals[0].equal && !batched;
     c.mass0 = hm[0];
     clear_error();
     return MLCC_OK;
+}
+
+mlcc_status mlcc_set_lenses(mlcc_ctx *ctx, int64_t n, const double *x, const double *y,
+                            const double *m, double kappa_s, double gamma)
+{
+    if (!ctx) return fail(MLCC_ERR_INVALID, "ctx is NULL");
+    if (n < 1) return fail(MLCC_ERR_INVALID, "need at least one star (n=%lld)", (long long)n);
+    if (n > (int64_t)1 << 28) return fail(MLCC_ERR_INVALID, "too many stars (%lld)", (long long)n);
+    const int64_t off[2] = {0, n};
+    return load_fields(ctx->impl, 1, off, x, y, m, &kappa_s, &gamma, false);
+}
+
+mlcc_status mlcc_set_lenses_batched(mlcc_ctx *ctx, int32_t n_fields, const int64_t *star_offsets,
+                                    const double *x, const double *y, const double *m,
+                                    const double *kappa_s, const double *gamma)
+{
+    if (!ctx) return fail(MLCC_ERR_INVALID, "ctx is NULL");
+    if (!star_offsets || !kappa_s || !gamma)
+        return fail(MLCC_ERR_INVALID, "star_offsets, kappa_s and gamma must be host arrays");
+    if (n_fields < 1 || n_fields > 65536)
+        return fail(MLCC_ERR_INVALID, "need 1..65536 fields (got %d)", n_fields);
+    for (int32_t r = 0; r < n_fields; ++r)
+        if (star_offsets[r + 1] - star_offsets[r] < 1 || star_offsets[r + 1] > ((int64_t)1 << 28))
+            return fail(MLCC_ERR_INVALID, "star_offsets must start at 0 and strictly increase");
+    return load_fields(ctx->impl, n_fields, star_offsets, x, y, m, kappa_s, gamma, true);
 }
 
 mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *params,
@@ -254,7 +311,7 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
     if (p.m_steps < 2 || (p.m_steps & 1))
         return fail(MLCC_ERR_INVALID, "m_steps must be even and >= 2 (got %lld)",
                     (long long)p.m_steps);
-    if (p.m_steps > (int64_t)1 << 30) return fail(MLCC_ERR_INVALID, "m_steps too large");
+    if (p.m_steps > (int64_t)1 << 28) return fail(MLCC_ERR_INVALID, "m_steps too large");
     if (p.n_subchains < 0 || (p.n_subchains > 0 && (p.m_steps / 2) % p.n_subchains))
         return fail(MLCC_ERR_INVALID, "n_subchains=%d must divide m_steps/2=%lld",
                     p.n_subchains, (long long)(p.m_steps / 2));
@@ -264,7 +321,7 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
         return fail(MLCC_ERR_INVALID, "tol_inv_mu must be >= 0 and finite");
     if (p.max_iter_cold < 0 || p.max_iter_warm < 0)
         return fail(MLCC_ERR_INVALID, "iteration caps must be >= 0");
-    if (p.precision != MLCC_FP64)
+    if (p.precision != MLCC_FP64 && p.precision != MLCC_MIXED)
         return fail(MLCC_ERR_INVALID, "unknown precision %d", p.precision);
     MLCC_TRY(check_device_ptr(&c, roots_re, "roots_re"));
     MLCC_TRY(check_device_ptr(&c, roots_im, "roots_im"));
@@ -276,7 +333,7 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
     }
     if (chain_next) MLCC_TRY(check_device_ptr(&c, chain_next, "chain_next"));
     clear_error();
-    return find_critical_curves_fp64(&c, &p, roots_re, roots_im, caustics_re, caustics_im,
+    return find_critical_curves_impl(&c, &p, roots_re, roots_im, caustics_re, caustics_im,
                                      chain_next, stats);
 }
 
@@ -287,6 +344,8 @@ mlcc_status mlcc_map_caustics(mlcc_ctx *ctx, int64_t count, const double *z_re,
     Ctx &c = ctx->impl;
     MLCC_TRY(use_device(&c));
     if (c.n < 1) return fail(MLCC_ERR_STATE, "call mlcc_set_lenses first");
+    if (c.batched)
+        return fail(MLCC_ERR_STATE, "mlcc_map_caustics needs a single field (mlcc_set_lenses)");
     if (count < 0) return fail(MLCC_ERR_INVALID, "count < 0");
     if (count == 0) return MLCC_OK;
     MLCC_TRY(check_device_ptr(&c, z_re, "z_re"));

@@ -5,7 +5,9 @@
 // other copy through wave-uniform scalar loads), the pairing is checked to be
 // one-to-one and tight, and blocks of rows are relabelled through it.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "mlcc_internal.h"
 
@@ -63,52 +65,55 @@ __global__ void check_hits(int32_t n, const int32_t *__restrict__ hits, PairAux 
     if (k < n && hits[k] != 1) atomicOr(&aux->bad, 1);
 }
 
-static mlcc_status pair_impl(Ctx *c, int64_t n, const double2 *a2, const double *a_re,
-                             const double *a_im, const double *b_re, const double *b_im,
-                             int32_t *perm, double tol, double *maxdist)
+mlcc_status pair_all(Ctx *c, const std::vector<PairJob> &jobs, double tol, double *maxdist)
 {
-    if (n > 0x7fffffff) return fail(MLCC_ERR_INVALID, "row too long to pair");
-    MLCC_TRY(c->match_aux.reserve(sizeof(PairAux) + (size_t)n * sizeof(int32_t)));
+    if (maxdist) *maxdist = 0.0;
+    if (jobs.empty()) return MLCC_OK;
+    int64_t total = 0;
+    for (const PairJob &j : jobs) {
+        if (j.n > 0x7fffffff) return fail(MLCC_ERR_INVALID, "row too long to pair");
+        total += j.n;
+    }
+    const size_t aux_bytes = jobs.size() * sizeof(PairAux);
+    MLCC_TRY(c->match_aux.reserve(aux_bytes + (size_t)total * sizeof(int32_t)));
     PairAux *aux = c->match_aux.as<PairAux>();
-    int32_t *hits = reinterpret_cast<int32_t *>(aux + 1);
-    MLCC_HIP(hipMemsetAsync(c->match_aux.p, 0, sizeof(PairAux) + (size_t)n * sizeof(int32_t),
+    int32_t *hits = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(c->match_aux.p) + aux_bytes);
+    MLCC_HIP(hipMemsetAsync(c->match_aux.p, 0, aux_bytes + (size_t)total * sizeof(int32_t),
                             c->stream));
-    const unsigned blocks = (unsigned)ceil_div(n, 64);
-    if (a2)
-        hipLaunchKernelGGL(nearest_kernel<true>, dim3(blocks), dim3(64), 0, c->stream, (int32_t)n,
-                           a2, nullptr, nullptr, b_re, b_im, perm, hits, aux);
-    else
-        hipLaunchKernelGGL(nearest_kernel<false>, dim3(blocks), dim3(64), 0, c->stream,
-                           (int32_t)n, nullptr, a_re, a_im, b_re, b_im, perm, hits, aux);
-    hipLaunchKernelGGL(check_hits, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream,
-                       (int32_t)n, hits, aux);
+    int64_t off = 0;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        const PairJob &j = jobs[i];
+        const unsigned blocks = (unsigned)ceil_div(j.n, 64);
+        if (j.a2)
+            hipLaunchKernelGGL(nearest_kernel<true>, dim3(blocks), dim3(64), 0, c->stream,
+                               (int32_t)j.n, j.a2, nullptr, nullptr, j.b_re, j.b_im, j.perm,
+                               hits + off, aux + i);
+        else
+            hipLaunchKernelGGL(nearest_kernel<false>, dim3(blocks), dim3(64), 0, c->stream,
+                               (int32_t)j.n, nullptr, j.a_re, j.a_im, j.b_re, j.b_im, j.perm,
+                               hits + off, aux + i);
+        hipLaunchKernelGGL(check_hits, dim3((unsigned)ceil_div(j.n, 256)), dim3(256), 0,
+                           c->stream, (int32_t)j.n, hits + off, aux + i);
+        off += j.n;
+    }
     MLCC_HIP(hipGetLastError());
-    PairAux h;
-    MLCC_HIP(hipMemcpyAsync(&h, aux, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    std::vector<PairAux> h(jobs.size());
+    MLCC_HIP(hipMemcpyAsync(h.data(), aux, aux_bytes, hipMemcpyDeviceToHost, c->stream));
     MLCC_HIP(hipStreamSynchronize(c->stream));
-    double d2;
-    memcpy(&d2, &h.maxbits, sizeof d2);
-    const double md = std::sqrt(d2);
+    double md = 0.0;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        double d2;
+        memcpy(&d2, &h[i].maxbits, sizeof d2);
+        const double d = std::sqrt(d2);
+        md = std::max(md, d);
+        if (h[i].bad)
+            return fail(MLCC_ERR_MATCH, "duplicate rows of %lld roots do not pair one-to-one",
+                        (long long)jobs[i].n);
+        if (!(d <= tol))
+            return fail(MLCC_ERR_MATCH, "duplicate rows pair at distance %.3g > %.3g", d, tol);
+    }
     if (maxdist) *maxdist = md;
-    if (h.bad)
-        return fail(MLCC_ERR_MATCH, "duplicate rows of %lld roots do not pair one-to-one",
-                    (long long)n);
-    if (!(md <= tol))
-        return fail(MLCC_ERR_MATCH, "duplicate rows pair at distance %.3g > %.3g", md, tol);
     return MLCC_OK;
-}
-
-mlcc_status pair_rows(Ctx *c, int64_t n, const double2 *a, const double *b_re,
-                      const double *b_im, int32_t *perm, double tol, double *maxdist)
-{
-    return pair_impl(c, n, a, nullptr, nullptr, b_re, b_im, perm, tol, maxdist);
-}
-
-mlcc_status pair_rows_soa(Ctx *c, int64_t n, const double *a_re, const double *a_im,
-                          const double *b_re, const double *b_im, int32_t *perm, double tol,
-                          double *maxdist)
-{
-    return pair_impl(c, n, nullptr, a_re, a_im, b_re, b_im, perm, tol, maxdist);
 }
 
 // scratch[b][label[k]] = src[b][k] for nb rows

@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "mlcc.h"
 
@@ -51,32 +52,72 @@ struct Front {
     int32_t dir;      // -1 toward row 0, +1 toward row m, 0 = cold start at the centre
     int32_t end_row;  // last row this front solves (inclusive)
     int32_t state;    // FRONT_IDLE / FRONT_ACTIVE / FRONT_DONE / FRONT_FAILED
-    int32_t sweeps;   // sweeps spent on the current row
-    int32_t src;      // front whose iterate this front reads on its next sweep
+    int32_t sweeps;   // FP64 sweeps spent on the current row
+    int32_t src;      // front whose iterate this front reads on its next pass
     int32_t partner;  // cold start: front that takes over the other direction
     int32_t bnd_slot; // >= 0: its end row is a duplicate boundary row, kept here
     int32_t lo, hi;   // rows of the subchain
-    int32_t max_warm; // most sweeps a warm row of this front needed
+    int32_t max_warm; // most FP64 sweeps a warm row of this front needed
     int32_t cold;     // sweeps its cold start needed
+    int32_t phase;    // PH_F64 / PH_F32 / PH_POLISH: what the next pass does
+    int32_t mode;     // phase a new warm row starts in
+    int32_t stamp;    // flag value meaning "converged on this row": 4 row + generation
+    int32_t passes;   // polish passes spent on the current row
+    int32_t real;     // realisation (star field) this front belongs to
+    int32_t blk0;     // first block of this front in the launch grid
+    int64_t it_off;   // first element of its roots in the iterate and flag arrays
+};
+
+// One star field of a (possibly batched) root-finder call, as the kernels
+// see it.
+struct Real {
+    int64_t star_off;   // first star in the concatenated star arrays
+    int64_t out_off;    // first element of its (m+1) x n_r output block
+    int64_t bnd_off;    // first element of its duplicate boundary rows
+    int32_t n_stars, n_r;
+    double m0;          // the common mass (equal-mass kernels)
+    double gamma, a, a1;   // shear, 1 - kappa_s, |1 - kappa_s|
+    double sz_r, sz_i, sz2_r, sz2_i, M;   // sum z_i, sum z_i^2, sum m_i (row identities)
+    double tol1, tol2;  // tolerances of the two row identities
+};
+
+// Host-side description of one star field.
+struct RealHost {
+    int64_t star_off = 0, n = 0;
+    double kappa_s = 0, gamma = 0, m0 = 1;
+    bool equal = false;
+    double2 sum_z{0, 0}, sum_z2{0, 0};
+    double sum_abs_z = 0, sum_abs_z2 = 0, max_abs_z = 0, mass_total = 0;
 };
 enum { FRONT_IDLE = 0, FRONT_ACTIVE = 1, FRONT_DONE = 2, FRONT_FAILED = 3 };
+enum { PH_F64 = 0, PH_F32 = 1, PH_POLISH = 2 };
 
 // Device-side totals of the root finder.
 struct Control {
-    int32_t active_fronts;      // fronts still IDLE or ACTIVE
+    int32_t active_fronts;            // fronts still IDLE or ACTIVE
     int32_t failed_rows;
     int64_t unconverged;
-    unsigned long long updates; // root updates
-    int64_t live_sweeps;        // sweep launches that found an active front
+    unsigned long long updates;       // FP64 Aberth root updates
+    unsigned long long updates_f32;   // FP32 Aberth root updates
+    unsigned long long polish_updates;
+    int64_t rows_fallback;            // rows that fell back to FP64 sweeps
+    int64_t live_sweeps;              // rounds that found an active front
+    unsigned long long star_updates;  // sum over FP64 updates of the field's star count
+    unsigned long long star_updates_f32;
+    unsigned long long star_updates_polish;
 };
 
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;   // rounds of the root finder when `stream` is null
 
-    // lenses
-    int64_t n = 0;
-    double kappa_s = 0.0, gamma = 0.0;
+    // lenses: one field (set_lenses) or a batch (set_lenses_batched), stars
+    // concatenated
+    bool batched = false;
+    std::vector<RealHost> reals;
+    int64_t n = 0;      // total stars
+    double kappa_s = 0.0, gamma = 0.0;  // the single field's macro-model
     bool equal_mass = false;
     double mass0 = 1.0; // the common mass when equal_mass
     DevBuf stars;  // double2[n]: (x, y)
@@ -94,7 +135,10 @@ struct Ctx {
     DevBuf perm;      // int32[(S + 1) * n_r]: pairings and global labels
     DevBuf match_aux; // matching workspace
     DevBuf relabel;   // scratch rows for the in-place relabel
-    DevBuf workflags; // int32[poll batch]: did launch i do work
+    DevBuf workflags; // int32[poll batch]: phases active in round i
+    DevBuf vieta;     // double4[blocks]: per-block row sums (mixed mode)
+    DevBuf reals_d;   // Real[n_real]
+    DevBuf bmap;      // int2[blocks]: (front, block within front)
 
     // crossing / distance workspace
     DevBuf diff;      // int32 per-row difference map
@@ -110,7 +154,7 @@ mlcc_status ensure_pinned(Ctx *c, size_t bytes);
 
 // Entry points implemented per translation unit (argument checks done by the
 // caller in api.hip).
-mlcc_status find_critical_curves_fp64(Ctx *c, const mlcc_cc_params *p, double *roots_re,
+mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *roots_re,
                                       double *roots_im, double *caus_re, double *caus_im,
                                       int32_t *chain_next, mlcc_cc_stats *stats);
 mlcc_status launch_map_caustics(Ctx *c, int64_t count, const double *zr, const double *zi,
@@ -122,14 +166,18 @@ mlcc_status launch_caustic_distances(Ctx *c, const mlcc_grid *g, const int32_t *
                                      double *dist, uint8_t *border_limited);
 
 // Nearest-neighbour pairing of two copies of one root set (chains.hip).
-//   a, b: n points each (double2 interleaved for a, SoA planes for b)
-//   perm[k] = index in b nearest a[k]; returns MLCC_ERR_MATCH when not 1-1 or
-//   when a pair is further apart than tol; *maxdist = largest paired distance.
-mlcc_status pair_rows(Ctx *c, int64_t n, const double2 *a, const double *b_re,
-                      const double *b_im, int32_t *perm, double tol, double *maxdist);
-mlcc_status pair_rows_soa(Ctx *c, int64_t n, const double *a_re, const double *a_im,
-                          const double *b_re, const double *b_im, int32_t *perm, double tol,
-                          double *maxdist);
+// A job pairs n points a (double2 interleaved, or SoA planes) with n points b
+// (SoA planes): perm[k] = index in b nearest a[k].  Jobs are enqueued without
+// waiting; pair_collect checks them all at once and fails with
+// MLCC_ERR_MATCH when a pairing is not one-to-one or a pair is further apart
+// than tol.  *maxdist receives the largest paired distance.
+struct PairJob {
+    const double2 *a2;
+    const double *a_re, *a_im, *b_re, *b_im;
+    int32_t *perm;
+    int64_t n;
+};
+mlcc_status pair_all(Ctx *c, const std::vector<PairJob> &jobs, double tol, double *maxdist);
 // Relabel rows [row0, row1) in place: new[j][label[k]] = old[j][k].
 mlcc_status relabel_rows(Ctx *c, double *re, double *im, int64_t n_r, int64_t row0,
                          int64_t row1, const int32_t *label);

@@ -29,10 +29,11 @@ MLCC_ERR_NOT_CONVERGED = -4
 MLCC_ERR_STATE = -5
 MLCC_ERR_MATCH = -7
 MLCC_FP64 = 0
+MLCC_MIXED = 1
 
 EXPORTED = [
     "mlcc_create", "mlcc_destroy", "mlcc_set_stream", "mlcc_last_error", "mlcc_set_lenses",
-    "mlcc_cc_params_default", "mlcc_find_critical_curves", "mlcc_map_caustics",
+    "mlcc_set_lenses_batched", "mlcc_cc_params_default", "mlcc_find_critical_curves", "mlcc_map_caustics",
     "mlcc_caustic_crossings", "mlcc_caustic_distances",
 ]
 
@@ -47,11 +48,17 @@ class CCParams(ctypes.Structure):
 
 class CCStats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int64), ("root_updates", ctypes.c_int64),
+                ("root_updates_f32", ctypes.c_int64), ("polish_updates", ctypes.c_int64),
                 ("unconverged", ctypes.c_int64), ("rows_capped", ctypes.c_int64),
+                ("rows_fallback", ctypes.c_int64),
                 ("n_subchains", ctypes.c_int32), ("max_row_sweeps", ctypes.c_int32),
                 ("cold_sweeps", ctypes.c_int32), ("polls", ctypes.c_int32),
                 ("match_maxdist", ctypes.c_double), ("sweep_ms", ctypes.c_double),
-                ("algorithmic_flop", ctypes.c_double)]
+                ("sweep_f32_ms", ctypes.c_double), ("polish_ms", ctypes.c_double),
+                ("sweep_launches", ctypes.c_int64), ("sweep_f32_launches", ctypes.c_int64),
+                ("polish_launches", ctypes.c_int64),
+                ("algorithmic_flop", ctypes.c_double), ("algorithmic_flop_f32", ctypes.c_double),
+                ("algorithmic_flop_polish", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -72,6 +79,7 @@ _SIG = {
     "mlcc_set_stream": ([_vp, _vp], ctypes.c_int),
     "mlcc_last_error": ([], ctypes.c_char_p),
     "mlcc_set_lenses": ([_vp, _i64, _vp, _vp, _vp, _d, _d], ctypes.c_int),
+    "mlcc_set_lenses_batched": ([_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "mlcc_cc_params_default": ([ctypes.POINTER(CCParams), _i64], None),
     "mlcc_find_critical_curves": ([_vp, ctypes.POINTER(CCParams), _vp, _vp, _vp, _vp, _vp,
                                    ctypes.POINTER(CCStats)], ctypes.c_int),
@@ -135,6 +143,7 @@ class Context:
                                 _vp(torch.cuda.current_stream(self.device).cuda_stream)))
         self._h = h
         self.n = 0
+        self.star_offsets = None   # set by set_lenses_batched
 
     def close(self):
         if getattr(self, "_h", None):
@@ -158,6 +167,32 @@ class Context:
         _check(_lib.mlcc_set_lenses(self._h, x.numel(), _ptr(x), _ptr(y), _ptr(m),
                                     float(kappa_s), float(gamma)))
         self.n = x.numel()
+        self.star_offsets = None
+
+    def set_lenses_batched(self, star_offsets, x: torch.Tensor, y: torch.Tensor, m: torch.Tensor,
+                           kappa_s, gamma):
+        """Several fields: field r holds stars star_offsets[r]:star_offsets[r+1]
+        of x, y, m; kappa_s and gamma are per field."""
+        for t, w in ((x, "x"), (y, "y"), (m, "m")):
+            _need(t, torch.float64, self.device, w)
+        off = (ctypes.c_int64 * len(star_offsets))(*[int(v) for v in star_offsets])
+        nf = len(star_offsets) - 1
+        if len(kappa_s) != nf or len(gamma) != nf:
+            raise ValueError("kappa_s and gamma need one value per field")
+        if int(star_offsets[-1]) != x.numel():
+            raise ValueError("star_offsets[-1] must equal the number of stars")
+        ks = (ctypes.c_double * nf)(*[float(v) for v in kappa_s])
+        gs = (ctypes.c_double * nf)(*[float(v) for v in gamma])
+        self._stream()
+        _check(_lib.mlcc_set_lenses_batched(self._h, nf, off, _ptr(x), _ptr(y), _ptr(m), ks, gs))
+        self.n = x.numel()
+        self.star_offsets = [int(v) for v in star_offsets]
+
+    def field_blocks(self, m_steps: int):
+        """[(roots offset, chain_next offset, n_r)] of every field in the
+        flat output arrays of a batched find_critical_curves call."""
+        off = self.star_offsets or [0, self.n]
+        return [((m_steps + 1) * 2 * a, 2 * a, 2 * (b - a)) for a, b in zip(off[:-1], off[1:])]
 
     @staticmethod
     def default_params(m_steps: int) -> CCParams:
@@ -169,10 +204,13 @@ class Context:
                              tol_inv_mu: float = 1e-9, max_iter_cold: int = 500,
                              max_iter_warm: int = 100, timing: bool = False,
                              chain_next: bool = True, caustics: bool = False, out=None,
-                             caustics_out=None, raise_on_error: bool = True):
+                             caustics_out=None, raise_on_error: bool = True,
+                             precision: str = "fp64"):
         """Returns (roots_re, roots_im, chain_next, stats, status), or with
         caustics=True (roots_re, roots_im, caus_re, caus_im, chain_next, stats,
-        status); arrays are (m_steps + 1, 2N) float64 device tensors."""
+        status).  One field: arrays are (m_steps + 1, 2N) float64 device
+        tensors.  Several fields: flat tensors of (m_steps + 1) * 2 * (total
+        stars) elements; field_blocks() gives each field's offsets."""
         p = self.default_params(m_steps)
         p.n_subchains = int(n_subchains)
         p.tol_step = float(tol_step)
@@ -180,9 +218,11 @@ class Context:
         p.max_iter_cold = int(max_iter_cold)
         p.max_iter_warm = int(max_iter_warm)
         p.timing = int(bool(timing))
+        p.precision = {"fp64": MLCC_FP64, "mixed": MLCC_MIXED}[precision]
         n_r = 2 * self.n
+        shape = (m_steps + 1, n_r) if self.star_offsets is None else ((m_steps + 1) * n_r,)
         if out is None:
-            rr = torch.empty((m_steps + 1, n_r), dtype=torch.float64, device=self.device)
+            rr = torch.empty(shape, dtype=torch.float64, device=self.device)
             ri = torch.empty_like(rr)
         else:
             rr, ri = out

@@ -53,12 +53,29 @@ def test_params_default_is_the_papers_setting(lib):
     assert p.max_iter_cold > 0 and p.max_iter_warm > 0 and p.precision == 0
 
 
-def test_struct_layouts_match_header():
-    """ctypes mirrors of the header structs have the C sizes."""
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of the header structs have the sizes and field offsets a
+    C compiler gives the header."""
     from paper_2506_02121_amd import mlcc
-    assert ctypes.sizeof(mlcc.CCParams) == 8 + 4 * 4 + 8 + 8 + 4 + 4
-    assert ctypes.sizeof(mlcc.CCStats) == 4 * 8 + 4 * 4 + 3 * 8
-    assert ctypes.sizeof(mlcc.GridC) == 4 * 8 + 2 * 4
+    mirrors = {"mlcc_cc_params": mlcc.CCParams, "mlcc_cc_stats": mlcc.CCStats,
+               "mlcc_grid": mlcc.GridC}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mlcc.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_errors_without_context(lib):

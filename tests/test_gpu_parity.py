@@ -176,6 +176,44 @@ def test_critical_curves_match_oracle(ctx, case):
     print(f"[{name}] max caustic distance (fused) {worst:.3e}", flush=True)
 
 
+MIXED_CASES = [
+    ("tiny_mixed", 10, "equal", 0.3, 0.0, 0.3, 1000, 0),
+    ("n100_mixed", 100, "equal", 0.5, 0.0, 0.3, 400, 4),
+    ("n150_salp_mixed", 150, "salpeter", 0.45, 0.1, 0.2, 400, 10),
+    ("n300_salp_mixed", 300, "salpeter", 0.4, 0.2, 0.45, 600, 6),
+]
+
+
+@pytest.mark.parametrize("case", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_mixed_precision_matches_oracle(ctx, case):
+    """FP32 bulk sweeps + FP64 Newton polish: roots and caustics within the
+    FP64 tolerance of the oracle."""
+    name, n, masses, ks, kap_s, g, m_steps, S = case
+    say("mixed", case)
+    if name.startswith("tiny"):
+        f = fields.tiny_field(0)
+    else:
+        f = fields.random_field(11, n, kappa_star=ks, kappa_s=kap_s, gamma=g, masses=masses)
+    R, cn, st, (rr, ri, cnt) = gpu_roots(ctx, f, m_steps, n_subchains=S, precision="mixed")
+    print("[stats]", {k: st[k] for k in ("root_updates", "root_updates_f32", "polish_updates",
+                                         "rows_fallback", "sweeps")}, flush=True)
+    assert st["root_updates_f32"] > 0 and st["polish_updates"] > 0
+    R_ref, cn_ref, _ = oracle.critical_curves(f, m_steps, n_sub=1)
+    worst = check_roots_against_oracle(f, R, R_ref, name)
+    assert sorted(cn.tolist()) == list(range(2 * n))
+    assert np.max(np.abs(R[-1] - R[0][cn])) < 1e-8
+    W_fused = gpu_roots.caustics
+    W_ref = oracle.lens_map(f, R_ref)
+    wworst = 0.0
+    for j in range(R.shape[0]):
+        idx, d = parity.pair(R_ref[j], R[j])
+        Fp = oracle.eval_F(f, oracle.phase(j, m_steps), R_ref[j])[1]
+        bw = 2 * abs(1 - f.kappa_s) * parity.root_bound(f, Fp) + 1e-11 * (1 + np.abs(W_ref[j]))
+        assert np.all(np.abs(W_fused[j][idx] - W_ref[j]) <= bw)
+        wworst = max(wworst, float(np.abs(W_fused[j][idx] - W_ref[j]).max()))
+    print(f"[{name}] mixed: max root error {worst:.3e}, max caustic error {wworst:.3e}", flush=True)
+
+
 def test_determinism_bitwise(ctx):
     say("determinism")
     f = fields.random_field(5, 60, kappa_star=0.4, gamma=0.3, masses="salpeter")
