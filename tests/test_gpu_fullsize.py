@@ -2,7 +2,8 @@
 benchmark times (library-chosen subchains, fused caustics, per-launch event
 timing).  The oracle cannot redo whole runs of this size, so it checks
 sampled rows (cold-started on their own), a window of subchain 0 grown
-centre-out exactly as the GPU grows it (same columns), and properties that
+centre-out as the GPU grows it (the same columns once the two centre
+rows are paired), and properties that
 hold at any size: the row identities sum r = 2 sum z_i and
 sum r^2 = 2 sum z_i^2 - 2M/c(phi), the closure row m = row 0 under
 chain_next, and crossing-map values at sampled pixels."""
@@ -121,11 +122,17 @@ def test_full_size_single_field(mlcc, case):
         R_rows = [host_c(rr[j], ri[j]) for j in rows]
         W_rows = [host_c(cr[j], ci[j]) for j in rows]
         check_sampled_rows(f, R_rows, W_rows, rows, m_steps, name)
-        # subchain 0 grown from its centre: the same columns as the oracle's
+        # subchain 0 grown from its centre: which seed ends at which root of
+        # the cold-started centre row is chaotic at this N (any rounding
+        # difference reorders it), so the oracle's centre row is paired with
+        # the GPU's; from there the warm-started rows must follow the same
+        # columns
         lo, c, hi = subchain0_window(st, m_steps, half)
         R_win, _ = oracle.subchain(f, m_steps, lo, c, hi)
         G_win = host_c(rr[lo:hi + 1], ri[lo:hi + 1])
-        colwise = float(np.max(np.abs(G_win - R_win)))
+        idx, d = parity.pair(R_win[c - lo], G_win[c - lo])
+        assert len(set(idx.tolist())) == n_r and d.max() < 1e-8
+        colwise = float(np.max(np.abs(G_win[:, idx] - R_win)))
         print(f"[{name}] rows {lo}..{hi} of subchain 0, column-wise: {colwise:.3e}", flush=True)
         assert colwise < 1e-8
         if n_pix:
