@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--subchains", type=int, default=0, help="0 = library choice")
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: the workload's own (mixed for n10k_mixed)")
+    ap.add_argument("--predictor", type=int, default=0, choices=[0, 1, 2],
+                    help="warm-row start: 0 previous row, 1 linear, 2 quadratic extrapolation")
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-sweeps", type=int, default=2,
@@ -124,7 +126,8 @@ def main():
         # roots and, in the same pass, their caustic images
         _, _, _, _, cn, st, _ = ctx.find_critical_curves(
             m_steps, n_subchains=args.subchains, timing=True, caustics=True,
-            out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=precision)
+            out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=precision,
+            predictor=args.predictor)
         ctx.caustic_crossings(w_re, w_im, cn, grid, out=ncc)
         ctx.caustic_distances(grid, ncc, out=(dist, bl))
         return st
@@ -171,7 +174,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "n_stars": n, "roots_per_row": n_r, "phase_steps": m_steps,
-                   "grid": [grid.nx, grid.ny], "precision": precision, "seed": args.seed},
+                   "grid": [grid.nx, grid.ny], "precision": precision,
+                   "predictor": args.predictor, "seed": args.seed},
         "roofline": {
             "bound": "alu",
             "kernel": dominant["kernel"],
@@ -259,7 +263,8 @@ def bench_batched(args, wl, precision):
         ctx.set_lenses_batched(off, x, y, mm, ks, gs)
         _, _, _, _, cn, st, _ = ctx.find_critical_curves(
             m_steps, n_subchains=args.subchains, timing=True, caustics=True,
-            out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=precision)
+            out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=precision,
+            predictor=args.predictor)
         return st
 
     for i in range(args.warmup):
@@ -289,7 +294,7 @@ def bench_batched(args, wl, precision):
         "data": "synthetic",
         "config": {"workload": f"batched: {WORKLOAD_TEXT['batched']}", "fields": len(fs),
                    "total_stars": n_tot, "roots_per_row": 2 * n_tot, "phase_steps": m_steps,
-                   "precision": precision, "seed": args.seed},
+                   "precision": precision, "predictor": args.predictor, "seed": args.seed},
         "roofline": {"bound": "alu", "kernel": dominant["kernel"],
                      "achieved": dominant["achieved"], "peak": dominant["peak"],
                      "unit": "TFLOP/s", "frac": dominant["frac"], "traffic": None,

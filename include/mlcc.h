@@ -109,7 +109,13 @@ typedef struct {
     double tol_inv_mu;     /* ... or once the App. C bound |F|(|F| + 2|1-kappa_s|) on
                               |1/mu| is below tol_inv_mu; 0 disables this test */
     int32_t timing;        /* nonzero: time every sweep launch with HIP events */
-    int32_t reserved;
+    int32_t predictor;     /* start of a warm row's first pass, for each root:
+                              0 = its value in the previous row (the warm start of
+                              Sec. 3.2); 1 = linear, 2 = quadratic extrapolation
+                              along its chain from the last 2 / 3 rows of the
+                              same subchain (fewer rows are used where fewer
+                              exist); the other roots enter that first pass at
+                              their previous-row values */
 } mlcc_cc_params;
 
 /* The paper's settings (Sec. 3.2 footnote: cutoffs 1e-9 and |mu| > 1e9),

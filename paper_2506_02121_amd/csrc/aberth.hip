@@ -183,6 +183,7 @@ struct Update {
     double zr, zi;   // new iterate
     double wr, wi;   // its image under the lens map
     bool flag;       // converged
+    double err;      // Newton polish: estimated error of the new iterate
 };
 
 // Degenerate iterate (on a star, or two iterates equal): nudge it off.
@@ -257,12 +258,14 @@ template <class T> struct RoundArgs {
     double2 *bnd;
     int32_t *counts;
     Control *ctl;
-    double4 *vieta;
+    double4 *vieta;    // two per block: row sums, and their error terms
+    double *errbuf;    // estimated error of each polished root
+    int32_t predictor;
 };
 
 // What one block knows about its front and star field.
 template <class T> struct BlockCtx {
-    int f, q, k0, k, lane, n_r, n_stars, row, stamp;
+    int f, q, k0, k, lane, n_r, n_stars, row, stamp, dir, pred;
     bool valid, boundary;
     int64_t base_f, out_off, bnd_row_off;
     const T *stars;
@@ -282,6 +285,8 @@ __device__ __forceinline__ bool enter(const RoundArgs<T> &A, int phase, BlockCtx
     const Real *R = A.reals + F->real;
     B.row = F->row;
     B.stamp = F->stamp;
+    B.dir = F->dir;
+    B.pred = (F->fresh && F->dir != 0 && F->hist >= 2) ? min(A.predictor, F->hist - 1) : 0;
     B.n_r = R->n_r;
     B.n_stars = R->n_stars;
     B.stars = A.stars + R->star_off;
@@ -301,6 +306,26 @@ __device__ __forceinline__ bool enter(const RoundArgs<T> &A, int phase, BlockCtx
     B.k = B.k0 + B.lane;
     B.valid = B.k < B.n_r;
     return true;
+}
+
+// Start of a new row's first pass for root k: extrapolation along its chain
+// from the previous row (z1, the converged iterate) and the rows before it,
+// which the subchain has already written to the output (same labels):
+// linear 2 z1 - z2, quadratic 3 (z1 - z2) + z3.
+template <class T>
+__device__ __forceinline__ void predict(const RoundArgs<T> &A, const BlockCtx<T> &B, int k,
+                                        double &zr, double &zi)
+{
+    const int64_t o2 = B.out_off + (int64_t)(B.row - 2 * B.dir) * B.n_r + k;
+    const double x2 = A.out_re[o2], y2 = A.out_im[o2];
+    if (B.pred == 1) {
+        zr = 2.0 * zr - x2;
+        zi = 2.0 * zi - y2;
+    } else {
+        const int64_t o3 = o2 - (int64_t)B.dir * B.n_r;
+        zr = fma(3.0, zr - x2, A.out_re[o3]);
+        zi = fma(3.0, zi - y2, A.out_im[o3]);
+    }
 }
 
 // Write-back of a converged root: its row of the output (or the duplicate
@@ -346,6 +371,7 @@ aberth_sweep_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
         zr = z.x;
         zi = z.y;
         act = flagrow[base_f + k] != B.stamp;
+        if (B.pred) predict(A, B, k, zr, zi);
     }
     const unsigned long long amask = __ballot(act);
     const int n_act = __popcll(amask);
@@ -416,8 +442,13 @@ aberth_sweep_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
 }
 
 // ---------------------------------------------------------------------------
-// FP32 Aberth sweep (mixed mode, first pass of a warm row)
+// FP32 Aberth sweep (mixed mode: cold starts, rows without a prediction, and
+// rows the polish did not settle)
 // ---------------------------------------------------------------------------
+
+// Steps shorter than this (theta_E units) are below what the FP32 sums
+// resolve reliably; the FP64 polish takes over from there.
+constexpr double TOL_F32 = 1e-6;
 
 // One Aberth step for every root of the row with the sums in FP32.  The
 // distance to each star is formed in FP64 and rounded, so no precision is
@@ -445,6 +476,7 @@ aberth_sweep_f32(RoundArgs<typename StarRec<EQUAL>::T> A)
         const double2 z = zsrc[k];
         zr = z.x;
         zi = z.y;
+        if (B.pred) predict(A, B, k, zr, zi);
     }
     // star sums: FP32 within a tile, FP64 across tiles
     double S1r = 0, S1i = 0, S2r = 0, S2i = 0, S3r = 0, S3i = 0;
@@ -514,7 +546,12 @@ aberth_sweep_f32(RoundArgs<typename StarRec<EQUAL>::T> A)
     if (!isfinite(u.zr) || !isfinite(u.zi)) nudge(u, zr, zi, k);
     if (valid) A.nxt[base_f + k] = make_double2(u.zr, u.zi);
     const int n_valid = __popcll(__ballot(valid));
+    // roots that moved by more than the FP32 sweep can resolve are still
+    // on their way (the control kernel uses this for cold starts)
+    const double mr = u.zr - zr, mi = u.zi - zi;
+    const int n_moving = __popcll(__ballot(valid && !(mr * mr + mi * mi <= TOL_F32 * TOL_F32)));
     if (lane == 0) {
+        if (n_moving) atomicAdd(&A.counts[B.f], n_moving);
         atomicAdd(&A.ctl->updates_f32, (unsigned long long)n_valid);
         atomicAdd(&A.ctl->star_updates_f32, (unsigned long long)n_valid * (unsigned)B.n_stars);
     }
@@ -588,6 +625,7 @@ __device__ __forceinline__ Update polish_finish(PSums S, double zr, double zi, d
     const double ratio = 6.0 * sqrt(S.s4r * S.s4r + S.s4i * S.s4i) / sqrt(den); // |F''/F'|
     const double err = 0.5 * ratio * aD * aD;
     u.flag = err <= tol && aD * ratio < 0.1 && aD < 1e-3;
+    u.err = err;
     if (!isfinite(u.zr) || !isfinite(u.zi)) nudge(u, zr, zi, k);
     const double d2r = Dr * Dr - Di * Di, d2i = 2.0 * Dr * Di;
     const double d3r = d2r * Dr - d2i * Di, d3i = d2r * Di + d2i * Dr;
@@ -723,6 +761,8 @@ __device__ __forceinline__ void row_done(Front &fr, int32_t *st, int f)
         fr.passes = 0;
         fr.phase = fr.mode;
         fr.stamp = 4 * fr.row;
+        fr.hist = min(fr.hist + 1, 3);
+        fr.fresh = 1;
     }
 }
 
@@ -769,6 +809,7 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
         const int32_t c = counts[f];
         counts[f] = 0;
         fr.src = f;
+        fr.fresh = 0;
         if (fr.phase == PH_F32) {
             fr.phase = PH_POLISH;
             fr.passes = 0;
@@ -817,6 +858,8 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
                 pr.passes = 0;
                 pr.phase = pr.mode;
                 pr.stamp = 4 * pr.row;
+                pr.hist = 1;   // the centre row
+                pr.fresh = 1;
                 fronts[p] = pr;
                 st[p - f0] = FRONT_ACTIVE;
                 fr.dir = -1;
@@ -825,6 +868,8 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
                 fr.passes = 0;
                 fr.phase = fr.mode;
                 fr.stamp = 4 * fr.row;
+                fr.hist = 1;
+                fr.fresh = 1;
             } else {
                 fr.max_warm = max(fr.max_warm, fr.sweeps + 1);
                 row_done(fr, st, f - f0);
@@ -1087,6 +1132,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         A.counts = c->counts.as<int32_t>();
         A.ctl = c->control.as<Control>();
         A.vieta = c->vieta.as<double4>();
+        A.predictor = p->predictor;
     };
     const dim3 grid((unsigned)nblocks);
     auto launch_kind = [&](int kind, const double2 *cur, double2 *nxt) {

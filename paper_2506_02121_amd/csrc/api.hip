@@ -170,6 +170,7 @@ void mlcc_cc_params_default(mlcc_cc_params *p, int64_t m_steps)
     p->tol_step = 1e-9;
     p->tol_inv_mu = 1e-9;
     p->timing = 0;
+    p->predictor = 0;
 }
 
 // Loads one or several star fields (concatenated; field r holds stars
@@ -323,6 +324,8 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
         return fail(MLCC_ERR_INVALID, "iteration caps must be >= 0");
     if (p.precision != MLCC_FP64 && p.precision != MLCC_MIXED)
         return fail(MLCC_ERR_INVALID, "unknown precision %d", p.precision);
+    if (p.predictor < 0 || p.predictor > 2)
+        return fail(MLCC_ERR_INVALID, "predictor must be 0, 1 or 2 (got %d)", p.predictor);
     MLCC_TRY(check_device_ptr(&c, roots_re, "roots_re"));
     MLCC_TRY(check_device_ptr(&c, roots_im, "roots_im"));
     if ((caustics_re == nullptr) != (caustics_im == nullptr))

@@ -65,6 +65,8 @@ struct Front {
     int32_t passes;   // polish passes spent on the current row
     int32_t real;     // realisation (star field) this front belongs to
     int32_t blk0;     // first block of this front in the launch grid
+    int32_t hist;     // finished rows of this subchain behind the current row (<= 3)
+    int32_t fresh;    // 1 until the first pass over the current row has run
     int64_t it_off;   // first element of its roots in the iterate and flag arrays
 };
 

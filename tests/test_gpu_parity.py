@@ -214,6 +214,51 @@ def test_mixed_precision_matches_oracle(ctx, case):
     print(f"[{name}] mixed: max root error {worst:.3e}, max caustic error {wworst:.3e}", flush=True)
 
 
+PREDICTOR_CASES = [
+    # name, n, masses, kappa_star, kappa_s, gamma, m_steps, n_sub, precision, predictor
+    ("n100_lin", 100, "equal", 0.5, 0.0, 0.3, 400, 4, "fp64", 1),
+    ("n100_quad", 100, "equal", 0.5, 0.0, 0.3, 400, 4, "fp64", 2),
+    ("n150_salp_quad", 150, "salpeter", 0.45, 0.1, 0.2, 400, 10, "fp64", 2),
+    ("n300_salp_quad_mixed", 300, "salpeter", 0.4, 0.2, 0.45, 600, 6, "mixed", 2),
+    ("tiny_quad", 10, "equal", 0.3, 0.0, 0.3, 1000, 0, "fp64", 2),
+]
+
+
+@pytest.mark.parametrize("case", PREDICTOR_CASES, ids=[c[0] for c in PREDICTOR_CASES])
+def test_predictor_matches_oracle(ctx, case):
+    """Warm rows started from an extrapolation along each chain: the same
+    root sets within tolerance, the same chains as the oracle's warm start
+    from the previous row, fewer updates than without it."""
+    name, n, masses, ks, kap_s, g, m_steps, S, precision, pred = case
+    say("predictor", case)
+    if name.startswith("tiny"):
+        f = fields.tiny_field(0)
+    else:
+        f = fields.random_field(11, n, kappa_star=ks, kappa_s=kap_s, gamma=g, masses=masses)
+    R0, _, st0, _ = gpu_roots(ctx, f, m_steps, n_subchains=S, precision=precision)
+    R, cn, st, _ = gpu_roots(ctx, f, m_steps, n_subchains=S, precision=precision,
+                             predictor=pred)
+    W_fused = gpu_roots.caustics
+    u0 = st0["root_updates"] + st0["root_updates_f32"] + st0["polish_updates"]
+    u1 = st["root_updates"] + st["root_updates_f32"] + st["polish_updates"]
+    print(f"[{name}] updates without / with predictor: {u0} / {u1}", flush=True)
+    assert u1 < u0
+    R_ref, _, _ = oracle.critical_curves(f, m_steps, n_sub=1)
+    check_roots_against_oracle(f, R, R_ref, name)
+    assert sorted(cn.tolist()) == list(range(2 * n))
+    assert np.max(np.abs(R[-1] - R[0][cn])) < 1e-8
+    R_s, cn_s, _ = oracle.critical_curves(f, m_steps, n_sub=st["n_subchains"])
+    colwise = float(np.max(np.abs(R - R_s)))
+    print(f"[{name}] column-wise distance to the oracle with S={st['n_subchains']}: {colwise:.3e}")
+    assert colwise < 1e-8
+    assert np.array_equal(cn, cn_s)
+    W_ref = oracle.lens_map(f, R_s)
+    bound = np.stack([parity.root_bound(f, oracle.eval_F(f, oracle.phase(j, m_steps), R_s[j])[1])
+                      for j in range(m_steps + 1)])
+    assert np.all(np.abs(W_fused - W_ref) <= 2 * abs(1 - f.kappa_s) * bound
+                  + 1e-11 * (1 + np.abs(W_ref)))
+
+
 def test_determinism_bitwise(ctx):
     say("determinism")
     f = fields.random_field(5, 60, kappa_star=0.4, gamma=0.3, masses="salpeter")
