@@ -56,12 +56,15 @@ def parse():
     ap.add_argument("--subchains", type=int, default=0, help="0 = library choice")
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: the workload's own (mixed for n10k_mixed)")
-    ap.add_argument("--predictor", type=int, default=0, choices=[0, 1, 2],
+    ap.add_argument("--predictor", type=int, default=2, choices=[0, 1, 2],
                     help="warm-row start: 0 previous row, 1 linear, 2 quadratic extrapolation")
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
-    ap.add_argument("--cpu-sweeps", type=int, default=2,
-                    help="oracle Jacobi sweeps timed for the CPU baseline")
+    ap.add_argument("--cpu-rows", type=int, default=4,
+                    help="warm rows of the oracle timed for the CPU baseline")
+    ap.add_argument("--compare", dest="compare", action="store_true", default=True,
+                    help="also run the other precision (mixed vs FP64) on the same field")
+    ap.add_argument("--no-compare", dest="compare", action="store_false")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (to scale "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -121,33 +124,35 @@ def main():
     ctx = mlcc.Context(0)
     torch.cuda.synchronize()
 
-    def step():
+    def step(prec):
         ctx.set_lenses(x, y, mm, f.kappa_s, f.gamma)
         # roots and, in the same pass, their caustic images
         _, _, _, _, cn, st, _ = ctx.find_critical_curves(
             m_steps, n_subchains=args.subchains, timing=True, caustics=True,
-            out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=precision,
+            out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=prec,
             predictor=args.predictor)
         ctx.caustic_crossings(w_re, w_im, cn, grid, out=ncc)
         ctx.caustic_distances(grid, ncc, out=(dist, bl))
         return st
 
-    for i in range(args.warmup):
-        t = time.perf_counter()
-        step()
+    def run(prec, warmup, steps):
+        for i in range(warmup):
+            t = time.perf_counter()
+            step(prec)
+            torch.cuda.synchronize()
+            log(f"{prec} warmup {i}: {time.perf_counter() - t:.3f} s")
+        stats = []
         torch.cuda.synchronize()
-        log(f"warmup {i}: {time.perf_counter() - t:.3f} s")
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ts = time.perf_counter()
+            stats.append(step(prec))
+            torch.cuda.synchronize()
+            log(f"{prec} step {i}: {time.perf_counter() - ts:.3f} s, {stats[-1]['sweeps']} rounds")
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, stats
 
-    stats = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        stats.append(step())
-        torch.cuda.synchronize()
-        log(f"step {i}: {time.perf_counter() - ts:.3f} s, {stats[-1]['sweeps']} sweeps")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed, stats = run(precision, args.warmup, args.steps)
     ms_per_step = 1e3 * elapsed / args.steps
     roots_per_step = m_steps * n_r
     value = roots_per_step / (elapsed / args.steps)
@@ -199,12 +204,35 @@ def main():
                   "max_row_sweeps": s0["max_row_sweeps"], "match_maxdist": s0["match_maxdist"],
                   "ncc_max": int(ncc_h.max()), "ncc_min": int(ncc_h.min())},
     }
+    if args.compare:
+        # the other precision on the same field: throughput, and how far its
+        # roots lie from this run's on sampled rows (same sets, any order)
+        from scipy.spatial import cKDTree
+        other = "mixed" if precision == "fp64" else "fp64"
+        sample = np.linspace(0, m_steps, 17).astype(np.int64)
+        ref = [(roots_re[j].cpu().numpy(), roots_im[j].cpu().numpy()) for j in sample]
+        el2, st2 = run(other, 0, args.steps)
+        dmax = 0.0
+        for j, (a_re, a_im) in zip(sample, ref):
+            b = np.stack([roots_re[j].cpu().numpy(), roots_im[j].cpu().numpy()], 1)
+            d, _ = cKDTree(b).query(np.stack([a_re, a_im], 1))
+            dmax = max(dmax, float(d.max()))
+        k2 = root_kernels(st2, other)
+        out["compare"] = {
+            "precision": other, "value": roots_per_step / (el2 / args.steps),
+            "ms_per_step": 1e3 * el2 / args.steps, "steps": args.steps,
+            "speedup_of_mixed_over_fp64": (el2 / elapsed if other == "fp64" else elapsed / el2),
+            "max_root_distance_to_main_run": dmax, "sampled_rows": len(sample),
+            "kernels": k2,
+            "stats": {k: st2[-1][k] for k in ("sweeps", "root_updates", "root_updates_f32",
+                                              "polish_updates", "rows_fallback")},
+        }
     ctx.close()
     del roots_re, roots_im, w_re, w_im
     torch.cuda.empty_cache()
 
     if args.cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(f, m_steps, updates_per_root_row, args.cpu_sweeps)
+        out["cpu_baseline"] = cpu_baseline(f, m_steps, args.cpu_rows)
     print(json.dumps(out), flush=True)
 
 
@@ -330,29 +358,34 @@ def measured_traffic(workload):
         return None
 
 
-def cpu_baseline(f, m_steps, updates_per_root_row, sweeps):
+def cpu_baseline(f, m_steps, rows):
     """The oracle as it stands, timed on the host's cores, on a bounded
-    sample: `sweeps` Jacobi sweeps of the cold-started centre row (every root
-    active).  Its root-update rate divided by the workload's root updates per
-    root per row (same algorithm and cutoffs) gives roots/s."""
+    sample of the same workload: the centre row of the phase grid cold-started
+    from the seeds (not timed), then `rows` warm rows, each seeded with the
+    previous row as the paper grows a chain (timed).  roots/s = rows x 2N /
+    time."""
     import numpy as np
 
     import oracle
-    log(f"cpu baseline: {sweeps} oracle sweeps of the centre row on {oracle.num_threads()} threads")
+    c = m_steps // 2
+    log(f"cpu baseline: oracle cold start at row {c}, then {rows} timed warm rows on "
+        f"{oracle.num_threads()} threads")
+    z, sw0, up0, _ = oracle.aberth_row(f, oracle.phase(c, m_steps))
     t = time.perf_counter()
-    z, sw, up, rc = oracle.aberth_row(f, np.pi, max_iter=sweeps, polish=False,
-                                      allow_unconverged=True)
+    ups = 0
+    for i in range(1, rows + 1):
+        z, sw, up, _ = oracle.aberth_row(f, oracle.phase(c + i, m_steps), z0=z)
+        ups += up
     dt = time.perf_counter() - t
-    rate = up / dt
     return {
-        "value": rate / updates_per_root_row,
+        "value": rows * 2 * f.n / dt,
         "unit": "roots/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": (f"{sw} cold Jacobi sweeps of the centre row ({up} root updates, "
-                   f"{2 * f.n} roots, {f.n} stars) in {dt:.1f} s = {rate:.3g} root updates/s, "
-                   f"divided by {updates_per_root_row:.3f} root updates per root per row "
-                   f"counted on the same workload"),
+        "sample": (f"{rows} warm rows (phase steps {c + 1}..{c + rows} of {m_steps}, "
+                   f"{2 * f.n} roots each, {f.n} stars), each seeded with the previous "
+                   f"row, after an untimed cold start at row {c}: {ups} root updates in "
+                   f"{dt:.1f} s"),
     }
 
 

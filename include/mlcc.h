@@ -45,9 +45,15 @@ typedef enum {
 
 typedef enum {
     MLCC_FP64 = 0, /* every step in IEEE double precision */
-    MLCC_MIXED = 1 /* warm rows: one FP32 Aberth sweep, then FP64 Newton polish with an
-                      a-posteriori acceptance test and a Vieta check of the row, FP64
-                      Aberth sweeps for anything not accepted; cold starts FP64 */
+    MLCC_MIXED = 1 /* Aberth sweeps in FP32 (FP64 star distances, FP32 sums per tile of
+                      64 stars carried in FP64), every root finished by FP64 Newton
+                      polish passes with an a-posteriori acceptance test per root and
+                      the two row identities (sum r, sum r^2) per row.  Cold starts:
+                      FP32 sweeps until the roots settle, then the polish.  Warm rows:
+                      the polish straight from the chain prediction (predictor > 0),
+                      else after one FP32 sweep.  A row the polish does not settle
+                      gets one FP32 sweep and the polish again, then FP64 Aberth
+                      sweeps.  Results meet the same cutoffs as MLCC_FP64. */
 } mlcc_precision;
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream` (a
@@ -118,8 +124,9 @@ typedef struct {
                               their previous-row values */
 } mlcc_cc_params;
 
-/* The paper's settings (Sec. 3.2 footnote: cutoffs 1e-9 and |mu| > 1e9),
- * library-chosen subchains, FP64. */
+/* The paper's cutoffs (Sec. 3.2 footnote: 1e-9 and |mu| > 1e9),
+ * library-chosen subchains, FP64, quadratic chain predictor (predictor = 0
+ * gives the paper's warm start from the previous row). */
 void mlcc_cc_params_default(mlcc_cc_params *p, int64_t m_steps);
 
 typedef struct {
@@ -131,8 +138,8 @@ typedef struct {
     int64_t rows_capped;     /* rows that hit an iteration cap */
     int64_t rows_fallback;   /* rows that fell back to FP64 Aberth sweeps (MLCC_MIXED) */
     int32_t n_subchains;     /* S actually used */
-    int32_t max_row_sweeps;  /* most FP64 sweeps any warm row needed */
-    int32_t cold_sweeps;     /* most sweeps any cold start needed */
+    int32_t max_row_sweeps;  /* most passes (of any kind) any warm row needed */
+    int32_t cold_sweeps;     /* most passes any cold start needed */
     int32_t polls;           /* host polls of the device-side front table */
     double match_maxdist;    /* largest distance between paired duplicate roots */
     double sweep_ms;         /* GPU time of FP64 sweep launches that did work (timing != 0) */

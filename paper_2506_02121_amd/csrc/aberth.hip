@@ -12,10 +12,14 @@
 //  * Jacobi double buffering: every kernel of a launch round reads iterate
 //    `cur` and writes `nxt`; the host alternates the two.
 //  * Each front carries a phase.  FP64 mode: every row is FP64 Aberth sweeps.
-//    Mixed mode, warm rows: one FP32 Aberth sweep, then FP64 Newton polish
-//    passes with an a-posteriori acceptance test and a Vieta check of the
-//    row, then FP64 Aberth sweeps for whatever was not accepted.  Cold starts
-//    are FP64 in both modes.
+//    Mixed mode: cold starts are FP32 Aberth sweeps until the roots settle;
+//    warm rows with a chain prediction start directly with FP64 Newton
+//    polish passes (a-posteriori acceptance test per root, row identities
+//    for the row), warm rows without one with a single FP32 sweep; a row the
+//    polish does not settle gets one FP32 sweep of the whole row and the
+//    polish again, then FP64 Aberth sweeps.
+//  * A warm row's first pass may start each root from an extrapolation
+//    along its chain instead of its previous-row value.
 //  * A single-work-group control kernel after every round advances the
 //    fronts (device-side; the host polls a status block one batch ahead).
 //  * Converged roots are mapped to the caustic in the same kernel.
@@ -656,11 +660,14 @@ newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
     const double m0 = B.m0, gamma = B.gamma, a = B.a, tol = A.tol_step;
     double zr = 0.0, zi = 0.0;
     bool act = false;
+    double er_ = 0.0;   // estimated error of the value this root ends the pass with
     if (valid) {
         const double2 z = zsrc[k];
         zr = z.x;
         zi = z.y;
         act = flagrow[base_f + k] != B.stamp;
+        if (B.pred) predict(A, B, k, zr, zi);
+        if (!act) er_ = A.errbuf[base_f + k];   // accepted in an earlier pass of this row
     }
     const unsigned long long amask = __ballot(act);
     const int n_act = __popcll(amask);
@@ -686,6 +693,8 @@ newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
                 fr_ = u.zr;
                 fi_ = u.zi;
                 if (u.flag) {
+                    er_ = u.err;
+                    A.errbuf[base_f + kk] = u.err;
                     flagrow[base_f + kk] = B.stamp;
                     put(A, B, kk, u);
                 }
@@ -703,6 +712,8 @@ newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
             fr_ = u.zr;
             fi_ = u.zi;
             if (u.flag) {
+                er_ = u.err;
+                A.errbuf[base_f + k] = u.err;
                 flagrow[base_f + k] = B.stamp;
                 put(A, B, k, u);
             }
@@ -710,12 +721,18 @@ newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
         n_after = __popcll(__ballot(act && !u.flag));
     }
     if (valid && !act) nxt[base_f + k] = make_double2(zr, zi);
-    // this block's share of sum z and sum z^2 over the row (Vieta check)
+    // this block's share of the row sums sum r and sum r^2 (row identities),
+    // and of what bounds their error: the roots' own estimated errors, and
+    // sum |r|, sum |r|^2 for the rounding of the sums
     double s1r = valid ? fr_ : 0.0, s1i = valid ? fi_ : 0.0;
     double s2r = valid ? fr_ * fr_ - fi_ * fi_ : 0.0, s2i = valid ? 2.0 * fr_ * fi_ : 0.0;
+    const double ab2 = valid ? fr_ * fr_ + fi_ * fi_ : 0.0, ab = sqrt(ab2);
+    double t_e = er_, t_e2 = er_ * (2.0 * ab + er_), t_a = ab, t_a2 = ab2;
     wave_sum(s1r); wave_sum(s1i); wave_sum(s2r); wave_sum(s2i);
+    wave_sum(t_e); wave_sum(t_e2); wave_sum(t_a); wave_sum(t_a2);
     if (lane == 0) {
-        A.vieta[blockIdx.x] = make_double4(s1r, s1i, s2r, s2i);
+        A.vieta[2 * blockIdx.x] = make_double4(s1r, s1i, s2r, s2i);
+        A.vieta[2 * blockIdx.x + 1] = make_double4(t_e, t_e2, t_a, t_a2);
         if (n_after) atomicAdd(&A.counts[B.f], n_after);
         if (n_act) {
             atomicAdd(&A.ctl->polish_updates, (unsigned long long)n_act);
@@ -749,47 +766,103 @@ __global__ void seed_centres(const T *__restrict__ stars, const Real *__restrict
 constexpr int CONTROL_THREADS = 256;
 constexpr int MAX_FRONTS = 1 << 16;
 constexpr int MAX_POLISH = 3;
+constexpr int F32_STALL = 4;
 
-__device__ __forceinline__ void row_done(Front &fr, int32_t *st, int f)
+// Puts a front at the start of its (new) row.  Mixed mode: a row with a
+// chain prediction goes straight to the FP64 polish; one without (the two
+// rows next to a subchain centre, or predictor 0) starts with an FP32 sweep.
+__device__ __forceinline__ void start_row(Front &fr, int predictor)
+{
+    fr.sweeps = 0;
+    fr.passes = 0;
+    fr.tried = 0;
+    fr.f32 = 0;
+    fr.best = 0x7fffffff;
+    fr.stall = 0;
+    fr.passes_row = 0;
+    fr.stamp = 4 * fr.row;
+    fr.fresh = 1;
+    if (fr.mode == PH_F64)
+        fr.phase = PH_F64;
+    else
+        fr.phase = (predictor > 0 && fr.hist >= 2) ? PH_POLISH : PH_F32;
+}
+
+__device__ __forceinline__ void row_done(Front &fr, int32_t *st, int f, int predictor)
 {
     if (fr.row == fr.end_row) {
         fr.state = FRONT_DONE;
         st[f] = FRONT_DONE;
     } else {
         fr.row += fr.dir;
-        fr.sweeps = 0;
-        fr.passes = 0;
-        fr.phase = fr.mode;
-        fr.stamp = 4 * fr.row;
         fr.hist = min(fr.hist + 1, 3);
-        fr.fresh = 1;
+        start_row(fr, predictor);
     }
 }
 
-// Advances every front after a round.  FP64 phase: a converged cold start
-// hands the upward half to its partner front and turns downward itself; a
-// converged warm row moves one row on or finishes at its end row; a front
-// that reaches its sweep cap stops and is counted as failed (with a partner
-// it can no longer start).  FP32 phase: always followed by the polish.
-// Polish phase: a row whose roots were all accepted and whose sums satisfy
-// the row identities is done; otherwise more polish passes, then FP64 sweeps
-// for the rest (all roots of the row again if an identity failed).
+// Every root of the current row converged.  A cold start hands the upward
+// half of its subchain to its partner front and turns downward itself; a
+// warm row moves one row on or finishes at its end row.
+__device__ __forceinline__ void row_converged(Front &fr, int f, Front *fronts, int32_t *st,
+                                              int f0, int predictor)
+{
+    if (fr.dir == 0) {
+        fr.cold = fr.passes_row;
+        const int p = fr.partner;
+        const int centre = fr.row;
+        Front pr = fronts[p];
+        pr.state = FRONT_ACTIVE;
+        pr.row = centre + 1;
+        pr.dir = 1;
+        pr.src = f;    // first pass reads the converged centre row
+        pr.hist = 1;   // the centre row
+        start_row(pr, predictor);
+        fronts[p] = pr;
+        st[p - f0] = FRONT_ACTIVE;
+        fr.dir = -1;
+        fr.row = centre - 1;
+        fr.hist = 1;
+        start_row(fr, predictor);
+    } else {
+        fr.max_warm = max(fr.max_warm, fr.passes_row);
+        row_done(fr, st, f - f0, predictor);
+    }
+}
+
+// Advances every front after a round (counts[f] = roots of front f still
+// unconverged after its pass, or, after an FP32 sweep, still moving).
+//   FP64 phase: a converged row moves on (row_converged); a front that
+//     reaches its sweep cap stops and is counted as failed (with a partner
+//     it can no longer start).
+//   FP32 phase (mixed): warm rows take one sweep; a cold start sweeps until
+//     no root moves by more than TOL_F32, or that count has not fallen for
+//     F32_STALL sweeps, or max_cold; then the polish.
+//   Polish phase (mixed): a row whose roots were all accepted and whose sums
+//     satisfy the row identities has converged.  Otherwise more polish
+//     passes (up to MAX_POLISH); then, once per row, an FP32 sweep of the
+//     whole row and the polish again; then FP64 sweeps for whatever is not
+//     accepted (all roots of the row if an identity failed).
 //
 // Row identities: the rationalised polynomial has leading coefficient
 // c = gamma - (1 - kappa_s) e^{-i phi} and next coefficient -2 c sum z_i, so
 // sum r = 2 sum z_i and sum r^2 = 2 sum z_i^2 - 2 M / c (M = sum m_i).  A
-// root found twice and one missed shifts them by about their distance.
+// root found twice and one missed shifts them by the distance of the two.
+// The test allows the roots' own estimated errors (twice over) plus a
+// bound on the rounding of the sums: partial sums of 64 values by a
+// butterfly, then the blocks in order, gives at most (6 + blocks) unit
+// roundoffs of sum |r| (one more for sum |r|^2, whose terms round too).
 //
-// `st` keeps the states in LDS so that a partner activated by one thread is
-// not processed by another in the same pass; with more fronts than fit, the
-// kernel runs as several work groups over disjoint ranges that keep each
-// subchain's two fronts together.
+// `st` keeps the states in LDS: the two fronts of a subchain sit in adjacent
+// lanes of one wave, which read their states before either is written, so
+// a partner activated in this pass is not also advanced in it.  With more
+// fronts than fit, the kernel runs as several work groups over disjoint
+// ranges that keep each subchain's two fronts together.
 __global__ void __launch_bounds__(CONTROL_THREADS)
 aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t n_fronts,
                Control *__restrict__ ctl, int32_t max_cold, int32_t max_warm,
                int32_t *__restrict__ workflag, const double4 *__restrict__ vieta,
                const Real *__restrict__ reals, const double2 *__restrict__ unit,
-               int32_t fronts_per_group)
+               int32_t fronts_per_group, int32_t predictor)
 {
     __shared__ int32_t st[4096];
     __shared__ int32_t s_active, s_live;
@@ -810,17 +883,37 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
         counts[f] = 0;
         fr.src = f;
         fr.fresh = 0;
+        fr.passes_row += 1;
         if (fr.phase == PH_F32) {
-            fr.phase = PH_POLISH;
-            fr.passes = 0;
+            fr.f32 += 1;
+            bool polish = true;
+            if (fr.dir == 0) {
+                if (c < fr.best) {
+                    fr.best = c;
+                    fr.stall = 0;
+                } else {
+                    fr.stall += 1;
+                }
+                polish = c == 0 || fr.stall >= F32_STALL || fr.f32 >= max_cold;
+            }
+            if (polish) {
+                if (fr.tried & TRIED_POLISH) fr.stamp += 1;   // polish every root again
+                fr.tried |= TRIED_F32;
+                fr.phase = PH_POLISH;
+                fr.passes = 0;
+            }
         } else if (fr.phase == PH_POLISH) {
+            fr.tried |= TRIED_POLISH;
+            bool retry = false, identity_failed = false;
             if (c == 0) {
                 const Real R = reals[fr.real];
                 const int bpf = (R.n_r + 63) / 64;
-                double a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+                double a1r = 0, a1i = 0, a2r = 0, a2i = 0, se = 0, se2 = 0, sa = 0, sa2 = 0;
                 for (int b = 0; b < bpf; ++b) {
-                    const double4 t = vieta[fr.blk0 + b];
+                    const double4 t = vieta[2 * (fr.blk0 + b)];
+                    const double4 q = vieta[2 * (fr.blk0 + b) + 1];
                     a1r += t.x; a1i += t.y; a2r += t.z; a2i += t.w;
+                    se += q.x; se2 += q.y; sa += q.z; sa2 += q.w;
                 }
                 const double2 u = unit[fr.row];
                 const double cr = R.gamma - R.a * u.x, ci = -R.a * u.y;   // c(phi)
@@ -829,51 +922,29 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
                 const double e1r = a1r - 2.0 * R.sz_r, e1i = a1i - 2.0 * R.sz_i;
                 const double e2r = a2r - (2.0 * R.sz2_r - 2.0 * mcr);
                 const double e2i = a2i - (2.0 * R.sz2_i - 2.0 * mci);
-                const bool ok = sqrt(e1r * e1r + e1i * e1i) <= R.tol1 &&
-                                sqrt(e2r * e2r + e2i * e2i) <= R.tol2;
-                if (ok) {
-                    row_done(fr, st, f - f0);
+                const double u_ro = 1.1102230246251565e-16;
+                const double tol1 = 2.0 * se + 2.0 * (6 + bpf) * u_ro * sa + R.tol1;
+                const double tol2 = 2.0 * se2 + 2.0 * (7 + bpf) * u_ro * sa2 + R.tol2 +
+                                    16.0 * u_ro * sqrt(mcr * mcr + mci * mci);
+                if (sqrt(e1r * e1r + e1i * e1i) <= tol1 && sqrt(e2r * e2r + e2i * e2i) <= tol2)
+                    row_converged(fr, f, fronts, st, f0, predictor);
+                else
+                    retry = identity_failed = true;
+            } else if (++fr.passes >= MAX_POLISH) {
+                retry = true;
+            }
+            if (retry) {
+                if (!(fr.tried & TRIED_F32)) {
+                    fr.phase = PH_F32;
                 } else {
-                    fr.stamp += 1;   // every root of the row active again
+                    if (identity_failed) fr.stamp += 1;   // every root of the row again
                     fr.phase = PH_F64;
                     fr.sweeps = 0;
                     atomicAdd((unsigned long long *)&ctl->rows_fallback, 1ull);
                 }
-            } else if (++fr.passes >= MAX_POLISH) {
-                fr.phase = PH_F64;
-                fr.sweeps = 0;
-                atomicAdd((unsigned long long *)&ctl->rows_fallback, 1ull);
             }
         } else if (c == 0) {
-            if (fr.dir == 0) {
-                fr.cold = fr.sweeps + 1;
-                const int p = fr.partner;
-                const int centre = fr.row;
-                Front pr = fronts[p];
-                pr.state = FRONT_ACTIVE;
-                pr.row = centre + 1;
-                pr.dir = 1;
-                pr.src = f;   // first pass reads the converged centre row
-                pr.sweeps = 0;
-                pr.passes = 0;
-                pr.phase = pr.mode;
-                pr.stamp = 4 * pr.row;
-                pr.hist = 1;   // the centre row
-                pr.fresh = 1;
-                fronts[p] = pr;
-                st[p - f0] = FRONT_ACTIVE;
-                fr.dir = -1;
-                fr.row = centre - 1;
-                fr.sweeps = 0;
-                fr.passes = 0;
-                fr.phase = fr.mode;
-                fr.stamp = 4 * fr.row;
-                fr.hist = 1;
-                fr.fresh = 1;
-            } else {
-                fr.max_warm = max(fr.max_warm, fr.sweeps + 1);
-                row_done(fr, st, f - f0);
-            }
+            row_converged(fr, f, fronts, st, f0, predictor);
         } else {
             fr.sweeps += 1;
             if (fr.sweeps >= (fr.dir == 0 ? max_cold : max_warm)) {
@@ -1019,10 +1090,11 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         R.sz2_r = h.sum_z2.x;
         R.sz2_i = h.sum_z2.y;
         R.M = h.mass_total;
-        // every root carries up to tol_step of error, and the sums round
-        R.tol1 = (double)n_r * p->tol_step + 1e-12 * (2.0 * h.sum_abs_z + (double)n_r);
-        R.tol2 = 2.0 * (h.max_abs_z + 2.0) * (double)n_r * p->tol_step +
-                 1e-12 * (2.0 * h.sum_abs_z2 + (double)n_r + h.mass_total);
+        // rounding of the reference values 2 sum z_i and 2 sum z_i^2 (compensated
+        // sums on the host, then the squares and the doubling)
+        const double u_ro = 1.1102230246251565e-16;
+        R.tol1 = 8.0 * u_ro * h.sum_abs_z;
+        R.tol2 = 16.0 * u_ro * h.sum_abs_z2;
         const int bpf = (int)ceil_div(n_r, 64);
         for (int s = 0; s < S; ++s) {
             const int32_t lo = (int32_t)(s * L), hi = (int32_t)(lo + L), cen = (int32_t)(lo + L / 2);
@@ -1031,7 +1103,8 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
             d.row = cen; d.dir = 0; d.end_row = lo; d.state = FRONT_ACTIVE;
             d.src = fd; d.partner = fd + 1; d.bnd_slot = s >= 1 ? s - 1 : -1;
             d.lo = lo; d.hi = hi;
-            d.phase = PH_F64; d.mode = warm_phase; d.stamp = 4 * cen;
+            d.phase = warm_phase; d.mode = warm_phase; d.stamp = 4 * cen;
+            d.best = 0x7fffffff;
             d.real = r;
             Front u{};
             u.row = cen + 1; u.dir = 1; u.end_row = hi; u.state = FRONT_IDLE;
@@ -1064,7 +1137,8 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     MLCC_TRY(c->control.reserve(sizeof(Control)));
     MLCC_TRY(c->etab.reserve((size_t)(m + 1) * sizeof(double2)));
     MLCC_TRY(c->bnd.reserve((size_t)std::max<int64_t>(bnd_total, 1) * sizeof(double2)));
-    MLCC_TRY(c->vieta.reserve((size_t)nblocks * sizeof(double4)));
+    MLCC_TRY(c->vieta.reserve((size_t)2 * nblocks * sizeof(double4)));
+    if (mixed) MLCC_TRY(c->errbuf.reserve((size_t)it_total * sizeof(double)));
     MLCC_TRY(c->reals_d.reserve((size_t)n_real * sizeof(Real)));
     MLCC_TRY(c->bmap.reserve((size_t)nblocks * sizeof(int2)));
     MLCC_TRY(c->workflags.reserve(2 * MAX_BATCH * sizeof(int32_t)));
@@ -1133,6 +1207,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         A.ctl = c->control.as<Control>();
         A.vieta = c->vieta.as<double4>();
         A.predictor = p->predictor;
+        A.errbuf = mixed ? c->errbuf.as<double>() : nullptr;
     };
     const dim3 grid((unsigned)nblocks);
     auto launch_kind = [&](int kind, const double2 *cur, double2 *nxt) {
@@ -1211,7 +1286,8 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
             hipLaunchKernelGGL(aberth_control, dim3(control_groups), dim3(CONTROL_THREADS), 0,
                                rs, c->fronts.as<Front>(), c->counts.as<int32_t>(), F, dctl,
                                max_cold, max_warm, wf, c->vieta.as<double4>(),
-                               c->reals_d.as<Real>(), c->etab.as<double2>(), fronts_per_group);
+                               c->reals_d.as<Real>(), c->etab.as<double2>(), fronts_per_group,
+                               p->predictor);
             hipLaunchKernelGGL(control_end, dim3(1), dim3(64), 0, rs, dctl, wf);
             parity ^= 1;
         }

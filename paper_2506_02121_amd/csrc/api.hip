@@ -143,7 +143,7 @@ void mlcc_destroy(mlcc_ctx *ctx)
     (void)hipStreamSynchronize(c.stream);
     DevBuf *bufs[] = {&c.stars, &c.mass, &c.stars4, &c.iter[0], &c.iter[1], &c.flagrow, &c.fronts,
                       &c.counts, &c.control, &c.etab, &c.bnd, &c.perm, &c.match_aux,
-                      &c.relabel, &c.workflags, &c.vieta, &c.reals_d, &c.bmap, &c.diff,
+                      &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.reals_d, &c.bmap, &c.diff,
                       &c.err, &c.edt_col};
     for (DevBuf *b : bufs) b->release();
     if (c.own_stream) (void)hipStreamDestroy(c.own_stream);
@@ -170,8 +170,20 @@ void mlcc_cc_params_default(mlcc_cc_params *p, int64_t m_steps)
     p->tol_step = 1e-9;
     p->tol_inv_mu = 1e-9;
     p->timing = 0;
-    p->predictor = 0;
+    p->predictor = 2;
 }
+
+// Compensated (Neumaier) summation.
+struct Neumaier {
+    double s = 0.0, c = 0.0;
+    void add(double x)
+    {
+        const double t = s + x;
+        c += std::fabs(s) >= std::fabs(x) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    double value() const { return s + c; }
+};
 
 // Loads one or several star fields (concatenated; field r holds stars
 // [off[r], off[r+1])) and the per-field sums the root finder checks rows
@@ -231,18 +243,22 @@ static mlcc_status load_fields(Ctx &c, int32_t n_fields, const int64_t *off, con
             if (hx[idx[i]] == hx[idx[i - 1]] && hy[idx[i]] == hy[idx[i - 1]])
                 return fail(MLCC_ERR_INVALID, "stars %lld and %lld share a position",
                             (long long)idx[i - 1], (long long)idx[i]);
-        // row identities of the root finder: sum z_i, sum z_i^2, total mass
+        // row identities of the root finder: sum z_i, sum z_i^2 (compensated
+        // sums), total mass
+        Neumaier s1r, s1i, s2r, s2i;
         for (int64_t i = i0; i < i1; ++i) {
-            h.sum_z.x += hx[i];
-            h.sum_z.y += hy[i];
-            h.sum_z2.x += hx[i] * hx[i] - hy[i] * hy[i];
-            h.sum_z2.y += 2.0 * hx[i] * hy[i];
+            s1r.add(hx[i]);
+            s1i.add(hy[i]);
+            s2r.add(hx[i] * hx[i] - hy[i] * hy[i]);
+            s2i.add(2.0 * hx[i] * hy[i]);
             const double r2 = hx[i] * hx[i] + hy[i] * hy[i];
             h.sum_abs_z += std::sqrt(r2);
             h.sum_abs_z2 += r2;
             h.max_abs_z = std::max(h.max_abs_z, std::sqrt(r2));
             h.mass_total += hm[i];
         }
+        h.sum_z = make_double2(s1r.value(), s1i.value());
+        h.sum_z2 = make_double2(s2r.value(), s2i.value());
     }
     std::vector<double> xy(2 * n), xym(4 * n);
     for (int64_t i = 0; i < n; ++i) {

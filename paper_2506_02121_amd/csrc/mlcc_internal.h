@@ -67,6 +67,12 @@ struct Front {
     int32_t blk0;     // first block of this front in the launch grid
     int32_t hist;     // finished rows of this subchain behind the current row (<= 3)
     int32_t fresh;    // 1 until the first pass over the current row has run
+    int32_t tried;    // mixed mode: TRIED_F32 | TRIED_POLISH done on the current row
+    int32_t f32;      // FP32 sweeps on the current row
+    int32_t best;     // fewest roots still moving after an FP32 sweep (cold start)
+    int32_t stall;    // FP32 sweeps since that count last fell
+    int32_t passes_row; // passes of any kind on the current row
+    int32_t pad_;
     int64_t it_off;   // first element of its roots in the iterate and flag arrays
 };
 
@@ -80,7 +86,7 @@ struct Real {
     double m0;          // the common mass (equal-mass kernels)
     double gamma, a, a1;   // shear, 1 - kappa_s, |1 - kappa_s|
     double sz_r, sz_i, sz2_r, sz2_i, M;   // sum z_i, sum z_i^2, sum m_i (row identities)
-    double tol1, tol2;  // tolerances of the two row identities
+    double tol1, tol2;  // rounding of the reference values of the two row identities
 };
 
 // Host-side description of one star field.
@@ -93,6 +99,7 @@ struct RealHost {
 };
 enum { FRONT_IDLE = 0, FRONT_ACTIVE = 1, FRONT_DONE = 2, FRONT_FAILED = 3 };
 enum { PH_F64 = 0, PH_F32 = 1, PH_POLISH = 2 };
+enum { TRIED_F32 = 1, TRIED_POLISH = 2 };
 
 // Device-side totals of the root finder.
 struct Control {
@@ -138,7 +145,8 @@ struct Ctx {
     DevBuf match_aux; // matching workspace
     DevBuf relabel;   // scratch rows for the in-place relabel
     DevBuf workflags; // int32[poll batch]: phases active in round i
-    DevBuf vieta;     // double4[blocks]: per-block row sums (mixed mode)
+    DevBuf vieta;     // double4[2 * blocks]: per-block row sums and error terms (mixed mode)
+    DevBuf errbuf;    // double[F * n_r]: estimated error of each polished root
     DevBuf reals_d;   // Real[n_real]
     DevBuf bmap;      // int2[blocks]: (front, block within front)
 

@@ -205,7 +205,7 @@ class Context:
                              max_iter_warm: int = 100, timing: bool = False,
                              chain_next: bool = True, caustics: bool = False, out=None,
                              caustics_out=None, raise_on_error: bool = True,
-                             precision: str = "fp64", predictor: int = 0):
+                             precision: str = "fp64", predictor: int = 2):
         """Returns (roots_re, roots_im, chain_next, stats, status), or with
         caustics=True (roots_re, roots_im, caus_re, caus_im, chain_next, stats,
         status).  One field: arrays are (m_steps + 1, 2N) float64 device

@@ -235,7 +235,8 @@ def test_predictor_matches_oracle(ctx, case):
         f = fields.tiny_field(0)
     else:
         f = fields.random_field(11, n, kappa_star=ks, kappa_s=kap_s, gamma=g, masses=masses)
-    R0, _, st0, _ = gpu_roots(ctx, f, m_steps, n_subchains=S, precision=precision)
+    R0, cn0, st0, _ = gpu_roots(ctx, f, m_steps, n_subchains=S, precision=precision,
+                                predictor=0)
     R, cn, st, _ = gpu_roots(ctx, f, m_steps, n_subchains=S, precision=precision,
                              predictor=pred)
     W_fused = gpu_roots.caustics
@@ -249,9 +250,11 @@ def test_predictor_matches_oracle(ctx, case):
     assert np.max(np.abs(R[-1] - R[0][cn])) < 1e-8
     R_s, cn_s, _ = oracle.critical_curves(f, m_steps, n_sub=st["n_subchains"])
     colwise = float(np.max(np.abs(R - R_s)))
-    print(f"[{name}] column-wise distance to the oracle with S={st['n_subchains']}: {colwise:.3e}")
-    assert colwise < 1e-8
-    assert np.array_equal(cn, cn_s)
+    colwise0 = float(np.max(np.abs(R0 - R_s)))
+    print(f"[{name}] column-wise distance to the oracle with S={st['n_subchains']}: "
+          f"{colwise:.3e} (predictor {pred}), {colwise0:.3e} (previous-row start)")
+    assert colwise < 1e-8 and colwise0 < 1e-8
+    assert np.array_equal(cn, cn_s) and np.array_equal(cn0, cn_s)
     W_ref = oracle.lens_map(f, R_s)
     bound = np.stack([parity.root_bound(f, oracle.eval_F(f, oracle.phase(j, m_steps), R_s[j])[1])
                       for j in range(m_steps + 1)])
