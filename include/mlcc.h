@@ -192,6 +192,20 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
                                       mlcc_cc_stats *stats);
 
 /*
+ * find_critical_curves_batched -- mlcc_find_critical_curves over the fields
+ * of mlcc_set_lenses_batched (one field after mlcc_set_lenses), with the
+ * layout made explicit: root_offsets (host int64[n_fields + 1], or NULL)
+ * receives the first element of each field's (m+1) x 2N_r block in roots_*
+ * and caustics_*, root_offsets[n_fields] the total; chain_next of field r
+ * starts at 2 star_offsets[r].  Everything else as mlcc_find_critical_curves.
+ */
+mlcc_status mlcc_find_critical_curves_batched(mlcc_ctx *ctx, const mlcc_cc_params *params,
+                                              int64_t *root_offsets, double *roots_re,
+                                              double *roots_im, double *caustics_re,
+                                              double *caustics_im, int32_t *chain_next,
+                                              mlcc_cc_stats *stats);
+
+/*
  * map_caustics -- the lens equation (Sec. 3.1, infinite sheet of App. A) at
  * `count` points: w = (1 - kappa_s) z + gamma conj(z) - sum_i m_i / conj(z - z_i).
  * Applied to the roots it gives the caustics.  z_re, z_im, w_re, w_im:

@@ -49,12 +49,13 @@ __device__ __forceinline__ double rcp_refined(double x)
 }
 
 // The hardware estimate v_rcp_f64 has relative error ~2^-24.4.  Star terms
-// take 2 refinement steps (fully accurate): F itself must be exact to the
-// last bits.  The root-root sum R only enters the step as F * (2 S1 - R);
+// take one refinement step (relative error ~2^-47): F then carries errors of
+// a few 1e-15 of its terms, far below what moves a root by the 1e-9 cutoff.
+// The root-root sum R only enters the step as F * (2 S1 - R);
 // that factor vanishes at a zero of F, so an error in R cannot move a
 // converged root, it only perturbs the path at second order in the error
 // of the iterate.  R therefore uses the unrefined estimate.
-constexpr int RCP_STAR = 2;
+constexpr int RCP_STAR = 1;
 constexpr int RCP_ROOT = 0;
 
 // Streams the records p[0..n) through body(i, rec) for a one-wave work
@@ -129,7 +130,9 @@ __device__ __forceinline__ void wave_sum(double &v)
 // Running sums for one root z, u_i = 1/(z - z_i):
 //   s1 = sum u_i                (for P'/P = F'/F + 2 s1)
 //   s0 = sum m_i u_i            (lens mapping; equals m0 s1 for equal masses)
-//   s2 = sum m_i u_i^2          (F = gamma + s2 - (1 - kappa_s) e^{-i phi})
+//   s2 = sum m_i u_i^2          (F = gamma + s2 - (1 - kappa_s) e^{-i phi});
+//                               while accumulating, s2i holds sum m_i ux uy
+//                               and finish() turns it into Im s2 = -2 that
 //   s3 = sum m_i u_i^3          (F' = -2 s3)
 //   R  = sum_{r != k} 1/(z - z_r)
 // For equal masses the m_i factors are left out and applied once at the end.
@@ -148,30 +151,27 @@ __device__ __forceinline__ void add_star(Sums &S, double zr, double zi, const T 
     const double dx = zr - s.x;
     const double dy = zi - s.y;
     const double inv = rcp_refined<RCP_STAR>(fma(dx, dx, dy * dy));
-    // u = ux - i uy = conj(d) / |d|^2
+    // u = conj(d) / |d|^2 = ux - i uy, with a = ux^2, b = uy^2:
+    //   u^2 = (a - b) - 2 i ux uy,   u^3 = ux (a - 3b) + i uy (b - 3a)
     const double ux = dx * inv;
     const double uy = dy * inv;
+    const double a = ux * ux, b = uy * uy;
     S.s1r += ux;
     S.s1i -= uy;
-    // u^2 = vx + i vy
-    const double vx = fma(ux, ux, -uy * uy);
-    const double vy = -2.0 * ux * uy;
-    // u^3 = u^2 u
-    const double tx = fma(vx, ux, vy * uy);
-    const double ty = fma(vy, ux, -vx * uy);
     if (EQUAL) {
-        S.s2r += vx;
-        S.s2i += vy;
-        S.s3r += tx;
-        S.s3i += ty;
+        S.s2r += a - b;
+        S.s2i = fma(ux, uy, S.s2i);
+        S.s3r = fma(ux, fma(-3.0, b, a), S.s3r);
+        S.s3i = fma(uy, fma(-3.0, a, b), S.s3i);
     } else {
         const double mi = StarRec<EQUAL>::mass(s);
-        S.s0r = fma(mi, ux, S.s0r);
-        S.s0i = fma(-mi, uy, S.s0i);
-        S.s2r = fma(mi, vx, S.s2r);
-        S.s2i = fma(mi, vy, S.s2i);
-        S.s3r = fma(mi, tx, S.s3r);
-        S.s3i = fma(mi, ty, S.s3i);
+        const double mux = mi * ux, muy = mi * uy;
+        S.s0r += mux;
+        S.s0i -= muy;
+        S.s2r = fma(mi, a - b, S.s2r);
+        S.s2i = fma(mux, uy, S.s2i);
+        S.s3r = fma(mux, fma(-3.0, b, a), S.s3r);
+        S.s3i = fma(muy, fma(-3.0, a, b), S.s3i);
     }
 }
 
@@ -208,6 +208,7 @@ __device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0
                                          double gamma, double a, double a1, double tol_step2,
                                          double tol_mu, int k)
 {
+    S.s2i *= -2.0;
     if (EQUAL) {   // every mass equals m0: the sums above left it out
         S.s0r = m0 * S.s1r;
         S.s0i = m0 * S.s1i;
@@ -261,6 +262,7 @@ template <class T> struct RoundArgs {
     double *out_re, *out_im, *caus_re, *caus_im;
     double2 *bnd;
     int32_t *counts;
+    int32_t *passupd;  // per front: roots updated by this round's pass (the control kernel sums them)
     Control *ctl;
     double4 *vieta;    // two per block: row sums, and their error terms
     double *errbuf;    // estimated error of each polished root
@@ -440,8 +442,7 @@ aberth_sweep_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
     }
     if (lane == 0) {
         if (n_after) atomicAdd(&A.counts[B.f], n_after);
-        atomicAdd(&A.ctl->updates, (unsigned long long)n_act);
-        atomicAdd(&A.ctl->star_updates, (unsigned long long)n_act * (unsigned)B.n_stars);
+        atomicAdd(&A.passupd[B.f], n_act);
     }
 }
 
@@ -490,18 +491,23 @@ aberth_sweep_f32(RoundArgs<typename StarRec<EQUAL>::T> A)
         [&](int, const T &s) {
             const float dx = (float)(zr - s.x), dy = (float)(zi - s.y);
             const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, dy * dy));
+            // as in add_star: p2i accumulates sum m ux uy (Im u^2 = -2 ux uy)
             const float ux = dx * inv, uy = dy * inv;
-            const float vx = fmaf(ux, ux, -uy * uy), vy = -2.0f * ux * uy;
-            const float tx = fmaf(vx, ux, vy * uy), ty = fmaf(vy, ux, -vx * uy);
+            const float a = ux * ux, b = uy * uy;
             p1r += ux;
             p1i -= uy;
             if (EQUAL) {
-                p2r += vx; p2i += vy;
-                p3r += tx; p3i += ty;
+                p2r += a - b;
+                p2i = fmaf(ux, uy, p2i);
+                p3r = fmaf(ux, fmaf(-3.0f, b, a), p3r);
+                p3i = fmaf(uy, fmaf(-3.0f, a, b), p3i);
             } else {
                 const float mi = (float)StarRec<EQUAL>::mass(s);
-                p2r = fmaf(mi, vx, p2r); p2i = fmaf(mi, vy, p2i);
-                p3r = fmaf(mi, tx, p3r); p3i = fmaf(mi, ty, p3i);
+                const float mux = mi * ux, muy = mi * uy;
+                p2r = fmaf(mi, a - b, p2r);
+                p2i = fmaf(mux, uy, p2i);
+                p3r = fmaf(mux, fmaf(-3.0f, b, a), p3r);
+                p3i = fmaf(muy, fmaf(-3.0f, a, b), p3i);
             }
         },
         [&]() {
@@ -534,6 +540,7 @@ aberth_sweep_f32(RoundArgs<typename StarRec<EQUAL>::T> A)
                     flush);
     stream_tiles_ex(zsrc + own_hi, n_r - own_hi, rt, to32, other, flush);
 
+    S2i *= -2.0;
     if (EQUAL) {
         S2r *= m0; S2i *= m0; S3r *= m0; S3i *= m0;
     }
@@ -556,8 +563,7 @@ aberth_sweep_f32(RoundArgs<typename StarRec<EQUAL>::T> A)
     const int n_moving = __popcll(__ballot(valid && !(mr * mr + mi * mi <= TOL_F32 * TOL_F32)));
     if (lane == 0) {
         if (n_moving) atomicAdd(&A.counts[B.f], n_moving);
-        atomicAdd(&A.ctl->updates_f32, (unsigned long long)n_valid);
-        atomicAdd(&A.ctl->star_updates_f32, (unsigned long long)n_valid * (unsigned)B.n_stars);
+        atomicAdd(&A.passupd[B.f], n_valid);
     }
 }
 
@@ -582,25 +588,32 @@ __device__ __forceinline__ void add_star_polish(PSums &S, double zr, double zi, 
     const double dx = zr - s.x;
     const double dy = zi - s.y;
     const double inv = rcp_refined<RCP_STAR>(fma(dx, dx, dy * dy));
+    // u = ux - i uy, a = ux^2, b = uy^2, v = a - b, c = ux uy:
+    //   u^2 = v - 2i c,  u^3 = ux (a - 3b) + i uy (b - 3a),  u^4 = v^2 - 4c^2 - 4i v c
+    // (s2i accumulates sum m c; polish_finish turns it into Im s2 = -2 that)
     const double ux = dx * inv;
     const double uy = dy * inv;
-    const double vx = fma(ux, ux, -uy * uy);
-    const double vy = -2.0 * ux * uy;
-    const double tx = fma(vx, ux, vy * uy);
-    const double ty = fma(vy, ux, -vx * uy);
-    const double qx = fma(vx, vx, -vy * vy);
-    const double qy = 2.0 * vx * vy;
+    const double a = ux * ux, b = uy * uy;
+    const double v = a - b, c = ux * uy;
     if (EQUAL) {
+        const double c4 = -4.0 * c;
         S.s0r += ux; S.s0i -= uy;
-        S.s2r += vx; S.s2i += vy;
-        S.s3r += tx; S.s3i += ty;
-        S.s4r += qx; S.s4i += qy;
+        S.s2r += v; S.s2i += c;
+        S.s3r = fma(ux, fma(-3.0, b, a), S.s3r);
+        S.s3i = fma(uy, fma(-3.0, a, b), S.s3i);
+        S.s4r = fma(v, v, S.s4r);
+        S.s4r = fma(c4, c, S.s4r);
+        S.s4i = fma(c4, v, S.s4i);
     } else {
         const double mi = StarRec<EQUAL>::mass(s);
+        const double mv = mi * v, mc = mi * c, mc4 = -4.0 * mc;
         S.s0r = fma(mi, ux, S.s0r); S.s0i = fma(-mi, uy, S.s0i);
-        S.s2r = fma(mi, vx, S.s2r); S.s2i = fma(mi, vy, S.s2i);
-        S.s3r = fma(mi, tx, S.s3r); S.s3i = fma(mi, ty, S.s3i);
-        S.s4r = fma(mi, qx, S.s4r); S.s4i = fma(mi, qy, S.s4i);
+        S.s2r += mv; S.s2i += mc;
+        S.s3r = fma(mi * ux, fma(-3.0, b, a), S.s3r);
+        S.s3i = fma(mi * uy, fma(-3.0, a, b), S.s3i);
+        S.s4r = fma(mv, v, S.s4r);
+        S.s4r = fma(mc4, c, S.s4r);
+        S.s4i = fma(mc4, v, S.s4i);
     }
 }
 
@@ -613,6 +626,7 @@ __device__ __forceinline__ Update polish_finish(PSums S, double zr, double zi, d
                                                 double2 e, double gamma, double a, double tol,
                                                 int k)
 {
+    S.s2i *= -2.0;
     if (EQUAL) {
         S.s0r *= m0; S.s0i *= m0; S.s2r *= m0; S.s2i *= m0;
         S.s3r *= m0; S.s3i *= m0; S.s4r *= m0; S.s4i *= m0;
@@ -734,10 +748,7 @@ newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
         A.vieta[2 * blockIdx.x] = make_double4(s1r, s1i, s2r, s2i);
         A.vieta[2 * blockIdx.x + 1] = make_double4(t_e, t_e2, t_a, t_a2);
         if (n_after) atomicAdd(&A.counts[B.f], n_after);
-        if (n_act) {
-            atomicAdd(&A.ctl->polish_updates, (unsigned long long)n_act);
-            atomicAdd(&A.ctl->star_updates_polish, (unsigned long long)n_act * (unsigned)B.n_stars);
-        }
+        if (n_act) atomicAdd(&A.passupd[B.f], n_act);
     }
 }
 
@@ -862,10 +873,11 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
                Control *__restrict__ ctl, int32_t max_cold, int32_t max_warm,
                int32_t *__restrict__ workflag, const double4 *__restrict__ vieta,
                const Real *__restrict__ reals, const double2 *__restrict__ unit,
-               int32_t fronts_per_group, int32_t predictor)
+               int32_t fronts_per_group, int32_t predictor, int32_t *__restrict__ passupd)
 {
     __shared__ int32_t st[4096];
     __shared__ int32_t s_active, s_live;
+    __shared__ unsigned long long s_upd[3], s_star[3];
     const int tid = threadIdx.x;
     const int f0 = blockIdx.x * fronts_per_group;
     const int f1 = min(n_fronts, f0 + fronts_per_group);
@@ -873,12 +885,20 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
         s_active = 0;
         s_live = 0;
     }
+    if (tid < 3) s_upd[tid] = s_star[tid] = 0ull;
+    unsigned long long my_upd[3] = {0ull, 0ull, 0ull}, my_star[3] = {0ull, 0ull, 0ull};
     for (int f = f0 + tid; f < f1; f += CONTROL_THREADS) st[f - f0] = fronts[f].state;
     __syncthreads();
     for (int f = f0 + tid; f < f1; f += CONTROL_THREADS) {
         if (st[f - f0] != FRONT_ACTIVE) continue;
         Front fr = fronts[f];
         atomicOr(&s_live, 1 << fr.phase);
+        {   // this round's updates of the front, by pass kind (FLOP counts weigh them by N)
+            const unsigned long long u = (unsigned)passupd[f];
+            passupd[f] = 0;
+            my_upd[fr.phase] += u;
+            my_star[fr.phase] += u * (unsigned)reals[fr.real].n_stars;
+        }
         const int32_t c = counts[f];
         counts[f] = 0;
         fr.src = f;
@@ -960,7 +980,27 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
         }
         fronts[f] = fr;
     }
+    for (int q = 0; q < 3; ++q) {
+        if (my_upd[q]) {
+            atomicAdd(&s_upd[q], my_upd[q]);
+            atomicAdd(&s_star[q], my_star[q]);
+        }
+    }
     __syncthreads();
+    if (tid == 0) {
+        if (s_upd[PH_F64]) {
+            atomicAdd(&ctl->updates, s_upd[PH_F64]);
+            atomicAdd(&ctl->star_updates, s_star[PH_F64]);
+        }
+        if (s_upd[PH_F32]) {
+            atomicAdd(&ctl->updates_f32, s_upd[PH_F32]);
+            atomicAdd(&ctl->star_updates_f32, s_star[PH_F32]);
+        }
+        if (s_upd[PH_POLISH]) {
+            atomicAdd(&ctl->polish_updates, s_upd[PH_POLISH]);
+            atomicAdd(&ctl->star_updates_polish, s_star[PH_POLISH]);
+        }
+    }
     int mine = 0;
     for (int f = f0 + tid; f < f1; f += CONTROL_THREADS)
         mine += (st[f - f0] == FRONT_ACTIVE || st[f - f0] == FRONT_IDLE);
@@ -993,46 +1033,81 @@ __global__ void control_end(Control *__restrict__ ctl, const int32_t *__restrict
 // Subchains and the autotuner
 // ---------------------------------------------------------------------------
 
-// Subchain counts must divide m/2 (integer centre rows).
-// Cost model of one field's run with S subchains, in units of one root
-// update's star-and-root work (N + 2N terms): every subchain pays a cold
-// start (~cold sweeps of all 2N roots) on top of the ~u updates per root and
-// row that the rows need whatever S is; the critical path is the longest
-// front, (m / 2S) rows of ~rounds_per_row rounds each, and a round costs at
-// least one wave's full pass.
+// Subchain counts S must divide m/2 (integer centre rows).  The autotuner
+// prices a run with S subchains from measured costs of the kernels on
+// gfx950 and picks the cheapest S.
+//
+// Cost of one wave's pass over a field of N stars and n_r = 2N roots, in
+// SIMD cycles (issue costs measured per wave64 instruction: FP64 add/FMA
+// ~4.4-5.4 cycles, v_rcp_f64 ~16, FP32 ~2.3, v_rcp_f32 ~8; the kernels
+// spend ~20 instructions per star term and ~7 per root term):
+//   FP64 Aberth sweep   112 N + 47 n_r
+//   FP32 Aberth sweep    56 N + 22 n_r
+//   FP64 Newton polish  141 N
+// A run does, per field, u (m + S) row passes of every block (u ~ 1.03
+// with the chain predictor, ~2 without; in the mixed form a row without a
+// prediction takes an FP32 sweep and a polish) plus S cold starts of ~27
+// sweeps.  Its time is that work over the 1024 SIMDs (fewer when fewer than
+// two waves per SIMD are in flight), plus, for every round, the tail of a
+// round: ~0.8 of the longest wave pass, plus ~40 us of launches and control.
+// The number of rounds is ~2.1 per row of a front's m / 2S rows, plus the
+// cold start.
 struct TuneModel {
-    double cold_sweeps = 25.0, updates_per_row = 2.05, rounds_per_row = 3.0;
+    double cold_sweeps = 27.0, rounds_per_row = 2.1, tail = 0.8, round_us = 40.0;
+    double clock_hz = 2.4e9, simds = 1024.0;
 };
 
-// Picks S for every field of a call.  All fields share one round clock, so a
-// common S keeps their fronts in step; it is the divisor of m/2 that
-// minimises max(total work / machine, critical path) under the model above,
-// with the machine taken as 1024 SIMDs x 10 resident waves, among the
-// divisors that leave every subchain at least 64 rows.
-static int autotune_subchains(const std::vector<RealHost> &reals, int64_t m, const TuneModel &tm)
+static double pass_cycles(int kind, double n)
+{
+    const double n_r = 2.0 * n;
+    if (kind == PH_F64) return 112.0 * n + 47.0 * n_r;
+    if (kind == PH_F32) return 56.0 * n + 22.0 * n_r;
+    return 141.0 * n;
+}
+
+static double predicted_seconds(const std::vector<RealHost> &reals, int64_t m, int64_t s, bool mixed,
+                         int predictor)
+{
+    const TuneModel tm;
+    double work = 0.0, blocks_all = 0.0, longest = 0.0;
+    for (const RealHost &r : reals) {
+        const double n = (double)r.n, blocks = std::ceil(2.0 * n / 64.0);
+        double row, cold;
+        if (!mixed) {
+            row = (predictor > 0 ? 1.03 : 2.0) * pass_cycles(PH_F64, n);
+            cold = tm.cold_sweeps * pass_cycles(PH_F64, n);
+        } else {
+            row = 1.02 * pass_cycles(PH_POLISH, n) +
+                  (predictor > 0 ? 0.0 : pass_cycles(PH_F32, n));
+            cold = tm.cold_sweeps * pass_cycles(PH_F32, n) + pass_cycles(PH_POLISH, n);
+        }
+        work += blocks * (row * (double)(m + s) + cold * (double)s);
+        blocks_all += blocks;
+        longest = std::max(longest, mixed ? pass_cycles(PH_POLISH, n) : pass_cycles(PH_F64, n));
+    }
+    // about half of the 2S fronts are in a full pass at any time
+    const double waves = (double)s * blocks_all;
+    const double simds = std::min(tm.simds, std::max(1.0, waves / 2.0));
+    const double rounds = tm.rounds_per_row * (double)(m / 2) / (double)s + tm.cold_sweeps;
+    return work / (simds * tm.clock_hz) +
+           rounds * (tm.tail * longest / tm.clock_hz + tm.round_us * 1e-6);
+}
+
+// Picks S for every field of a call (all fields share one round clock, so a
+// common S keeps their fronts in step): the divisor of m/2 with the lowest
+// predicted time among those that leave every subchain at least 16 rows and
+// keep the front table within MAX_FRONTS.
+static int autotune_subchains(const std::vector<RealHost> &reals, int64_t m, bool mixed,
+                              int predictor)
 {
     const int64_t half = m / 2;
+    const int64_t s_max = std::max<int64_t>(
+        1, std::min<int64_t>(MAX_FRONTS / (2 * (int64_t)reals.size()), m / 16));
     double best = 1e300;
     int best_s = 1;
-    double max_pass = 0.0;   // one wave's pass over the largest field
-    for (const RealHost &r : reals) max_pass = std::max(max_pass, 3.0 * (double)r.n);
-    const double slots = 1024.0 * 10.0;
-    // at least 64 rows per subchain: shorter ones are mostly cold start
-    const int64_t s_max = std::max<int64_t>(
-        1, std::min<int64_t>(MAX_FRONTS / (2 * (int64_t)reals.size()), m / 64));
-    for (int64_t s = 1; s <= std::min<int64_t>(half, std::min<int64_t>(s_max, 2048)); ++s) {
+    for (int64_t s = 1; s <= std::min<int64_t>(half, std::min<int64_t>(s_max, 4096)); ++s) {
         if (half % s) continue;
-        double work = 0.0, waves = 0.0;
-        for (const RealHost &r : reals) {
-            const double n_r = 2.0 * (double)r.n, terms = 3.0 * (double)r.n;
-            const double blocks = std::ceil(n_r / 64.0);
-            work += terms * blocks * (tm.updates_per_row * (double)(m + s) +
-                                      tm.cold_sweeps * (double)s);
-            waves += 2.0 * (double)s * blocks;
-        }
-        const double rounds = tm.rounds_per_row * (double)half / (double)s + tm.cold_sweeps;
-        const double occupancy = std::min(1.0, waves / slots);
-        const double t = std::max(work / (slots * std::max(occupancy, 1e-3)), rounds * max_pass);
+        const double t = predicted_seconds(reals, m, s, mixed, predictor);
         if (t < best * 0.999) {
             best = t;
             best_s = (int)s;
@@ -1055,7 +1130,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     // one field with equal masses: (x, y) records, the mass applied once
     const bool equal = !c->batched && c->equal_mass;
     int S = p->n_subchains;
-    if (S <= 0) S = autotune_subchains(c->reals, m, TuneModel{});
+    if (S <= 0) S = autotune_subchains(c->reals, m, mixed, p->predictor);
     if ((m / 2) % S) return fail(MLCC_ERR_INVALID, "n_subchains=%d must divide m/2", S);
     const int64_t L = m / S;
     const int max_cold = p->max_iter_cold > 0 ? p->max_iter_cold : 500;
@@ -1134,6 +1209,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     MLCC_TRY(c->flagrow.reserve((size_t)it_total * sizeof(int32_t)));
     MLCC_TRY(c->fronts.reserve((size_t)F * sizeof(Front)));
     MLCC_TRY(c->counts.reserve((size_t)F * sizeof(int32_t)));
+    MLCC_TRY(c->passupd.reserve((size_t)F * sizeof(int32_t)));
     MLCC_TRY(c->control.reserve(sizeof(Control)));
     MLCC_TRY(c->etab.reserve((size_t)(m + 1) * sizeof(double2)));
     MLCC_TRY(c->bnd.reserve((size_t)std::max<int64_t>(bnd_total, 1) * sizeof(double2)));
@@ -1164,6 +1240,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     MLCC_HIP(hipMemcpyAsync(c->control.p, &ctl0, sizeof ctl0, hipMemcpyHostToDevice, c->stream));
     MLCC_HIP(hipMemsetAsync(c->flagrow.p, 0xff, (size_t)it_total * sizeof(int32_t), c->stream));
     MLCC_HIP(hipMemsetAsync(c->counts.p, 0, F * sizeof(int32_t), c->stream));
+    MLCC_HIP(hipMemsetAsync(c->passupd.p, 0, F * sizeof(int32_t), c->stream));
     if (equal)
         hipLaunchKernelGGL(seed_centres<double2>, dim3((unsigned)nblocks), dim3(64), 0, c->stream,
                            c->stars.as<double2>(), c->reals_d.as<Real>(), c->fronts.as<Front>(),
@@ -1204,6 +1281,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         A.caus_im = caus_im;
         A.bnd = c->bnd.as<double2>();
         A.counts = c->counts.as<int32_t>();
+        A.passupd = c->passupd.as<int32_t>();
         A.ctl = c->control.as<Control>();
         A.vieta = c->vieta.as<double4>();
         A.predictor = p->predictor;
@@ -1287,7 +1365,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
                                rs, c->fronts.as<Front>(), c->counts.as<int32_t>(), F, dctl,
                                max_cold, max_warm, wf, c->vieta.as<double4>(),
                                c->reals_d.as<Real>(), c->etab.as<double2>(), fronts_per_group,
-                               p->predictor);
+                               p->predictor, c->passupd.as<int32_t>());
             hipLaunchKernelGGL(control_end, dim3(1), dim3(64), 0, rs, dctl, wf);
             parity ^= 1;
         }
@@ -1454,17 +1532,19 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
             }
             MLCC_HIP(hipMemcpyAsync(perm, lab.data(), (size_t)perm_total * sizeof(int32_t),
                                     hipMemcpyHostToDevice, c->stream));
+            std::vector<RelabelJob> rj;
             for (int r = 0; r < n_real; ++r) {
                 const int64_t n_r = rd[r].n_r;
                 for (int s = 1; s < S; ++s) {
                     const int32_t *lb = perm + perm_off[r] + s * n_r;
-                    MLCC_TRY(relabel_rows(c, roots_re + rd[r].out_off, roots_im + rd[r].out_off,
-                                          n_r, s * L + 1, (s + 1) * L + 1, lb));
+                    rj.push_back(RelabelJob{roots_re + rd[r].out_off, roots_im + rd[r].out_off,
+                                            n_r, s * L + 1, (s + 1) * L + 1, lb});
                     if (caus_re)
-                        MLCC_TRY(relabel_rows(c, caus_re + rd[r].out_off, caus_im + rd[r].out_off,
-                                              n_r, s * L + 1, (s + 1) * L + 1, lb));
+                        rj.push_back(RelabelJob{caus_re + rd[r].out_off, caus_im + rd[r].out_off,
+                                                n_r, s * L + 1, (s + 1) * L + 1, lb});
                 }
             }
+            MLCC_TRY(relabel_all(c, rj));
             MLCC_HIP(hipStreamSynchronize(c->stream));
         }
         if (chain_next) {

@@ -143,7 +143,7 @@ void mlcc_destroy(mlcc_ctx *ctx)
     (void)hipStreamSynchronize(c.stream);
     DevBuf *bufs[] = {&c.stars, &c.mass, &c.stars4, &c.iter[0], &c.iter[1], &c.flagrow, &c.fronts,
                       &c.counts, &c.control, &c.etab, &c.bnd, &c.perm, &c.match_aux,
-                      &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.reals_d, &c.bmap, &c.diff,
+                      &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.passupd, &c.reals_d, &c.bmap, &c.diff,
                       &c.err, &c.edt_col};
     for (DevBuf *b : bufs) b->release();
     if (c.own_stream) (void)hipStreamDestroy(c.own_stream);
@@ -353,6 +353,25 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
     if (chain_next) MLCC_TRY(check_device_ptr(&c, chain_next, "chain_next"));
     clear_error();
     return find_critical_curves_impl(&c, &p, roots_re, roots_im, caustics_re, caustics_im,
+                                     chain_next, stats);
+}
+
+mlcc_status mlcc_find_critical_curves_batched(mlcc_ctx *ctx, const mlcc_cc_params *params,
+                                              int64_t *root_offsets, double *roots_re,
+                                              double *roots_im, double *caustics_re,
+                                              double *caustics_im, int32_t *chain_next,
+                                              mlcc_cc_stats *stats)
+{
+    if (!ctx || !params) return fail(MLCC_ERR_INVALID, "ctx or params is NULL");
+    Ctx &c = ctx->impl;
+    if (c.reals.empty()) return fail(MLCC_ERR_STATE, "call mlcc_set_lenses_batched first");
+    if (root_offsets) {
+        const int64_t rows = params->m_steps + 1;
+        for (size_t r = 0; r < c.reals.size(); ++r)
+            root_offsets[r] = rows * 2 * c.reals[r].star_off;
+        root_offsets[c.reals.size()] = rows * 2 * c.n;
+    }
+    return mlcc_find_critical_curves(ctx, params, roots_re, roots_im, caustics_re, caustics_im,
                                      chain_next, stats);
 }
 

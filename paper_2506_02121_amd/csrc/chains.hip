@@ -19,89 +19,120 @@ struct PairAux {
     unsigned long long maxbits; // bit pattern of the largest paired squared distance
 };
 
-template <bool INTERLEAVED>
+// A pairing job as the kernels see it.
+struct PairJobDev {
+    const double2 *a2;
+    const double *a_re, *a_im, *b_re, *b_im;
+    int32_t *perm;
+    int64_t n, hits_off;
+};
+
+// One launch for every job: block q works on job blk_job[q], points
+// 64 blk_idx[q] .. +63 of it.  Each lane scans the other copy and keeps the
+// nearest point; the hit counts and the largest distance go to the job's
+// slots.
 __global__ void __launch_bounds__(64)
-nearest_kernel(int32_t n, const double2 *__restrict__ a2, const double *__restrict__ a_re,
-               const double *__restrict__ a_im, const double *__restrict__ b_re,
-               const double *__restrict__ b_im, int32_t *__restrict__ perm,
-               int32_t *__restrict__ hits, PairAux *__restrict__ aux)
+nearest_jobs(const PairJobDev *__restrict__ jobs, const int2 *__restrict__ blk,
+             int32_t *__restrict__ hits, PairAux *__restrict__ aux)
 {
-    const int k = blockIdx.x * 64 + threadIdx.x;
+    const int2 q = blk[blockIdx.x];
+    const PairJobDev J = jobs[q.x];
+    const int64_t k = (int64_t)q.y * 64 + threadIdx.x;
     double ax = 0.0, ay = 0.0;
-    if (k < n) {
-        if (INTERLEAVED) {
-            const double2 a = a2[k];
-            ax = a.x;
-            ay = a.y;
+    if (k < J.n) {
+        if (J.a2) {
+            const double2 v = J.a2[k];
+            ax = v.x;
+            ay = v.y;
         } else {
-            ax = a_re[k];
-            ay = a_im[k];
+            ax = J.a_re[k];
+            ay = J.a_im[k];
         }
     }
     double best = INFINITY;
     int bi = -1;
-    for (int j = 0; j < n; ++j) {
-        const double dx = ax - b_re[j], dy = ay - b_im[j];
+    for (int j = 0; j < (int)J.n; ++j) {
+        const double dx = ax - J.b_re[j], dy = ay - J.b_im[j];
         const double d = fma(dx, dx, dy * dy);
         if (d < best) {
             best = d;
             bi = j;
         }
     }
-    if (k >= n) return;
-    perm[k] = bi;
+    if (k >= J.n) return;
+    J.perm[k] = bi;
     if (bi < 0) {
-        atomicOr(&aux->bad, 1);
+        atomicOr(&aux[q.x].bad, 1);
         return;
     }
-    atomicAdd(&hits[bi], 1);
+    atomicAdd(&hits[J.hits_off + bi], 1);
     // non-negative doubles order like their bit patterns
-    atomicMax(&aux->maxbits, (unsigned long long)__double_as_longlong(best));
+    atomicMax(&aux[q.x].maxbits, (unsigned long long)__double_as_longlong(best));
 }
 
-__global__ void check_hits(int32_t n, const int32_t *__restrict__ hits, PairAux *__restrict__ aux)
+// Every point of the second copy must be hit exactly once.
+__global__ void check_hits_jobs(const int64_t *__restrict__ hits_off, int32_t n_jobs,
+                                const int32_t *__restrict__ hits, int64_t total,
+                                PairAux *__restrict__ aux)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n && hits[k] != 1) atomicOr(&aux->bad, 1);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total || hits[t] == 1) return;
+    int lo = 0, hi = n_jobs - 1;   // last job with hits_off <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (hits_off[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    atomicOr(&aux[lo].bad, 1);
 }
 
 mlcc_status pair_all(Ctx *c, const std::vector<PairJob> &jobs, double tol, double *maxdist)
 {
     if (maxdist) *maxdist = 0.0;
     if (jobs.empty()) return MLCC_OK;
+    const int32_t nj = (int32_t)jobs.size();
+    std::vector<PairJobDev> jd(nj);
+    std::vector<int64_t> hoff(nj);
+    std::vector<int2> blk;
     int64_t total = 0;
-    for (const PairJob &j : jobs) {
+    for (int32_t i = 0; i < nj; ++i) {
+        const PairJob &j = jobs[i];
         if (j.n > 0x7fffffff) return fail(MLCC_ERR_INVALID, "row too long to pair");
+        jd[i] = PairJobDev{j.a2, j.a_re, j.a_im, j.b_re, j.b_im, j.perm, j.n, total};
+        hoff[i] = total;
+        for (int64_t q = 0; q < ceil_div(j.n, 64); ++q) blk.push_back(make_int2(i, (int)q));
         total += j.n;
     }
-    const size_t aux_bytes = jobs.size() * sizeof(PairAux);
-    MLCC_TRY(c->match_aux.reserve(aux_bytes + (size_t)total * sizeof(int32_t)));
-    PairAux *aux = c->match_aux.as<PairAux>();
-    int32_t *hits = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(c->match_aux.p) + aux_bytes);
-    MLCC_HIP(hipMemsetAsync(c->match_aux.p, 0, aux_bytes + (size_t)total * sizeof(int32_t),
-                            c->stream));
-    int64_t off = 0;
-    for (size_t i = 0; i < jobs.size(); ++i) {
-        const PairJob &j = jobs[i];
-        const unsigned blocks = (unsigned)ceil_div(j.n, 64);
-        if (j.a2)
-            hipLaunchKernelGGL(nearest_kernel<true>, dim3(blocks), dim3(64), 0, c->stream,
-                               (int32_t)j.n, j.a2, nullptr, nullptr, j.b_re, j.b_im, j.perm,
-                               hits + off, aux + i);
-        else
-            hipLaunchKernelGGL(nearest_kernel<false>, dim3(blocks), dim3(64), 0, c->stream,
-                               (int32_t)j.n, nullptr, j.a_re, j.a_im, j.b_re, j.b_im, j.perm,
-                               hits + off, aux + i);
-        hipLaunchKernelGGL(check_hits, dim3((unsigned)ceil_div(j.n, 256)), dim3(256), 0,
-                           c->stream, (int32_t)j.n, hits + off, aux + i);
-        off += j.n;
-    }
+    // device layout: aux[nj] | hits[total] | jobs[nj] | hits_off[nj] | blk[...]
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_hits = al(nj * sizeof(PairAux));
+    const size_t o_jobs = al(o_hits + (size_t)total * sizeof(int32_t));
+    const size_t o_hoff = al(o_jobs + nj * sizeof(PairJobDev));
+    const size_t o_blk = al(o_hoff + nj * sizeof(int64_t));
+    const size_t bytes = o_blk + blk.size() * sizeof(int2);
+    MLCC_TRY(c->match_aux.reserve(bytes));
+    char *base = static_cast<char *>(c->match_aux.p);
+    PairAux *aux = reinterpret_cast<PairAux *>(base);
+    int32_t *hits = reinterpret_cast<int32_t *>(base + o_hits);
+    MLCC_HIP(hipMemsetAsync(base, 0, o_jobs, c->stream));
+    MLCC_HIP(hipMemcpyAsync(base + o_jobs, jd.data(), nj * sizeof(PairJobDev),
+                            hipMemcpyHostToDevice, c->stream));
+    MLCC_HIP(hipMemcpyAsync(base + o_hoff, hoff.data(), nj * sizeof(int64_t),
+                            hipMemcpyHostToDevice, c->stream));
+    MLCC_HIP(hipMemcpyAsync(base + o_blk, blk.data(), blk.size() * sizeof(int2),
+                            hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(nearest_jobs, dim3((unsigned)blk.size()), dim3(64), 0, c->stream,
+                       reinterpret_cast<const PairJobDev *>(base + o_jobs),
+                       reinterpret_cast<const int2 *>(base + o_blk), hits, aux);
+    hipLaunchKernelGGL(check_hits_jobs, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0,
+                       c->stream, reinterpret_cast<const int64_t *>(base + o_hoff), nj, hits,
+                       total, aux);
     MLCC_HIP(hipGetLastError());
-    std::vector<PairAux> h(jobs.size());
-    MLCC_HIP(hipMemcpyAsync(h.data(), aux, aux_bytes, hipMemcpyDeviceToHost, c->stream));
+    std::vector<PairAux> h(nj);
+    MLCC_HIP(hipMemcpyAsync(h.data(), aux, nj * sizeof(PairAux), hipMemcpyDeviceToHost, c->stream));
+    // (the host vectors above stay alive until this synchronisation)
     MLCC_HIP(hipStreamSynchronize(c->stream));
     double md = 0.0;
-    for (size_t i = 0; i < jobs.size(); ++i) {
+    for (int32_t i = 0; i < nj; ++i) {
         double d2;
         memcpy(&d2, &h[i].maxbits, sizeof d2);
         const double d = std::sqrt(d2);
@@ -116,39 +147,97 @@ mlcc_status pair_all(Ctx *c, const std::vector<PairJob> &jobs, double tol, doubl
     return MLCC_OK;
 }
 
-// scratch[b][label[k]] = src[b][k] for nb rows
-__global__ void scatter_rows(int64_t n_r, int64_t nb, const double *__restrict__ src_re,
-                             const double *__restrict__ src_im, const int32_t *__restrict__ label,
-                             double *__restrict__ dst_re, double *__restrict__ dst_im)
+// A run of rows of one array whose columns are relabelled: new[b][label[k]]
+// = old[b][k] for b < rows.  `elem0` is its first element in the chunk's
+// scratch.
+struct RelabelSeg {
+    double *re, *im;
+    const int32_t *label;
+    int64_t n_r, rows, elem0;
+};
+
+__device__ __forceinline__ int find_seg(const RelabelSeg *segs, int nseg, int64_t t)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_r * nb) return;
-    const int64_t b = t / n_r, k = t - b * n_r;
-    const int64_t to = b * n_r + label[k];
-    dst_re[to] = src_re[t];
-    dst_im[to] = src_im[t];
+    int lo = 0, hi = nseg - 1;   // last segment with elem0 <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].elem0 <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
-mlcc_status relabel_rows(Ctx *c, double *re, double *im, int64_t n_r, int64_t row0,
-                         int64_t row1, const int32_t *label)
+__global__ void relabel_scatter(const RelabelSeg *__restrict__ segs, int32_t nseg, int64_t total,
+                                double *__restrict__ sre, double *__restrict__ sim)
 {
-    if (row1 <= row0) return MLCC_OK;
-    const int64_t budget = (int64_t)64 << 20; // bytes of scratch
-    int64_t B = std::max<int64_t>(1, budget / (2 * (int64_t)sizeof(double) * n_r));
-    B = std::min<int64_t>(B, row1 - row0);
-    MLCC_TRY(c->relabel.reserve((size_t)2 * B * n_r * sizeof(double)));
-    double *sre = c->relabel.as<double>(), *sim = sre + B * n_r;
-    for (int64_t r = row0; r < row1; r += B) {
-        const int64_t nb = std::min<int64_t>(B, row1 - r);
-        const int64_t tot = nb * n_r;
-        hipLaunchKernelGGL(scatter_rows, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0,
-                           c->stream, n_r, nb, re + r * n_r, im + r * n_r, label, sre, sim);
-        MLCC_HIP(hipGetLastError());
-        MLCC_HIP(hipMemcpyAsync(re + r * n_r, sre, tot * sizeof(double), hipMemcpyDeviceToDevice,
-                                c->stream));
-        MLCC_HIP(hipMemcpyAsync(im + r * n_r, sim, tot * sizeof(double), hipMemcpyDeviceToDevice,
-                                c->stream));
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const RelabelSeg g = segs[find_seg(segs, nseg, t)];
+    const int64_t e = t - g.elem0, b = e / g.n_r, k = e - b * g.n_r;
+    const int64_t to = g.elem0 + b * g.n_r + g.label[k];
+    sre[to] = g.re[e];
+    sim[to] = g.im[e];
+}
+
+__global__ void relabel_back(const RelabelSeg *__restrict__ segs, int32_t nseg, int64_t total,
+                             const double *__restrict__ sre, const double *__restrict__ sim)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const RelabelSeg g = segs[find_seg(segs, nseg, t)];
+    const int64_t e = t - g.elem0;
+    g.re[e] = sre[t];
+    g.im[e] = sim[t];
+}
+
+mlcc_status relabel_all(Ctx *c, const std::vector<RelabelJob> &jobs)
+{
+    if (jobs.empty()) return MLCC_OK;
+    const int64_t budget = (int64_t)16 << 20;   // elements per chunk (256 MiB of scratch)
+    // split the jobs into chunks of whole rows, at most `budget` elements each
+    std::vector<RelabelSeg> segs;
+    std::vector<std::pair<size_t, int64_t>> chunks;   // (first segment, elements)
+    int64_t fill = 0;
+    size_t first = 0;
+    for (const RelabelJob &j : jobs) {
+        if (j.n_r < 1 || j.n_r > budget)
+            return fail(MLCC_ERR_INVALID, "row of %lld roots too long to relabel",
+                        (long long)j.n_r);
+        int64_t r = j.row0;
+        while (r < j.row1) {
+            if (fill + j.n_r > budget) {
+                chunks.emplace_back(first, fill);
+                first = segs.size();
+                fill = 0;
+            }
+            const int64_t nb = std::min<int64_t>(j.row1 - r, (budget - fill) / j.n_r);
+            segs.push_back(RelabelSeg{j.re + r * j.n_r, j.im + r * j.n_r, j.label, j.n_r, nb, fill});
+            fill += nb * j.n_r;
+            r += nb;
+        }
     }
+    if (fill) chunks.emplace_back(first, fill);
+    int64_t max_fill = 0;
+    for (auto &ch : chunks) max_fill = std::max(max_fill, ch.second);
+    const size_t seg_bytes = (segs.size() * sizeof(RelabelSeg) + 255) & ~(size_t)255;
+    MLCC_TRY(c->relabel.reserve(seg_bytes + (size_t)2 * max_fill * sizeof(double)));
+    char *base = static_cast<char *>(c->relabel.p);
+    RelabelSeg *dsegs = reinterpret_cast<RelabelSeg *>(base);
+    double *sre = reinterpret_cast<double *>(base + seg_bytes), *sim = sre + max_fill;
+    MLCC_HIP(hipMemcpyAsync(dsegs, segs.data(), segs.size() * sizeof(RelabelSeg),
+                            hipMemcpyHostToDevice, c->stream));
+    for (size_t i = 0; i < chunks.size(); ++i) {
+        const size_t s0 = chunks[i].first;
+        const size_t s1 = i + 1 < chunks.size() ? chunks[i + 1].first : segs.size();
+        const int64_t tot = chunks[i].second;
+        const unsigned g = (unsigned)ceil_div(tot, 256);
+        hipLaunchKernelGGL(relabel_scatter, dim3(g), dim3(256), 0, c->stream, dsegs + s0,
+                           (int32_t)(s1 - s0), tot, sre, sim);
+        hipLaunchKernelGGL(relabel_back, dim3(g), dim3(256), 0, c->stream, dsegs + s0,
+                           (int32_t)(s1 - s0), tot, sre, sim);
+    }
+    MLCC_HIP(hipGetLastError());
+    // the segment table is read by the kernels: keep it until they are done
+    MLCC_HIP(hipStreamSynchronize(c->stream));
     return MLCC_OK;
 }
 

@@ -138,6 +138,7 @@ struct Ctx {
     DevBuf flagrow;   // int32[F * n_r]: row at which the root was flagged
     DevBuf fronts;    // Front[F]
     DevBuf counts;    // int32[F]: unflagged roots after the last sweep
+    DevBuf passupd;   // int32[F]: roots updated by the last round's pass
     DevBuf control;   // Control
     DevBuf etab;      // double2[m + 1]: (1 - kappa_s) e^{-i phi_j}
     DevBuf bnd;       // double2[(S - 1) * n_r]: duplicate boundary rows
@@ -177,8 +178,8 @@ mlcc_status launch_caustic_distances(Ctx *c, const mlcc_grid *g, const int32_t *
 
 // Nearest-neighbour pairing of two copies of one root set (chains.hip).
 // A job pairs n points a (double2 interleaved, or SoA planes) with n points b
-// (SoA planes): perm[k] = index in b nearest a[k].  Jobs are enqueued without
-// waiting; pair_collect checks them all at once and fails with
+// (SoA planes): perm[k] = index in b nearest a[k].  All jobs run in one
+// launch and are checked at once; the call fails with
 // MLCC_ERR_MATCH when a pairing is not one-to-one or a pair is further apart
 // than tol.  *maxdist receives the largest paired distance.
 struct PairJob {
@@ -188,9 +189,14 @@ struct PairJob {
     int64_t n;
 };
 mlcc_status pair_all(Ctx *c, const std::vector<PairJob> &jobs, double tol, double *maxdist);
-// Relabel rows [row0, row1) in place: new[j][label[k]] = old[j][k].
-mlcc_status relabel_rows(Ctx *c, double *re, double *im, int64_t n_r, int64_t row0,
-                         int64_t row1, const int32_t *label);
+// Relabel rows [row0, row1) of (re, im) in place: new[j][label[k]] =
+// old[j][k]; all jobs in a few chunked launches through context scratch.
+struct RelabelJob {
+    double *re, *im;
+    int64_t n_r, row0, row1;
+    const int32_t *label;
+};
+mlcc_status relabel_all(Ctx *c, const std::vector<RelabelJob> &jobs);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

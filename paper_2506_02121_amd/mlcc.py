@@ -33,7 +33,8 @@ MLCC_MIXED = 1
 
 EXPORTED = [
     "mlcc_create", "mlcc_destroy", "mlcc_set_stream", "mlcc_last_error", "mlcc_set_lenses",
-    "mlcc_set_lenses_batched", "mlcc_cc_params_default", "mlcc_find_critical_curves", "mlcc_map_caustics",
+    "mlcc_set_lenses_batched", "mlcc_cc_params_default", "mlcc_find_critical_curves",
+    "mlcc_find_critical_curves_batched", "mlcc_map_caustics",
     "mlcc_caustic_crossings", "mlcc_caustic_distances",
 ]
 
@@ -83,6 +84,8 @@ _SIG = {
     "mlcc_cc_params_default": ([ctypes.POINTER(CCParams), _i64], None),
     "mlcc_find_critical_curves": ([_vp, ctypes.POINTER(CCParams), _vp, _vp, _vp, _vp, _vp,
                                    ctypes.POINTER(CCStats)], ctypes.c_int),
+    "mlcc_find_critical_curves_batched": ([_vp, ctypes.POINTER(CCParams), _vp, _vp, _vp, _vp,
+                                           _vp, _vp, ctypes.POINTER(CCStats)], ctypes.c_int),
     "mlcc_map_caustics": ([_vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
     "mlcc_caustic_crossings": ([_vp, _i64, _i64, _vp, _vp, _vp, ctypes.POINTER(GridC), _vp],
                                ctypes.c_int),
@@ -236,8 +239,15 @@ class Context:
         cn = torch.empty(n_r, dtype=torch.int32, device=self.device) if chain_next else None
         st = CCStats()
         self._stream()
-        code = _lib.mlcc_find_critical_curves(self._h, ctypes.byref(p), _ptr(rr), _ptr(ri),
-                                              _ptr(cr), _ptr(ci), _ptr(cn), ctypes.byref(st))
+        if self.star_offsets is None:
+            code = _lib.mlcc_find_critical_curves(self._h, ctypes.byref(p), _ptr(rr), _ptr(ri),
+                                                  _ptr(cr), _ptr(ci), _ptr(cn), ctypes.byref(st))
+        else:
+            offs = (ctypes.c_int64 * len(self.star_offsets))()
+            code = _lib.mlcc_find_critical_curves_batched(self._h, ctypes.byref(p), offs, _ptr(rr),
+                                                          _ptr(ri), _ptr(cr), _ptr(ci), _ptr(cn),
+                                                          ctypes.byref(st))
+            self.root_offsets = list(offs)
         if raise_on_error:
             _check(code)
         if caustics:

@@ -115,6 +115,7 @@ def test_batched_fields_match_oracle(ctx, precision, S):
     if precision == "mixed":
         assert st["root_updates_f32"] > 0
     R, W, C = split(ctx, m_steps, rr, ri, cr, ci, cn)
+    assert ctx.root_offsets == [o for o, _, _ in ctx.field_blocks(m_steps)] + [rr.numel()]
     for i, f in enumerate(fs):
         check_field(f, R[i], W[i], C[i], m_steps, st["n_subchains"], f"{precision} S={S} field {i}",
                     colwise=precision == "fp64")
@@ -175,3 +176,26 @@ def test_batched_invalid(ctx, mlcc):
     z = dev(np.zeros(4))
     with pytest.raises(mlcc.MlccError):
         ctx.map_caustics(z, z)
+
+
+def test_graph_and_eager_rounds_agree(ctx):
+    """Without per-launch timing the rounds are replayed from captured
+    hipGraphs (on the caller's stream, or on the context's own stream when
+    the caller's is the null stream); with timing they are launched one by
+    one.  All three give the same bits."""
+    say("graph vs eager")
+    fs = batch_fields()
+    load_batch(ctx, fs)
+    m_steps, S = 200, 5
+    out = []
+    for timing, side in ((True, False), (False, False), (False, True)):
+        s = torch.cuda.Stream() if side else torch.cuda.current_stream()
+        with torch.cuda.stream(s):
+            rr, ri, cr, ci, cn, st, code = ctx.find_critical_curves(
+                m_steps, n_subchains=S, caustics=True, precision="mixed", timing=timing)
+        s.synchronize()
+        out.append((rr.cpu().numpy(), ri.cpu().numpy(), cr.cpu().numpy(), ci.cpu().numpy(),
+                    cn.cpu().numpy()))
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
