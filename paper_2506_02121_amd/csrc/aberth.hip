@@ -243,6 +243,15 @@ __device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0
     return u;
 }
 
+// Resident waves per SIMD the sweep and polish kernels are compiled for
+// (register budget 512 / waves); the loops keep their instruction counts.
+#ifndef MLCC_SWEEP_WAVES
+#define MLCC_SWEEP_WAVES 4
+#endif
+#ifndef MLCC_POLISH_WAVES
+#define MLCC_POLISH_WAVES 4
+#endif
+
 // Blocks with at most this many unconverged roots take the cooperative path.
 constexpr int SPARSE_MAX = 16;
 
@@ -354,7 +363,7 @@ __device__ __forceinline__ void put(const RoundArgs<T> &A, const BlockCtx<T> &B,
 }
 
 template <bool EQUAL>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MLCC_SWEEP_WAVES, 8)))
 aberth_sweep_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
 {
     using T = typename StarRec<EQUAL>::T;
@@ -657,7 +666,7 @@ __device__ __forceinline__ Update polish_finish(PSums S, double zr, double zi, d
 }
 
 template <bool EQUAL>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MLCC_POLISH_WAVES, 8)))
 newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
 {
     using T = typename StarRec<EQUAL>::T;
