@@ -1,0 +1,154 @@
+"""Edge cases of the root finder on the GPU: the smallest phase grid, the
+shortest subchains, a single star in every mode, iteration caps in the mixed
+form, size limits, and one field through the batched entry point."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_02121_amd import fields
+from tests import parity
+from tests.conftest import make_lens
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def mlcc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_02121_amd import mlcc as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mlcc):
+    c = mlcc.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.array(a, copy=True), dtype=dtype).cuda()
+
+
+def host_c(re, im):
+    return re.cpu().numpy() + 1j * im.cpu().numpy()
+
+
+def run(ctx, f, m_steps, **kw):
+    ctx.set_lenses(dev(f.x), dev(f.y), dev(f.m), f.kappa_s, f.gamma)
+    rr, ri, cr, ci, cn, st, code = ctx.find_critical_curves(m_steps, caustics=True, **kw)
+    torch.cuda.synchronize()
+    return host_c(rr, ri), host_c(cr, ci), cn.cpu().numpy(), st, code
+
+
+def against_oracle(f, R, W, cn, m_steps, S, colwise=True):
+    R_ref, cn_ref, _ = oracle.critical_curves(f, m_steps, n_sub=S)
+    Fp = np.stack([oracle.eval_F(f, oracle.phase(j, m_steps), R_ref[j])[1]
+                   for j in range(m_steps + 1)])
+    bound = parity.root_bound(f, Fp)
+    worst, ratio = parity.compare_row_sets(R, R_ref, bound)
+    assert ratio <= 1.0
+    n_r = R.shape[1]
+    assert sorted(cn.tolist()) == list(range(n_r))
+    assert np.max(np.abs(R[-1] - R[0][cn])) < 1e-8
+    if colwise:
+        assert float(np.max(np.abs(R - R_ref))) < 1e-8
+        assert np.array_equal(cn, cn_ref)
+    W_ref = oracle.lens_map(f, R_ref)
+    for j in range(m_steps + 1):
+        idx, _ = parity.pair(R_ref[j], R[j])
+        bw = 2 * abs(1 - f.kappa_s) * bound[j] + 1e-11 * (1 + np.abs(W_ref[j]))
+        assert np.all(np.abs(W[j][idx] - W_ref[j]) <= bw)
+    return worst
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_two_steps(ctx, precision):
+    """m = 2: one subchain, centre row 1, rows 0 and 2 at its ends."""
+    say("m=2", precision)
+    f = fields.random_field(41, 12, kappa_star=0.4, gamma=0.35, masses="salpeter")
+    R, W, cn, st, code = run(ctx, f, 2, precision=precision)
+    assert R.shape == (3, 24) and st["n_subchains"] == 1
+    against_oracle(f, R, W, cn, 2, 1, colwise=precision == "fp64")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_shortest_subchains(ctx, precision):
+    """S = m/2: every subchain is a centre row and its two neighbours, and
+    every even row is a duplicated boundary."""
+    say("S=m/2", precision)
+    f = fields.random_field(42, 20, kappa_star=0.5, gamma=0.25, masses="equal")
+    m_steps = 40
+    R, W, cn, st, code = run(ctx, f, m_steps, n_subchains=m_steps // 2, precision=precision)
+    assert st["n_subchains"] == m_steps // 2
+    against_oracle(f, R, W, cn, m_steps, m_steps // 2, colwise=precision == "fp64")
+
+
+@pytest.mark.parametrize("precision,predictor", [("fp64", 0), ("fp64", 2), ("mixed", 1),
+                                                 ("mixed", 2)])
+def test_single_star_every_mode(ctx, precision, predictor):
+    """N = 1: two roots on the ring |z - z1| = sqrt(m/(1 - kappa_s)), a
+    point caustic at (1 - kappa_s) z1."""
+    say("single star", precision, predictor)
+    z1, mass, kap = -0.7 + 0.4j, 0.6, 0.15
+    f = make_lens(z1, mass, kap, 0.0)
+    m_steps = 96
+    R, W, cn, st, code = run(ctx, f, m_steps, precision=precision, predictor=predictor)
+    rho = np.sqrt(mass / (1 - kap))
+    assert np.max(np.abs(np.abs(R - z1) - rho)) < 1e-9
+    assert np.max(np.abs(W - (1 - kap) * z1)) < 1e-8
+    assert cn.tolist() == [1, 0]
+
+
+def test_mixed_iteration_cap_is_reported(ctx, mlcc):
+    """A cold start capped at one sweep in the mixed form ends in the FP64
+    fallback, which reports the cap instead of running on."""
+    say("mixed cap")
+    f = fields.random_field(3, 20)
+    ctx.set_lenses(dev(f.x), dev(f.y), dev(f.m), f.kappa_s, f.gamma)
+    rr, ri, cn, st, code = ctx.find_critical_curves(100, max_iter_cold=1, precision="mixed",
+                                                    raise_on_error=False)
+    assert code == mlcc.MLCC_ERR_NOT_CONVERGED
+    assert st["rows_capped"] >= 1
+
+
+def test_size_limits_rejected(ctx, mlcc):
+    """Limits are checked before any allocation."""
+    say("size limits")
+    f = fields.random_field(3, 5)
+    ctx.set_lenses(dev(f.x), dev(f.y), dev(f.m), f.kappa_s, f.gamma)
+    lib = mlcc.library()
+    p = ctx.default_params((1 << 28) + 2)
+    z = dev(np.zeros(4))
+    code = lib.mlcc_find_critical_curves(ctx._h, p, mlcc._ptr(z), mlcc._ptr(z), None, None, None,
+                                         None)
+    assert code == mlcc.MLCC_ERR_INVALID
+    p = ctx.default_params(100)
+    p.predictor = 3
+    code = lib.mlcc_find_critical_curves(ctx._h, p, mlcc._ptr(z), mlcc._ptr(z), None, None, None,
+                                         None)
+    assert code == mlcc.MLCC_ERR_INVALID
+    with pytest.raises(mlcc.MlccError):
+        ctx.set_lenses(dev(np.zeros(0)), dev(np.zeros(0)), dev(np.zeros(0)), 0.0, 0.3)
+
+
+def test_one_field_batched_equals_single(ctx):
+    """The batched entry point with one field gives the single-field result
+    bit for bit (unequal masses: the same kernels run either way)."""
+    say("one field batched")
+    f = fields.random_field(44, 45, kappa_star=0.35, kappa_s=0.05, gamma=0.4, masses="salpeter")
+    R1, W1, cn1, _, _ = run(ctx, f, 120, n_subchains=6)
+    ctx.set_lenses_batched([0, 45], dev(f.x), dev(f.y), dev(f.m), [f.kappa_s], [f.gamma])
+    rr, ri, cr, ci, cn, st, code = ctx.find_critical_curves(120, n_subchains=6, caustics=True)
+    torch.cuda.synchronize()
+    assert ctx.root_offsets == [0, rr.numel()]
+    assert np.array_equal(host_c(rr, ri).reshape(R1.shape).view(np.float64), R1.view(np.float64))
+    assert np.array_equal(host_c(cr, ci).reshape(W1.shape).view(np.float64), W1.view(np.float64))
+    assert np.array_equal(cn.cpu().numpy(), cn1)
