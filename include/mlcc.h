@@ -47,8 +47,9 @@ typedef enum {
     MLCC_FP64 = 0, /* every step in IEEE double precision */
     MLCC_MIXED = 1 /* Aberth sweeps in FP32 (FP64 star distances, FP32 sums per tile of
                       64 stars carried in FP64), every root finished by FP64 Newton
-                      polish passes with an a-posteriori acceptance test per root and
-                      the two row identities (sum r, sum r^2) per row.  Cold starts:
+                      polish passes that accept a root on the same cutoffs as the
+                      Aberth sweeps (on the Newton step), and the two row identities
+                      (sum r, sum r^2) per row.  Cold starts:
                       FP32 sweeps until the roots settle, then the polish.  Warm rows:
                       the polish straight from the chain prediction (predictor > 0),
                       else after one FP32 sweep.  A row the polish does not settle
@@ -149,7 +150,7 @@ typedef struct {
     double algorithmic_flop; /* FP64 sweeps: root_updates * (29 N + 10 (2N - 1)); FMA = 2,
                                 add/mul/reciprocal = 1 */
     double algorithmic_flop_f32;    /* FP32 sweeps: root_updates_f32 * (29 N + 10 (2N - 1)) */
-    double algorithmic_flop_polish; /* polish: polish_updates * 36 N */
+    double algorithmic_flop_polish; /* polish: polish_updates * 29 N (star terms only) */
 } mlcc_cc_stats;
 
 /*

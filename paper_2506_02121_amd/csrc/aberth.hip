@@ -14,7 +14,7 @@
 //  * Each front carries a phase.  FP64 mode: every row is FP64 Aberth sweeps.
 //    Mixed mode: cold starts are FP32 Aberth sweeps until the roots settle;
 //    warm rows with a chain prediction start directly with FP64 Newton
-//    polish passes (a-posteriori acceptance test per root, row identities
+//    polish passes (the paper's cutoffs on each Newton step, row identities
 //    for the row), warm rows without one with a single FP32 sweep; a row the
 //    polish does not settle gets one FP32 sweep of the whole row and the
 //    polish again, then FP64 Aberth sweeps.
@@ -580,15 +580,16 @@ aberth_sweep_f32(RoundArgs<typename StarRec<EQUAL>::T> A)
 // FP64 Newton polish (mixed mode)
 // ---------------------------------------------------------------------------
 
-// Sums for the Newton polish: s0 = sum m u, s2 = sum m u^2, s3 = sum m u^3,
-// s4 = sum m u^4 (F'' = 6 s4).
+// Sums for the Newton polish: s0 = sum m u, s2 = sum m u^2, s3 = sum m u^3
+// (F = gamma + s2 - (1 - kappa_s) e^{-i phi}, F' = -2 s3) and the real
+// q = sum m |u|^4, which bounds |F''| = 6 |sum m u^4| <= 6 q.
 struct PSums {
-    double s0r, s0i, s2r, s2i, s3r, s3i, s4r, s4i;
+    double s0r, s0i, s2r, s2i, s3r, s3i, q;
 };
 
 __device__ __forceinline__ void zero(PSums &S)
 {
-    S.s0r = S.s0i = S.s2r = S.s2i = S.s3r = S.s3i = S.s4r = S.s4i = 0.0;
+    S.s0r = S.s0i = S.s2r = S.s2i = S.s3r = S.s3i = S.q = 0.0;
 }
 
 template <bool EQUAL, class T>
@@ -597,48 +598,50 @@ __device__ __forceinline__ void add_star_polish(PSums &S, double zr, double zi, 
     const double dx = zr - s.x;
     const double dy = zi - s.y;
     const double inv = rcp_refined<RCP_STAR>(fma(dx, dx, dy * dy));
-    // u = ux - i uy, a = ux^2, b = uy^2, v = a - b, c = ux uy:
-    //   u^2 = v - 2i c,  u^3 = ux (a - 3b) + i uy (b - 3a),  u^4 = v^2 - 4c^2 - 4i v c
-    // (s2i accumulates sum m c; polish_finish turns it into Im s2 = -2 that)
+    // u = ux - i uy, a = ux^2, b = uy^2:  u^2 = (a - b) - 2i ux uy,
+    // u^3 = ux (a - 3b) + i uy (b - 3a),  |u|^4 = inv^2
+    // (s2i accumulates sum m ux uy; polish_finish turns it into Im s2 = -2 that)
     const double ux = dx * inv;
     const double uy = dy * inv;
     const double a = ux * ux, b = uy * uy;
-    const double v = a - b, c = ux * uy;
     if (EQUAL) {
-        const double c4 = -4.0 * c;
         S.s0r += ux; S.s0i -= uy;
-        S.s2r += v; S.s2i += c;
+        S.s2r += a - b;
+        S.s2i = fma(ux, uy, S.s2i);
         S.s3r = fma(ux, fma(-3.0, b, a), S.s3r);
         S.s3i = fma(uy, fma(-3.0, a, b), S.s3i);
-        S.s4r = fma(v, v, S.s4r);
-        S.s4r = fma(c4, c, S.s4r);
-        S.s4i = fma(c4, v, S.s4i);
+        S.q = fma(inv, inv, S.q);
     } else {
         const double mi = StarRec<EQUAL>::mass(s);
-        const double mv = mi * v, mc = mi * c, mc4 = -4.0 * mc;
-        S.s0r = fma(mi, ux, S.s0r); S.s0i = fma(-mi, uy, S.s0i);
-        S.s2r += mv; S.s2i += mc;
-        S.s3r = fma(mi * ux, fma(-3.0, b, a), S.s3r);
-        S.s3i = fma(mi * uy, fma(-3.0, a, b), S.s3i);
-        S.s4r = fma(mv, v, S.s4r);
-        S.s4r = fma(mc4, c, S.s4r);
-        S.s4i = fma(mc4, v, S.s4i);
+        const double mux = mi * ux, muy = mi * uy;
+        S.s0r += mux; S.s0i -= muy;
+        S.s2r = fma(mi, a - b, S.s2r);
+        S.s2i = fma(mux, uy, S.s2i);
+        S.s3r = fma(mux, fma(-3.0, b, a), S.s3r);
+        S.s3i = fma(muy, fma(-3.0, a, b), S.s3i);
+        S.q = fma(mi * inv, inv, S.q);
     }
 }
 
-// Newton step z' = z - F/F' and its acceptance: after the step the error is
-// about |F''| |D|^2 / (2 |F'|) (quadratic convergence), trusted only while
-// |D| |F''/F'| stays small.  The caustic of z' reuses the sums through
-// sum m/(z' - z_i) = s0 + D s2 + D^2 s3 + D^3 s4 + O(D^4).
+// Newton step z' = z - D, D = F/F', accepted on the paper's cutoffs for the
+// step just taken (|D| < tol_step, or the App. C bound on |1/mu| at z), or
+// when the error it leaves, at most ~|F''| |D|^2 / (2 |F'|) by quadratic
+// convergence, is below POLISH_ERR_FRACTION * tol_step -- always while
+// |D| |F''/F'| < 0.1 on the bound |F''| <= 6 q, so that z' lies well inside
+// the region where Newton's method converges to one root.  The error bound
+// is recorded for the row identities.  The caustic of z' reuses
+// the sums: sum m/(z' - z_i) = s0 + D s2 + D^2 s3 + O(D^3 sum m |u|^4).
+constexpr double POLISH_ERR_FRACTION = 1e-3;
+
 template <bool EQUAL>
 __device__ __forceinline__ Update polish_finish(PSums S, double zr, double zi, double m0,
-                                                double2 e, double gamma, double a, double tol,
-                                                int k)
+                                                double2 e, double gamma, double a, double a1,
+                                                double tol_step2, double tol_mu, int k)
 {
     S.s2i *= -2.0;
     if (EQUAL) {
         S.s0r *= m0; S.s0i *= m0; S.s2r *= m0; S.s2i *= m0;
-        S.s3r *= m0; S.s3i *= m0; S.s4r *= m0; S.s4i *= m0;
+        S.s3r *= m0; S.s3i *= m0; S.q *= m0;
     }
     const double Fr = gamma + S.s2r - e.x, Fi = S.s2i - e.y;
     const double Fpr = -2.0 * S.s3r, Fpi = -2.0 * S.s3i;
@@ -648,18 +651,17 @@ __device__ __forceinline__ Update polish_finish(PSums S, double zr, double zi, d
     Update u;
     u.zr = zr - Dr;
     u.zi = zi - Di;
-    const double aD = sqrt(Dr * Dr + Di * Di);
-    const double ratio = 6.0 * sqrt(S.s4r * S.s4r + S.s4i * S.s4i) / sqrt(den); // |F''/F'|
-    const double err = 0.5 * ratio * aD * aD;
-    u.flag = err <= tol && aD * ratio < 0.1 && aD < 1e-3;
-    u.err = err;
+    const double aD2 = Dr * Dr + Di * Di, aD = sqrt(aD2);
+    const double ratio = 6.0 * S.q / sqrt(den);   // bound on |F''/F'|
+    const double aF = sqrt(Fr * Fr + Fi * Fi);
+    u.err = 0.5 * ratio * aD2;
+    u.flag = (aD2 < tol_step2 || aF * (aF + 2.0 * a1) < tol_mu ||
+              u.err * u.err < POLISH_ERR_FRACTION * POLISH_ERR_FRACTION * tol_step2) &&
+             aD * ratio < 0.1;
     if (!isfinite(u.zr) || !isfinite(u.zi)) nudge(u, zr, zi, k);
     const double d2r = Dr * Dr - Di * Di, d2i = 2.0 * Dr * Di;
-    const double d3r = d2r * Dr - d2i * Di, d3i = d2r * Di + d2i * Dr;
-    const double Tr = S.s0r + (Dr * S.s2r - Di * S.s2i) + (d2r * S.s3r - d2i * S.s3i) +
-                      (d3r * S.s4r - d3i * S.s4i);
-    const double Ti = S.s0i + (Dr * S.s2i + Di * S.s2r) + (d2r * S.s3i + d2i * S.s3r) +
-                      (d3r * S.s4i + d3i * S.s4r);
+    const double Tr = S.s0r + (Dr * S.s2r - Di * S.s2i) + (d2r * S.s3r - d2i * S.s3i);
+    const double Ti = S.s0i + (Dr * S.s2i + Di * S.s2r) + (d2r * S.s3i + d2i * S.s3r);
     u.wr = fma(a, u.zr, gamma * u.zr) - Tr;
     u.wi = fma(a, u.zi, -gamma * u.zi) + Ti;
     return u;
@@ -680,7 +682,8 @@ newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
     const T *__restrict__ stars = B.stars;
     double2 *__restrict__ nxt = A.nxt;
     int32_t *__restrict__ flagrow = A.flagrow;
-    const double m0 = B.m0, gamma = B.gamma, a = B.a, tol = A.tol_step;
+    const double m0 = B.m0, gamma = B.gamma, a = B.a, a1 = B.a1;
+    const double tol_step2 = A.tol_step2, tol_mu = A.tol_mu;
     double zr = 0.0, zi = 0.0;
     bool act = false;
     double er_ = 0.0;   // estimated error of the value this root ends the pass with
@@ -708,9 +711,9 @@ newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
 #pragma unroll 4
             for (int i = lane; i < n_stars; i += 64) add_star_polish<EQUAL>(S, xk, yk, stars[i]);
             wave_sum(S.s0r); wave_sum(S.s0i); wave_sum(S.s2r); wave_sum(S.s2i);
-            wave_sum(S.s3r); wave_sum(S.s3i); wave_sum(S.s4r); wave_sum(S.s4i);
+            wave_sum(S.s3r); wave_sum(S.s3i); wave_sum(S.q);
             const int kk = k0 + l;
-            const Update u = polish_finish<EQUAL>(S, xk, yk, m0, e, gamma, a, tol, kk);
+            const Update u = polish_finish<EQUAL>(S, xk, yk, m0, e, gamma, a, a1, tol_step2, tol_mu, kk);
             if (lane == l) {
                 nxt[base_f + kk] = make_double2(u.zr, u.zi);
                 fr_ = u.zr;
@@ -729,7 +732,7 @@ newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
         zero(S);
         stream_tiles(stars, n_stars, reinterpret_cast<T *>(tiles),
                      [&](int, const T &s) { add_star_polish<EQUAL>(S, zr, zi, s); });
-        const Update u = polish_finish<EQUAL>(S, zr, zi, m0, e, gamma, a, tol, k);
+        const Update u = polish_finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k);
         if (act) {
             nxt[base_f + k] = make_double2(u.zr, u.zi);
             fr_ = u.zr;
@@ -1601,13 +1604,16 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         stats->sweep_launches = kind_launches[0];
         stats->sweep_f32_launches = kind_launches[1];
         stats->polish_launches = kind_launches[2];
-        // algorithmic FLOP of one update of a root of a field of N stars:
-        // 29 N + 10 (2N - 1) (Aberth sweep), 36 N (polish); the device counts
-        // updates and updates x N, which gives the sums over mixed fields
+        // algorithmic FLOP of one update of a root of a field of N stars
+        // (FMA = 2, add/mul/reciprocal = 1): 29 per star term (difference,
+        // |d|^2, reciprocal, u, u^2, u^3 and their sums) and 10 per root
+        // term, 29 N + 10 (2N - 1) for an Aberth update, 29 N for a polish
+        // update (star terms only); the device counts updates and
+        // updates x N, which gives the sums over mixed field sizes
         stats->algorithmic_flop = 49.0 * (double)h.star_updates - 10.0 * (double)h.updates;
         stats->algorithmic_flop_f32 =
             49.0 * (double)h.star_updates_f32 - 10.0 * (double)h.updates_f32;
-        stats->algorithmic_flop_polish = 36.0 * (double)h.star_updates_polish;
+        stats->algorithmic_flop_polish = 29.0 * (double)h.star_updates_polish;
     }
     return result;
 }
