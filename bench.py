@@ -287,11 +287,11 @@ def bench_batched(args, wl, precision):
     ctx = mlcc.Context(0)
     torch.cuda.synchronize()
 
-    def step():
+    def step(prec=precision):
         ctx.set_lenses_batched(off, x, y, mm, ks, gs)
         _, _, _, _, cn, st, _ = ctx.find_critical_curves(
             m_steps, n_subchains=args.subchains, timing=True, caustics=True,
-            out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=precision,
+            out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=prec,
             predictor=args.predictor)
         return st
 
@@ -332,6 +332,39 @@ def bench_batched(args, wl, precision):
                                      "polish_updates", "rows_fallback", "n_subchains",
                                      "cold_sweeps", "max_row_sweeps", "match_maxdist")},
     }
+    if args.compare:
+        # the other precision on the same fields: throughput, and how far its
+        # roots lie from this run's on sampled rows of sampled fields
+        from scipy.spatial import cKDTree
+        other = "mixed" if precision == "fp64" else "fp64"
+        blocks = ctx.field_blocks(m_steps)
+        picks = np.linspace(0, len(fs) - 1, 8).astype(int)
+        rows = np.linspace(0, m_steps, 9).astype(np.int64)
+
+        def sample():
+            got = []
+            for i in picks:
+                o, _, n_r = blocks[i]
+                for j in rows:
+                    a = slice(o + j * n_r, o + (j + 1) * n_r)
+                    got.append(np.stack([roots_re[a].cpu().numpy(), roots_im[a].cpu().numpy()], 1))
+            return got
+        ref = sample()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st2 = [step(other) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - t0
+        dmax = max(float(cKDTree(b).query(a)[0].max()) for a, b in zip(ref, sample()))
+        out["compare"] = {
+            "precision": other, "value": roots_per_step / (el2 / args.steps),
+            "ms_per_step": 1e3 * el2 / args.steps, "steps": args.steps,
+            "speedup_of_mixed_over_fp64": (el2 / elapsed if other == "fp64" else elapsed / el2),
+            "max_root_distance_to_main_run": dmax,
+            "sampled": f"{len(picks)} fields x {len(rows)} rows",
+            "kernels": root_kernels(st2, other),
+        }
+        log(f"{other}: {1e3 * el2 / args.steps:.0f} ms per step, max root distance {dmax:.2e}")
     print(json.dumps(out), flush=True)
 
 
