@@ -44,7 +44,10 @@ typedef enum {
 } mlcc_status;
 
 typedef enum {
-    MLCC_FP64 = 0, /* every step in IEEE double precision */
+    MLCC_FP64 = 0, /* every sum and step in IEEE double precision; the root-root
+                      reciprocal inside the Aberth correction uses the hardware
+                      estimate (relative error ~2^-24), which cannot move a root
+                      at convergence */
     MLCC_MIXED = 1 /* Aberth sweeps in FP32 (FP64 star distances, FP32 sums per tile of
                       64 stars carried in FP64), every root finished by FP64 Newton
                       polish passes that accept a root on the same cutoffs as the
