@@ -56,8 +56,9 @@ typedef enum {
                       FP32 sweeps until the roots settle, then the polish.  Warm rows:
                       the polish straight from the chain prediction (predictor > 0),
                       else after one FP32 sweep.  A row the polish does not settle
-                      gets one FP32 sweep and the polish again, then FP64 Aberth
-                      sweeps.  Results meet the same cutoffs as MLCC_FP64. */
+                      gets one FP32 sweep and the polish again, then restarts from
+                      its start values with FP64 Aberth sweeps.  Results meet the
+                      same cutoffs as MLCC_FP64. */
 } mlcc_precision;
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream` (a

@@ -370,6 +370,24 @@ aberth_sweep_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
     __shared__ double4 tiles[128];   // two tiles of up to 32-byte records
     BlockCtx<T> B;
     if (!enter(A, PH_F64, B)) return;
+    if (A.fronts[B.f].reseed) {
+        // restart the row from its start values: the seeds z_i +- 1 for a
+        // cold start, the previous row of the subchain otherwise
+        if (B.valid) {
+            double2 z;
+            if (B.dir == 0) {
+                const T st = B.stars[B.k >> 1];
+                z = make_double2(st.x + ((B.k & 1) ? -1.0 : 1.0), st.y);
+            } else {
+                const int64_t o = B.out_off + (int64_t)(B.row - B.dir) * B.n_r + B.k;
+                z = make_double2(A.out_re[o], A.out_im[o]);
+            }
+            A.nxt[B.base_f + B.k] = z;
+        }
+        const int n_valid = __popcll(__ballot(B.valid));
+        if (threadIdx.x == 0) atomicAdd(&A.counts[B.f], n_valid);
+        return;
+    }
     const int lane = B.lane, k0 = B.k0, k = B.k, n_r = B.n_r, n_stars = B.n_stars;
     const bool valid = B.valid;
     const int64_t base_f = B.base_f;
@@ -803,6 +821,7 @@ __device__ __forceinline__ void start_row(Front &fr, int predictor)
     fr.best = 0x7fffffff;
     fr.stall = 0;
     fr.passes_row = 0;
+    fr.reseed = 0;
     fr.stamp = 4 * fr.row;
     fr.fresh = 1;
     if (fr.mode == PH_F64)
@@ -863,8 +882,8 @@ __device__ __forceinline__ void row_converged(Front &fr, int f, Front *fronts, i
 //   Polish phase (mixed): a row whose roots were all accepted and whose sums
 //     satisfy the row identities has converged.  Otherwise more polish
 //     passes (up to MAX_POLISH); then, once per row, an FP32 sweep of the
-//     whole row and the polish again; then FP64 sweeps for whatever is not
-//     accepted (all roots of the row if an identity failed).
+//     whole row and the polish again; then the row restarts from its start
+//     values (seeds, or the previous row) with plain FP64 Aberth sweeps.
 //
 // Row identities: the rationalised polynomial has leading coefficient
 // c = gamma - (1 - kappa_s) e^{-i phi} and next coefficient -2 c sum z_i, so
@@ -936,7 +955,7 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
             }
         } else if (fr.phase == PH_POLISH) {
             fr.tried |= TRIED_POLISH;
-            bool retry = false, identity_failed = false;
+            bool retry = false;
             if (c == 0) {
                 const Real R = reals[fr.real];
                 const int bpf = (R.n_r + 63) / 64;
@@ -961,7 +980,7 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
                 if (sqrt(e1r * e1r + e1i * e1i) <= tol1 && sqrt(e2r * e2r + e2i * e2i) <= tol2)
                     row_converged(fr, f, fronts, st, f0, predictor);
                 else
-                    retry = identity_failed = true;
+                    retry = true;
             } else if (++fr.passes >= MAX_POLISH) {
                 retry = true;
             }
@@ -969,12 +988,18 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
                 if (!(fr.tried & TRIED_F32)) {
                     fr.phase = PH_F32;
                 } else {
-                    if (identity_failed) fr.stamp += 1;   // every root of the row again
+                    // plain FP64 Aberth sweeps over every root from the row's
+                    // start values: Newton steps may have sent two columns to
+                    // one root, which Aberth steps from there would not undo
+                    fr.stamp += 1;
+                    fr.reseed = 1;
                     fr.phase = PH_F64;
                     fr.sweeps = 0;
                     atomicAdd((unsigned long long *)&ctl->rows_fallback, 1ull);
                 }
             }
+        } else if (fr.reseed) {
+            fr.reseed = 0;   // the restart pass only reloaded the start values
         } else if (c == 0) {
             row_converged(fr, f, fronts, st, f0, predictor);
         } else {

@@ -72,7 +72,7 @@ struct Front {
     int32_t best;     // fewest roots still moving after an FP32 sweep (cold start)
     int32_t stall;    // FP32 sweeps since that count last fell
     int32_t passes_row; // passes of any kind on the current row
-    int32_t pad_;
+    int32_t reseed;   // 1: the next FP64 pass restarts the row from its start values
     int64_t it_off;   // first element of its roots in the iterate and flag arrays
 };
 

@@ -199,3 +199,23 @@ def test_graph_and_eager_rounds_agree(ctx):
     for other in out[1:]:
         for a, b in zip(out[0], other):
             assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+def test_many_fronts_several_control_groups(ctx):
+    """More than 4096 fronts: the control kernel runs as several work groups
+    over disjoint front ranges (each keeping a subchain's two fronts)."""
+    say("many fronts")
+    fs = [fields.random_field(2000 + i, 2 + i % 4, kappa_star=0.3, kappa_s=0.05 * (i % 3),
+                              gamma=0.2 + 0.05 * (i % 5), masses="salpeter")
+          for i in range(300)]
+    load_batch(ctx, fs)
+    m_steps, S = 64, 8   # 300 fields x 2S = 4800 fronts
+    for precision in ("fp64", "mixed"):
+        rr, ri, cr, ci, cn, st, code = ctx.find_critical_curves(m_steps, n_subchains=S,
+                                                                caustics=True,
+                                                                precision=precision)
+        torch.cuda.synchronize()
+        R, W, C = split(ctx, m_steps, rr, ri, cr, ci, cn)
+        for i in (0, 1, 2, 3, 150, 299):
+            check_field(fs[i], R[i], W[i], C[i], m_steps, S, f"{precision} field {i}",
+                        colwise=precision == "fp64")

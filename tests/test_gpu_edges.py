@@ -152,3 +152,17 @@ def test_one_field_batched_equals_single(ctx):
     assert np.array_equal(host_c(rr, ri).reshape(R1.shape).view(np.float64), R1.view(np.float64))
     assert np.array_equal(host_c(cr, ci).reshape(W1.shape).view(np.float64), W1.view(np.float64))
     assert np.array_equal(cn.cpu().numpy(), cn1)
+
+
+def test_mixed_restart_after_doubled_root(ctx):
+    """A 3-star field whose cold start, finished by Newton steps, puts two
+    columns on one root: the row identities catch it, and the row restarts
+    from the seeds in FP64 instead of keeping the doubled root."""
+    say("mixed doubled root")
+    f = fields.random_field(2233, 3, kappa_star=0.3, kappa_s=0.1, gamma=0.35, masses="salpeter")
+    m_steps, S = 64, 8
+    R, W, cn, st, code = run(ctx, f, m_steps, n_subchains=S, precision="mixed")
+    assert code == 0
+    print("[stats]", {k: st[k] for k in ("rows_fallback", "polish_updates", "root_updates")})
+    assert st["rows_fallback"] >= 1
+    against_oracle(f, R, W, cn, m_steps, S, colwise=False)

@@ -71,6 +71,22 @@ def check_sampled_rows(f, R_rows, W_rows, rows, m_steps, label):
           f"max caustic distance {wworst:.3e}", flush=True)
 
 
+def boundary_continuity(rr, ri, m_steps, S):
+    """Across every subchain boundary row b (computed by two subchains and
+    joined by relabelling) and at the closure, each root of row b+1 must have
+    its own column's root of row b as nearest neighbour, and row b-1 likewise:
+    a wrong relabelling breaks whole columns.  Returns the worst fraction of
+    columns that keep their label."""
+    L = m_steps // S
+    worst = 1.0
+    for b in range(L, m_steps, L):
+        rb = host_c(rr[b], ri[b])
+        for j in (b - 1, b + 1):
+            idx, _ = parity.pair(host_c(rr[j], ri[j]), rb)
+            worst = min(worst, float(np.mean(idx == np.arange(len(idx)))))
+    return worst
+
+
 def subchain0_window(st, m_steps, half):
     S = st["n_subchains"]
     L = m_steps // S
@@ -115,6 +131,10 @@ def test_full_size_single_field(mlcc, case):
         print(f"[{name}] row identities: {e1:.2e} (sum r, per root), {e2:.2e} (sum r^2, relative)",
               flush=True)
         assert e1 < 1e-9 and e2 < 1e-9
+        keep = boundary_continuity(rr, ri, m_steps, st["n_subchains"])
+        print(f"[{name}] columns keeping their label across subchain boundaries: {keep:.5f}",
+              flush=True)
+        assert keep >= 0.999
         # sampled rows against cold-started oracle rows
         rng = np.random.default_rng(12345)
         rows = sorted(set([0, m_steps // 2, m_steps] +
@@ -128,6 +148,10 @@ def test_full_size_single_field(mlcc, case):
         # the GPU's; from there the warm-started rows must follow the same
         # columns
         lo, c, hi = subchain0_window(st, m_steps, half)
+        if name == "n1k":
+            # grow the oracle's window on through the first boundary row, where
+            # the GPU's columns continue only through the relabelling
+            hi = m_steps // st["n_subchains"] + half
         R_win, _ = oracle.subchain(f, m_steps, lo, c, hi)
         G_win = host_c(rr[lo:hi + 1], ri[lo:hi + 1])
         idx, d = parity.pair(R_win[c - lo], G_win[c - lo])
@@ -191,6 +215,15 @@ def test_full_size_batched(mlcc):
         print(f"[batched] row identities over all fields: {worst1:.2e}, {worst2:.2e}", flush=True)
         assert worst1 < 1e-9 and worst2 < 1e-9
         order = np.argsort([f.n for f in fs])
+        keep = 1.0
+        for i in order[-4:]:
+            o, co, n_r = blocks[i]
+            fr = rr[o:o + (m_steps + 1) * n_r].view(m_steps + 1, n_r)
+            fi = ri[o:o + (m_steps + 1) * n_r].view(m_steps + 1, n_r)
+            keep = min(keep, boundary_continuity(fr, fi, m_steps, st["n_subchains"]))
+        print(f"[batched] columns keeping their label across boundaries (4 largest fields): "
+              f"{keep:.5f}", flush=True)
+        assert keep >= 0.999
         # the three smallest fields: the whole chain against the oracle
         for i in order[:3]:
             f = fs[i]
