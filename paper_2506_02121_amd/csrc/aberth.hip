@@ -245,6 +245,13 @@ __device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0
 
 // Resident waves per SIMD the sweep and polish kernels are compiled for
 // (register budget 512 / waves); the loops keep their instruction counts.
+// MLCC_XCD_MAP 1 keeps every front's blocks on one XCD (one L2 per front's
+// iterate).  Measured on n10k it is ~30% slower than the plain order, which
+// spreads each front over all eight XCDs: the fronts in a full pass change
+// from round to round, and whole fronts per XCD leave XCDs idle.
+#ifndef MLCC_XCD_MAP
+#define MLCC_XCD_MAP 0
+#endif
 #ifndef MLCC_SWEEP_WAVES
 #define MLCC_SWEEP_WAVES 4
 #endif
@@ -281,6 +288,7 @@ template <class T> struct RoundArgs {
 // What one block knows about its front and star field.
 template <class T> struct BlockCtx {
     int f, q, k0, k, lane, n_r, n_stars, row, stamp, dir, pred;
+    int vslot;   // this block's slot in the per-block row sums (front order)
     bool valid, boundary;
     int64_t base_f, out_off, bnd_row_off;
     const T *stars;
@@ -300,6 +308,7 @@ __device__ __forceinline__ bool enter(const RoundArgs<T> &A, int phase, BlockCtx
     const Real *R = A.reals + F->real;
     B.row = F->row;
     B.stamp = F->stamp;
+    B.vslot = F->blk0 + B.q;
     B.dir = F->dir;
     B.pred = (F->fresh && F->dir != 0 && F->hist >= 2) ? min(A.predictor, F->hist - 1) : 0;
     B.n_r = R->n_r;
@@ -775,8 +784,8 @@ newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
     wave_sum(s1r); wave_sum(s1i); wave_sum(s2r); wave_sum(s2i);
     wave_sum(t_e); wave_sum(t_e2); wave_sum(t_a); wave_sum(t_a2);
     if (lane == 0) {
-        A.vieta[2 * blockIdx.x] = make_double4(s1r, s1i, s2r, s2i);
-        A.vieta[2 * blockIdx.x + 1] = make_double4(t_e, t_e2, t_a, t_a2);
+        A.vieta[2 * B.vslot] = make_double4(s1r, s1i, s2r, s2i);
+        A.vieta[2 * B.vslot + 1] = make_double4(t_e, t_e2, t_a, t_a2);
         if (n_after) atomicAdd(&A.counts[B.f], n_after);
         if (n_act) atomicAdd(&A.passupd[B.f], n_act);
     }
@@ -1077,10 +1086,11 @@ __global__ void control_end(Control *__restrict__ ctl, const int32_t *__restrict
 // Cost of one wave's pass over a field of N stars and n_r = 2N roots, in
 // SIMD cycles (issue costs measured per wave64 instruction: FP64 add/FMA
 // ~4.4-5.4 cycles, v_rcp_f64 ~16, FP32 ~2.3, v_rcp_f32 ~8; the kernels
-// spend ~20 instructions per star term and ~7 per root term):
-//   FP64 Aberth sweep   112 N + 47 n_r
+// spend ~21 instructions per star term and ~7 per root term in a sweep,
+// ~22 per star term in the polish):
+//   FP64 Aberth sweep   114 N + 47 n_r
 //   FP32 Aberth sweep    56 N + 22 n_r
-//   FP64 Newton polish  141 N
+//   FP64 Newton polish  120 N
 // A run does, per field, u (m + S) row passes of every block (u ~ 1.03
 // with the chain predictor, ~2 without; in the mixed form a row without a
 // prediction takes an FP32 sweep and a polish) plus S cold starts of ~27
@@ -1097,9 +1107,9 @@ struct TuneModel {
 static double pass_cycles(int kind, double n)
 {
     const double n_r = 2.0 * n;
-    if (kind == PH_F64) return 112.0 * n + 47.0 * n_r;
+    if (kind == PH_F64) return 114.0 * n + 47.0 * n_r;
     if (kind == PH_F32) return 56.0 * n + 22.0 * n_r;
-    return 141.0 * n;
+    return 120.0 * n;
 }
 
 static double predicted_seconds(const std::vector<RealHost> &reals, int64_t m, int64_t s, bool mixed,
@@ -1234,9 +1244,42 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         }
     }
     const int F = (int)fr.size();
-    const int64_t nblocks = (int64_t)bmap.size();
-    if (F > MAX_FRONTS || nblocks > 0x7fffffff)
+    const int64_t nblocks = (int64_t)bmap.size();   // blocks of all fronts, in front order
+    if (F > MAX_FRONTS || nblocks > 0x3fffffff)
         return fail(MLCC_ERR_INVALID, "too many fronts (%d) for one call", F);
+#if MLCC_XCD_MAP
+    // Launch-grid order: work group g runs on XCD g mod 8, so the blocks of
+    // one front are all placed at indices of one residue, and each XCD's L2
+    // holds the iterates of its own fronts only (fronts go to the least
+    // loaded XCD, largest first).  Unused grid slots point at a sentinel
+    // front that is never active.
+    {
+        constexpr int XCDS = 8;
+        std::vector<int> byblocks(F);
+        for (int f = 0; f < F; ++f) byblocks[f] = f;
+        auto nb = [&](int f) { return ceil_div(rd[fr[f].real].n_r, 64); };
+        std::stable_sort(byblocks.begin(), byblocks.end(),
+                         [&](int a, int b) { return nb(a) > nb(b); });
+        std::vector<std::vector<int2>> lists(XCDS);
+        std::vector<int64_t> load(XCDS, 0);
+        for (int f : byblocks) {
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            for (int64_t q = 0; q < nb(f); ++q) lists[x].push_back(make_int2(f, (int)q));
+            load[x] += nb(f);
+        }
+        const int64_t per = *std::max_element(load.begin(), load.end());
+        bmap.assign((size_t)(per * XCDS), make_int2(F, 0));
+        for (int x = 0; x < XCDS; ++x)
+            for (size_t i = 0; i < lists[x].size(); ++i) bmap[i * XCDS + x] = lists[x][i];
+    }
+#endif
+    const int64_t ngrid = (int64_t)bmap.size();
+    {
+        Front sentinel{};
+        sentinel.state = FRONT_DONE;
+        sentinel.dir = 1;
+        fr.push_back(sentinel);
+    }
     // the control kernel's groups hold whole subchains (two fronts) in LDS
     const int fronts_per_group = 4096;
     const int control_groups = (int)ceil_div(F, fronts_per_group);
@@ -1244,7 +1287,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     MLCC_TRY(c->iter[0].reserve((size_t)it_total * sizeof(double2)));
     MLCC_TRY(c->iter[1].reserve((size_t)it_total * sizeof(double2)));
     MLCC_TRY(c->flagrow.reserve((size_t)it_total * sizeof(int32_t)));
-    MLCC_TRY(c->fronts.reserve((size_t)F * sizeof(Front)));
+    MLCC_TRY(c->fronts.reserve((size_t)(F + 1) * sizeof(Front)));
     MLCC_TRY(c->counts.reserve((size_t)F * sizeof(int32_t)));
     MLCC_TRY(c->passupd.reserve((size_t)F * sizeof(int32_t)));
     MLCC_TRY(c->control.reserve(sizeof(Control)));
@@ -1253,7 +1296,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     MLCC_TRY(c->vieta.reserve((size_t)2 * nblocks * sizeof(double4)));
     if (mixed) MLCC_TRY(c->errbuf.reserve((size_t)it_total * sizeof(double)));
     MLCC_TRY(c->reals_d.reserve((size_t)n_real * sizeof(Real)));
-    MLCC_TRY(c->bmap.reserve((size_t)nblocks * sizeof(int2)));
+    MLCC_TRY(c->bmap.reserve((size_t)ngrid * sizeof(int2)));
     MLCC_TRY(c->workflags.reserve(2 * MAX_BATCH * sizeof(int32_t)));
     MLCC_TRY(ensure_pinned(c, 2 * (sizeof(Control) + MAX_BATCH * sizeof(int32_t))));
 
@@ -1268,22 +1311,22 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     ctl0.active_fronts = F;
     MLCC_HIP(hipMemcpyAsync(c->etab.p, unit.data(), (m + 1) * sizeof(double2),
                             hipMemcpyHostToDevice, c->stream));
-    MLCC_HIP(hipMemcpyAsync(c->fronts.p, fr.data(), F * sizeof(Front), hipMemcpyHostToDevice,
+    MLCC_HIP(hipMemcpyAsync(c->fronts.p, fr.data(), (F + 1) * sizeof(Front), hipMemcpyHostToDevice,
                             c->stream));
     MLCC_HIP(hipMemcpyAsync(c->reals_d.p, rd.data(), n_real * sizeof(Real), hipMemcpyHostToDevice,
                             c->stream));
-    MLCC_HIP(hipMemcpyAsync(c->bmap.p, bmap.data(), nblocks * sizeof(int2), hipMemcpyHostToDevice,
+    MLCC_HIP(hipMemcpyAsync(c->bmap.p, bmap.data(), ngrid * sizeof(int2), hipMemcpyHostToDevice,
                             c->stream));
     MLCC_HIP(hipMemcpyAsync(c->control.p, &ctl0, sizeof ctl0, hipMemcpyHostToDevice, c->stream));
     MLCC_HIP(hipMemsetAsync(c->flagrow.p, 0xff, (size_t)it_total * sizeof(int32_t), c->stream));
     MLCC_HIP(hipMemsetAsync(c->counts.p, 0, F * sizeof(int32_t), c->stream));
     MLCC_HIP(hipMemsetAsync(c->passupd.p, 0, F * sizeof(int32_t), c->stream));
     if (equal)
-        hipLaunchKernelGGL(seed_centres<double2>, dim3((unsigned)nblocks), dim3(64), 0, c->stream,
+        hipLaunchKernelGGL(seed_centres<double2>, dim3((unsigned)ngrid), dim3(64), 0, c->stream,
                            c->stars.as<double2>(), c->reals_d.as<Real>(), c->fronts.as<Front>(),
                            c->bmap.as<int2>(), c->iter[0].as<double2>());
     else
-        hipLaunchKernelGGL(seed_centres<double4>, dim3((unsigned)nblocks), dim3(64), 0, c->stream,
+        hipLaunchKernelGGL(seed_centres<double4>, dim3((unsigned)ngrid), dim3(64), 0, c->stream,
                            c->stars4.as<double4>(), c->reals_d.as<Real>(), c->fronts.as<Front>(),
                            c->bmap.as<int2>(), c->iter[0].as<double2>());
     MLCC_HIP(hipGetLastError());
@@ -1324,7 +1367,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         A.predictor = p->predictor;
         A.errbuf = mixed ? c->errbuf.as<double>() : nullptr;
     };
-    const dim3 grid((unsigned)nblocks);
+    const dim3 grid((unsigned)ngrid);
     auto launch_kind = [&](int kind, const double2 *cur, double2 *nxt) {
         if (equal) {
             fill(A2, c->stars.as<double2>(), cur, nxt);
