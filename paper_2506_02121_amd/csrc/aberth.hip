@@ -813,6 +813,31 @@ __global__ void seed_centres(const T *__restrict__ stars, const Real *__restrict
     iter[F->it_off + k] = make_double2(z.x + ((k & 1) ? -1.0 : 1.0), z.y);
 }
 
+// Row sums of every front in the polish phase: one wave per front adds its
+// blocks' partial sums in a fixed order (lanes stride over the blocks, then
+// a butterfly), so the control kernel reads eight numbers per front.
+__global__ void __launch_bounds__(64)
+row_sums(const Front *__restrict__ fronts, const Real *__restrict__ reals,
+         const double4 *__restrict__ vieta, double4 *__restrict__ vsum)
+{
+    const int f = blockIdx.x;
+    const Front *F = fronts + f;
+    if (F->state != FRONT_ACTIVE || F->phase != PH_POLISH) return;
+    const int bpf = (reals[F->real].n_r + 63) / 64;
+    double v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0, v6 = 0, v7 = 0;
+    for (int b = threadIdx.x; b < bpf; b += 64) {
+        const double4 t = vieta[2 * (F->blk0 + b)], q = vieta[2 * (F->blk0 + b) + 1];
+        v0 += t.x; v1 += t.y; v2 += t.z; v3 += t.w;
+        v4 += q.x; v5 += q.y; v6 += q.z; v7 += q.w;
+    }
+    wave_sum(v0); wave_sum(v1); wave_sum(v2); wave_sum(v3);
+    wave_sum(v4); wave_sum(v5); wave_sum(v6); wave_sum(v7);
+    if (threadIdx.x == 0) {
+        vsum[2 * f] = make_double4(v0, v1, v2, v3);
+        vsum[2 * f + 1] = make_double4(v4, v5, v6, v7);
+    }
+}
+
 constexpr int CONTROL_THREADS = 256;
 constexpr int MAX_FRONTS = 1 << 16;
 constexpr int MAX_POLISH = 3;
@@ -900,8 +925,9 @@ __device__ __forceinline__ void row_converged(Front &fr, int f, Front *fronts, i
 // root found twice and one missed shifts them by the distance of the two.
 // The test allows the roots' own estimated errors (twice over) plus a
 // bound on the rounding of the sums: partial sums of 64 values by a
-// butterfly, then the blocks in order, gives at most (6 + blocks) unit
-// roundoffs of sum |r| (one more for sum |r|^2, whose terms round too).
+// butterfly, then (row_sums) lanes striding over the blocks and another
+// butterfly, gives at most (12 + blocks) unit roundoffs of sum |r| (one
+// more for sum |r|^2, whose terms round too).
 //
 // `st` keeps the states in LDS: the two fronts of a subchain sit in adjacent
 // lanes of one wave, which read their states before either is written, so
@@ -911,7 +937,7 @@ __device__ __forceinline__ void row_converged(Front &fr, int f, Front *fronts, i
 __global__ void __launch_bounds__(CONTROL_THREADS)
 aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t n_fronts,
                Control *__restrict__ ctl, int32_t max_cold, int32_t max_warm,
-               int32_t *__restrict__ workflag, const double4 *__restrict__ vieta,
+               int32_t *__restrict__ workflag, const double4 *__restrict__ vsum,
                const Real *__restrict__ reals, const double2 *__restrict__ unit,
                int32_t fronts_per_group, int32_t predictor, int32_t *__restrict__ passupd)
 {
@@ -968,13 +994,9 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
             if (c == 0) {
                 const Real R = reals[fr.real];
                 const int bpf = (R.n_r + 63) / 64;
-                double a1r = 0, a1i = 0, a2r = 0, a2i = 0, se = 0, se2 = 0, sa = 0, sa2 = 0;
-                for (int b = 0; b < bpf; ++b) {
-                    const double4 t = vieta[2 * (fr.blk0 + b)];
-                    const double4 q = vieta[2 * (fr.blk0 + b) + 1];
-                    a1r += t.x; a1i += t.y; a2r += t.z; a2i += t.w;
-                    se += q.x; se2 += q.y; sa += q.z; sa2 += q.w;
-                }
+                const double4 t = vsum[2 * f], q = vsum[2 * f + 1];
+                const double a1r = t.x, a1i = t.y, a2r = t.z, a2i = t.w;
+                const double se = q.x, se2 = q.y, sa = q.z, sa2 = q.w;
                 const double2 u = unit[fr.row];
                 const double cr = R.gamma - R.a * u.x, ci = -R.a * u.y;   // c(phi)
                 const double cc = cr * cr + ci * ci;
@@ -983,8 +1005,8 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
                 const double e2r = a2r - (2.0 * R.sz2_r - 2.0 * mcr);
                 const double e2i = a2i - (2.0 * R.sz2_i - 2.0 * mci);
                 const double u_ro = 1.1102230246251565e-16;
-                const double tol1 = 2.0 * se + 2.0 * (6 + bpf) * u_ro * sa + R.tol1;
-                const double tol2 = 2.0 * se2 + 2.0 * (7 + bpf) * u_ro * sa2 + R.tol2 +
+                const double tol1 = 2.0 * se + 2.0 * (12 + bpf) * u_ro * sa + R.tol1;
+                const double tol2 = 2.0 * se2 + 2.0 * (13 + bpf) * u_ro * sa2 + R.tol2 +
                                     16.0 * u_ro * sqrt(mcr * mcr + mci * mci);
                 if (sqrt(e1r * e1r + e1i * e1i) <= tol1 && sqrt(e2r * e2r + e2i * e2i) <= tol2)
                     row_converged(fr, f, fronts, st, f0, predictor);
@@ -1294,6 +1316,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     MLCC_TRY(c->etab.reserve((size_t)(m + 1) * sizeof(double2)));
     MLCC_TRY(c->bnd.reserve((size_t)std::max<int64_t>(bnd_total, 1) * sizeof(double2)));
     MLCC_TRY(c->vieta.reserve((size_t)2 * nblocks * sizeof(double4)));
+    MLCC_TRY(c->vsum.reserve((size_t)2 * F * sizeof(double4)));
     if (mixed) MLCC_TRY(c->errbuf.reserve((size_t)it_total * sizeof(double)));
     MLCC_TRY(c->reals_d.reserve((size_t)n_real * sizeof(Real)));
     MLCC_TRY(c->bmap.reserve((size_t)ngrid * sizeof(int2)));
@@ -1438,12 +1461,16 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
                 if (timed) MLCC_HIP(hipEventRecord(ev(slot, i, kind, 0), rs));
                 launch_kind(kind, cur, nxt);
                 if (timed) MLCC_HIP(hipEventRecord(ev(slot, i, kind, 1), rs));
+                if (kind == 2)
+                    hipLaunchKernelGGL(row_sums, dim3((unsigned)F), dim3(64), 0, rs,
+                                       c->fronts.as<Front>(), c->reals_d.as<Real>(),
+                                       c->vieta.as<double4>(), c->vsum.as<double4>());
             }
             int32_t *wf = c->workflags.as<int32_t>() + slot * MAX_BATCH + i;
             hipLaunchKernelGGL(control_begin, dim3(1), dim3(64), 0, rs, dctl, wf);
             hipLaunchKernelGGL(aberth_control, dim3(control_groups), dim3(CONTROL_THREADS), 0,
                                rs, c->fronts.as<Front>(), c->counts.as<int32_t>(), F, dctl,
-                               max_cold, max_warm, wf, c->vieta.as<double4>(),
+                               max_cold, max_warm, wf, c->vsum.as<double4>(),
                                c->reals_d.as<Real>(), c->etab.as<double2>(), fronts_per_group,
                                p->predictor, c->passupd.as<int32_t>());
             hipLaunchKernelGGL(control_end, dim3(1), dim3(64), 0, rs, dctl, wf);

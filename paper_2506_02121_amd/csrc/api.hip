@@ -143,7 +143,7 @@ void mlcc_destroy(mlcc_ctx *ctx)
     (void)hipStreamSynchronize(c.stream);
     DevBuf *bufs[] = {&c.stars, &c.mass, &c.stars4, &c.iter[0], &c.iter[1], &c.flagrow, &c.fronts,
                       &c.counts, &c.control, &c.etab, &c.bnd, &c.perm, &c.match_aux,
-                      &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.passupd, &c.reals_d, &c.bmap, &c.diff,
+                      &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.vsum, &c.passupd, &c.reals_d, &c.bmap, &c.diff,
                       &c.err, &c.edt_col};
     for (DevBuf *b : bufs) b->release();
     if (c.own_stream) (void)hipStreamDestroy(c.own_stream);

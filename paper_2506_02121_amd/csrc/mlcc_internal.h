@@ -148,6 +148,7 @@ struct Ctx {
     DevBuf workflags; // int32[poll batch]: phases active in round i
     DevBuf vieta;     // double4[2 * blocks]: per-block row sums and error terms (mixed mode)
     DevBuf errbuf;    // double[F * n_r]: estimated error of each polished root
+    DevBuf vsum;      // double4[2 * F]: each front's row sums (mixed mode)
     DevBuf reals_d;   // Real[n_real]
     DevBuf bmap;      // int2[blocks]: (front, block within front)
 
