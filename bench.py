@@ -60,6 +60,8 @@ def parse():
                     help="warm-row start: 0 previous row, 1 linear, 2 quadratic extrapolation")
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--schedule", default="rounds", choices=["rounds", "persistent"],
+                    help="root-finder scheduling: global rounds, or one persistent launch")
     ap.add_argument("--cpu-rows", type=int, default=4,
                     help="warm rows of the oracle timed for the CPU baseline")
     ap.add_argument("--compare", dest="compare", action="store_true", default=True,
@@ -130,7 +132,7 @@ def main():
         _, _, _, _, cn, st, _ = ctx.find_critical_curves(
             m_steps, n_subchains=args.subchains, timing=True, caustics=True,
             out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=prec,
-            predictor=args.predictor)
+            predictor=args.predictor, schedule=args.schedule)
         ctx.caustic_crossings(w_re, w_im, cn, grid, out=ncc)
         ctx.caustic_distances(grid, ncc, out=(dist, bl))
         return st
@@ -180,7 +182,7 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "n_stars": n, "roots_per_row": n_r, "phase_steps": m_steps,
                    "grid": [grid.nx, grid.ny], "precision": precision,
-                   "predictor": args.predictor, "seed": args.seed},
+                   "predictor": args.predictor, "schedule": args.schedule, "seed": args.seed},
         "roofline": {
             "bound": "alu",
             "kernel": dominant["kernel"],
@@ -292,7 +294,7 @@ def bench_batched(args, wl, precision):
         _, _, _, _, cn, st, _ = ctx.find_critical_curves(
             m_steps, n_subchains=args.subchains, timing=True, caustics=True,
             out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=prec,
-            predictor=args.predictor)
+            predictor=args.predictor, schedule=args.schedule)
         return st
 
     for i in range(args.warmup):
@@ -322,7 +324,8 @@ def bench_batched(args, wl, precision):
         "data": "synthetic",
         "config": {"workload": f"batched: {WORKLOAD_TEXT['batched']}", "fields": len(fs),
                    "total_stars": n_tot, "roots_per_row": 2 * n_tot, "phase_steps": m_steps,
-                   "precision": precision, "predictor": args.predictor, "seed": args.seed},
+                   "precision": precision, "predictor": args.predictor,
+                   "schedule": args.schedule, "seed": args.seed},
         "roofline": {"bound": "alu", "kernel": dominant["kernel"],
                      "achieved": dominant["achieved"], "peak": dominant["peak"],
                      "unit": "TFLOP/s", "frac": dominant["frac"], "traffic": None,

@@ -61,6 +61,15 @@ typedef enum {
                       same cutoffs as MLCC_FP64. */
 } mlcc_precision;
 
+typedef enum {
+    MLCC_SCHEDULE_ROUNDS = 0,     /* global rounds: every front's pass, then a control kernel
+                                     advancing all fronts; batches of rounds run as hipGraphs */
+    MLCC_SCHEDULE_PERSISTENT = 1  /* one persistent launch: (front, block) passes from a
+                                     device-side queue, each front advanced by the work group
+                                     that finishes its pass, no global rounds.  Same results
+                                     bit for bit. */
+} mlcc_schedule;
+
 /* Create a context on HIP device `device`, enqueuing on `hip_stream` (a
  * hipStream_t; NULL = the legacy default stream).  *out receives the context;
  * release it with mlcc_destroy. */
@@ -127,6 +136,8 @@ typedef struct {
                               same subchain (fewer rows are used where fewer
                               exist); the other roots enter that first pass at
                               their previous-row values */
+    int32_t schedule;      /* mlcc_schedule */
+    int32_t reserved;      /* 0 */
 } mlcc_cc_params;
 
 /* The paper's cutoffs (Sec. 3.2 footnote: 1e-9 and |mu| > 1e9),

@@ -283,6 +283,8 @@ template <class T> struct RoundArgs {
     double4 *vieta;    // two per block: row sums, and their error terms
     double *errbuf;    // estimated error of each polished root
     int32_t predictor;
+    int32_t persistent; // the persistent scheduler: iterates by per-front parity
+    double2 *iter0, *iter1;
 };
 
 // What one block knows about its front and star field.
@@ -293,18 +295,19 @@ template <class T> struct BlockCtx {
     int64_t base_f, out_off, bnd_row_off;
     const T *stars;
     const double2 *zsrc;
+    double2 *nxt;
     double m0, gamma, a, a1;
     double2 e;   // (1 - kappa_s) e^{-i phi} of the front's row
 };
 
 template <class T>
-__device__ __forceinline__ bool enter(const RoundArgs<T> &A, int phase, BlockCtx<T> &B)
+__device__ __forceinline__ bool enter_fq(const RoundArgs<T> &A, int phase, int f, int q,
+                                         BlockCtx<T> &B)
 {
-    const int2 fq = A.bmap[blockIdx.x];
-    B.f = fq.x;
-    B.q = fq.y;
+    B.f = f;
+    B.q = q;
     const Front *F = A.fronts + B.f;
-    if (F->state != FRONT_ACTIVE || F->phase != phase) return false;
+    if (F->state != FRONT_ACTIVE || (phase >= 0 && F->phase != phase)) return false;
     const Real *R = A.reals + F->real;
     B.row = F->row;
     B.stamp = F->stamp;
@@ -319,7 +322,13 @@ __device__ __forceinline__ bool enter(const RoundArgs<T> &A, int phase, BlockCtx
     B.a = R->a;
     B.a1 = R->a1;
     B.base_f = F->it_off;
-    B.zsrc = A.cur + A.fronts[F->src].it_off;
+    if (A.persistent) {   // every front keeps its own ping-pong parity
+        B.zsrc = (F->par ? A.iter1 : A.iter0) + F->it_off;
+        B.nxt = F->par ? A.iter0 : A.iter1;
+    } else {
+        B.zsrc = A.cur + A.fronts[F->src].it_off;
+        B.nxt = A.nxt;
+    }
     B.out_off = R->out_off;
     B.boundary = F->bnd_slot >= 0 && B.row == F->end_row;
     B.bnd_row_off = R->bnd_off + (int64_t)max(F->bnd_slot, 0) * R->n_r;
@@ -330,6 +339,14 @@ __device__ __forceinline__ bool enter(const RoundArgs<T> &A, int phase, BlockCtx
     B.k = B.k0 + B.lane;
     B.valid = B.k < B.n_r;
     return true;
+}
+
+// Block context of this work group in a round: (front, block) from bmap.
+template <class T>
+__device__ __forceinline__ bool enter(const RoundArgs<T> &A, int phase, BlockCtx<T> &B)
+{
+    const int2 fq = A.bmap[blockIdx.x];
+    return enter_fq(A, phase, fq.x, fq.y, B);
 }
 
 // Start of a new row's first pass for root k: extrapolation along its chain
@@ -371,14 +388,14 @@ __device__ __forceinline__ void put(const RoundArgs<T> &A, const BlockCtx<T> &B,
     }
 }
 
+// One FP64 Aberth pass of a block (the block context is set by enter()).
+// `tiles` holds two tiles of up to 32-byte records.
 template <bool EQUAL>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MLCC_SWEEP_WAVES, 8)))
-aberth_sweep_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
+__device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<EQUAL>::T> &A,
+                                               const BlockCtx<typename StarRec<EQUAL>::T> &B,
+                                               double4 *tiles)
 {
     using T = typename StarRec<EQUAL>::T;
-    __shared__ double4 tiles[128];   // two tiles of up to 32-byte records
-    BlockCtx<T> B;
-    if (!enter(A, PH_F64, B)) return;
     if (A.fronts[B.f].reseed) {
         // restart the row from its start values: the seeds z_i +- 1 for a
         // cold start, the previous row of the subchain otherwise
@@ -391,7 +408,7 @@ aberth_sweep_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
                 const int64_t o = B.out_off + (int64_t)(B.row - B.dir) * B.n_r + B.k;
                 z = make_double2(A.out_re[o], A.out_im[o]);
             }
-            A.nxt[B.base_f + B.k] = z;
+            B.nxt[B.base_f + B.k] = z;
         }
         const int n_valid = __popcll(__ballot(B.valid));
         if (threadIdx.x == 0) atomicAdd(&A.counts[B.f], n_valid);
@@ -402,7 +419,7 @@ aberth_sweep_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
     const int64_t base_f = B.base_f;
     const double2 *__restrict__ zsrc = B.zsrc;
     const T *__restrict__ stars = B.stars;
-    double2 *__restrict__ nxt = A.nxt;
+    double2 *__restrict__ nxt = B.nxt;
     int32_t *__restrict__ flagrow = A.flagrow;
     const double m0 = B.m0, gamma = B.gamma, a = B.a, a1 = B.a1;
     const double tol_step2 = A.tol_step2, tol_mu = A.tol_mu;
@@ -482,6 +499,16 @@ aberth_sweep_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
     }
 }
 
+template <bool EQUAL>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MLCC_SWEEP_WAVES, 8)))
+aberth_sweep_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
+{
+    __shared__ double4 tiles[128];
+    BlockCtx<typename StarRec<EQUAL>::T> B;
+    if (!enter(A, PH_F64, B)) return;
+    sweep_f64_pass<EQUAL>(A, B, tiles);
+}
+
 // ---------------------------------------------------------------------------
 // FP32 Aberth sweep (mixed mode: cold starts, rows without a prediction, and
 // rows the polish did not settle)
@@ -499,13 +526,11 @@ constexpr double TOL_F32 = 1e-6;
 // coordinates (they only steer the step).  The step itself and the new
 // iterate are FP64.
 template <bool EQUAL>
-__global__ void __launch_bounds__(64)
-aberth_sweep_f32(RoundArgs<typename StarRec<EQUAL>::T> A)
+__device__ __forceinline__ void sweep_f32_pass(const RoundArgs<typename StarRec<EQUAL>::T> &A,
+                                               const BlockCtx<typename StarRec<EQUAL>::T> &B,
+                                               double4 *tiles)
 {
     using T = typename StarRec<EQUAL>::T;
-    __shared__ double4 tiles[128];
-    BlockCtx<T> B;
-    if (!enter(A, PH_F32, B)) return;
     const int lane = B.lane, k0 = B.k0, k = B.k, n_r = B.n_r, n_stars = B.n_stars;
     const bool valid = B.valid;
     const int64_t base_f = B.base_f;
@@ -591,7 +616,7 @@ aberth_sweep_f32(RoundArgs<typename StarRec<EQUAL>::T> A)
     u.zr = zr - (Fr * Dr + Fi * Di) / den;
     u.zi = zi - (Fi * Dr - Fr * Di) / den;
     if (!isfinite(u.zr) || !isfinite(u.zi)) nudge(u, zr, zi, k);
-    if (valid) A.nxt[base_f + k] = make_double2(u.zr, u.zi);
+    if (valid) B.nxt[base_f + k] = make_double2(u.zr, u.zi);
     const int n_valid = __popcll(__ballot(valid));
     // roots that moved by more than the FP32 sweep can resolve are still
     // on their way (the control kernel uses this for cold starts)
@@ -601,6 +626,16 @@ aberth_sweep_f32(RoundArgs<typename StarRec<EQUAL>::T> A)
         if (n_moving) atomicAdd(&A.counts[B.f], n_moving);
         atomicAdd(&A.passupd[B.f], n_valid);
     }
+}
+
+template <bool EQUAL>
+__global__ void __launch_bounds__(64)
+aberth_sweep_f32(RoundArgs<typename StarRec<EQUAL>::T> A)
+{
+    __shared__ double4 tiles[128];
+    BlockCtx<typename StarRec<EQUAL>::T> B;
+    if (!enter(A, PH_F32, B)) return;
+    sweep_f32_pass<EQUAL>(A, B, tiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -695,19 +730,17 @@ __device__ __forceinline__ Update polish_finish(PSums S, double zr, double zi, d
 }
 
 template <bool EQUAL>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MLCC_POLISH_WAVES, 8)))
-newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
+__device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQUAL>::T> &A,
+                                            const BlockCtx<typename StarRec<EQUAL>::T> &B,
+                                            double4 *tiles)
 {
     using T = typename StarRec<EQUAL>::T;
-    __shared__ double4 tiles[128];
-    BlockCtx<T> B;
-    if (!enter(A, PH_POLISH, B)) return;
     const int lane = B.lane, k0 = B.k0, k = B.k, n_stars = B.n_stars;
     const bool valid = B.valid;
     const int64_t base_f = B.base_f;
     const double2 *__restrict__ zsrc = B.zsrc;
     const T *__restrict__ stars = B.stars;
-    double2 *__restrict__ nxt = A.nxt;
+    double2 *__restrict__ nxt = B.nxt;
     int32_t *__restrict__ flagrow = A.flagrow;
     const double m0 = B.m0, gamma = B.gamma, a = B.a, a1 = B.a1;
     const double tol_step2 = A.tol_step2, tol_mu = A.tol_mu;
@@ -791,6 +824,16 @@ newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
     }
 }
 
+template <bool EQUAL>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MLCC_POLISH_WAVES, 8)))
+newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
+{
+    __shared__ double4 tiles[128];
+    BlockCtx<typename StarRec<EQUAL>::T> B;
+    if (!enter(A, PH_POLISH, B)) return;
+    polish_pass<EQUAL>(A, B, tiles);
+}
+
 // ---------------------------------------------------------------------------
 // Seeds and front control
 // ---------------------------------------------------------------------------
@@ -868,7 +911,7 @@ __device__ __forceinline__ void row_done(Front &fr, int32_t *st, int f, int pred
 {
     if (fr.row == fr.end_row) {
         fr.state = FRONT_DONE;
-        st[f] = FRONT_DONE;
+        if (st) st[f] = FRONT_DONE;
     } else {
         fr.row += fr.dir;
         fr.hist = min(fr.hist + 1, 3);
@@ -879,8 +922,8 @@ __device__ __forceinline__ void row_done(Front &fr, int32_t *st, int f, int pred
 // Every root of the current row converged.  A cold start hands the upward
 // half of its subchain to its partner front and turns downward itself; a
 // warm row moves one row on or finishes at its end row.
-__device__ __forceinline__ void row_converged(Front &fr, int f, Front *fronts, int32_t *st,
-                                              int f0, int predictor)
+__device__ __forceinline__ int row_converged(Front &fr, int f, Front *fronts, int32_t *st,
+                                             int f0, int predictor)
 {
     if (fr.dir == 0) {
         fr.cold = fr.passes_row;
@@ -894,15 +937,108 @@ __device__ __forceinline__ void row_converged(Front &fr, int f, Front *fronts, i
         pr.hist = 1;   // the centre row
         start_row(pr, predictor);
         fronts[p] = pr;
-        st[p - f0] = FRONT_ACTIVE;
+        if (st) st[p - f0] = FRONT_ACTIVE;
         fr.dir = -1;
         fr.row = centre - 1;
         fr.hist = 1;
         start_row(fr, predictor);
-    } else {
-        fr.max_warm = max(fr.max_warm, fr.passes_row);
-        row_done(fr, st, f - f0, predictor);
+        return p;
     }
+    fr.max_warm = max(fr.max_warm, fr.passes_row);
+    row_done(fr, st, f - f0, predictor);
+    return -1;
+}
+
+// One front after its pass (c = its roots still unconverged, or, after an
+// FP32 sweep, still moving; rs = its row sums when the pass was a polish).
+// Returns the partner front a finished cold start activated, else -1.
+// `st` (the control kernel's LDS copy of the states) may be null.
+__device__ __attribute__((noinline)) int advance_front(Front &fr, int f, int32_t c, const double4 *rs, Front *fronts,
+                             int32_t *st, int f0, Control *ctl, const Real *reals,
+                             const double2 *unit, int max_cold, int max_warm, int predictor)
+{
+    int partner = -1;
+    fr.npass += 1;
+    fr.src = f;
+    fr.fresh = 0;
+    fr.passes_row += 1;
+    if (fr.phase == PH_F32) {
+        fr.f32 += 1;
+        bool polish = true;
+        if (fr.dir == 0) {
+            if (c < fr.best) {
+                fr.best = c;
+                fr.stall = 0;
+            } else {
+                fr.stall += 1;
+            }
+            polish = c == 0 || fr.stall >= F32_STALL || fr.f32 >= max_cold;
+        }
+        if (polish) {
+            if (fr.tried & TRIED_POLISH) fr.stamp += 1;   // polish every root again
+            fr.tried |= TRIED_F32;
+            fr.phase = PH_POLISH;
+            fr.passes = 0;
+        }
+    } else if (fr.phase == PH_POLISH) {
+        fr.tried |= TRIED_POLISH;
+        bool retry = false;
+        if (c == 0) {
+            const Real R = reals[fr.real];
+            const int bpf = (R.n_r + 63) / 64;
+            const double4 t = rs[0], q = rs[1];
+            const double a1r = t.x, a1i = t.y, a2r = t.z, a2i = t.w;
+            const double se = q.x, se2 = q.y, sa = q.z, sa2 = q.w;
+            const double2 u = unit[fr.row];
+            const double cr = R.gamma - R.a * u.x, ci = -R.a * u.y;   // c(phi)
+            const double cc = cr * cr + ci * ci;
+            const double mcr = R.M * cr / cc, mci = -R.M * ci / cc;   // M / c
+            const double e1r = a1r - 2.0 * R.sz_r, e1i = a1i - 2.0 * R.sz_i;
+            const double e2r = a2r - (2.0 * R.sz2_r - 2.0 * mcr);
+            const double e2i = a2i - (2.0 * R.sz2_i - 2.0 * mci);
+            const double u_ro = 1.1102230246251565e-16;
+            const double tol1 = 2.0 * se + 2.0 * (12 + bpf) * u_ro * sa + R.tol1;
+            const double tol2 = 2.0 * se2 + 2.0 * (13 + bpf) * u_ro * sa2 + R.tol2 +
+                                16.0 * u_ro * sqrt(mcr * mcr + mci * mci);
+            if (sqrt(e1r * e1r + e1i * e1i) <= tol1 && sqrt(e2r * e2r + e2i * e2i) <= tol2)
+                partner = row_converged(fr, f, fronts, st, f0, predictor);
+            else
+                retry = true;
+        } else if (++fr.passes >= MAX_POLISH) {
+            retry = true;
+        }
+        if (retry) {
+            if (!(fr.tried & TRIED_F32)) {
+                fr.phase = PH_F32;
+            } else {
+                // plain FP64 Aberth sweeps over every root from the row's
+                // start values: Newton steps may have sent two columns to
+                // one root, which Aberth steps from there would not undo
+                fr.stamp += 1;
+                fr.reseed = 1;
+                fr.phase = PH_F64;
+                fr.sweeps = 0;
+                atomicAdd((unsigned long long *)&ctl->rows_fallback, 1ull);
+            }
+        }
+    } else if (fr.reseed) {
+        fr.reseed = 0;   // the restart pass only reloaded the start values
+    } else if (c == 0) {
+        partner = row_converged(fr, f, fronts, st, f0, predictor);
+    } else {
+        fr.sweeps += 1;
+        if (fr.sweeps >= (fr.dir == 0 ? max_cold : max_warm)) {
+            fr.state = FRONT_FAILED;
+            if (st) st[f - f0] = FRONT_FAILED;
+            atomicAdd(&ctl->failed_rows, 1);
+            atomicAdd((unsigned long long *)&ctl->unconverged, (unsigned long long)c);
+            if (fr.dir == 0) {
+                fronts[fr.partner].state = FRONT_FAILED;
+                if (st) st[fr.partner - f0] = FRONT_FAILED;
+            }
+        }
+    }
+    return partner;
 }
 
 // Advances every front after a round (counts[f] = roots of front f still
@@ -967,85 +1103,8 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
         }
         const int32_t c = counts[f];
         counts[f] = 0;
-        fr.src = f;
-        fr.fresh = 0;
-        fr.passes_row += 1;
-        if (fr.phase == PH_F32) {
-            fr.f32 += 1;
-            bool polish = true;
-            if (fr.dir == 0) {
-                if (c < fr.best) {
-                    fr.best = c;
-                    fr.stall = 0;
-                } else {
-                    fr.stall += 1;
-                }
-                polish = c == 0 || fr.stall >= F32_STALL || fr.f32 >= max_cold;
-            }
-            if (polish) {
-                if (fr.tried & TRIED_POLISH) fr.stamp += 1;   // polish every root again
-                fr.tried |= TRIED_F32;
-                fr.phase = PH_POLISH;
-                fr.passes = 0;
-            }
-        } else if (fr.phase == PH_POLISH) {
-            fr.tried |= TRIED_POLISH;
-            bool retry = false;
-            if (c == 0) {
-                const Real R = reals[fr.real];
-                const int bpf = (R.n_r + 63) / 64;
-                const double4 t = vsum[2 * f], q = vsum[2 * f + 1];
-                const double a1r = t.x, a1i = t.y, a2r = t.z, a2i = t.w;
-                const double se = q.x, se2 = q.y, sa = q.z, sa2 = q.w;
-                const double2 u = unit[fr.row];
-                const double cr = R.gamma - R.a * u.x, ci = -R.a * u.y;   // c(phi)
-                const double cc = cr * cr + ci * ci;
-                const double mcr = R.M * cr / cc, mci = -R.M * ci / cc;   // M / c
-                const double e1r = a1r - 2.0 * R.sz_r, e1i = a1i - 2.0 * R.sz_i;
-                const double e2r = a2r - (2.0 * R.sz2_r - 2.0 * mcr);
-                const double e2i = a2i - (2.0 * R.sz2_i - 2.0 * mci);
-                const double u_ro = 1.1102230246251565e-16;
-                const double tol1 = 2.0 * se + 2.0 * (12 + bpf) * u_ro * sa + R.tol1;
-                const double tol2 = 2.0 * se2 + 2.0 * (13 + bpf) * u_ro * sa2 + R.tol2 +
-                                    16.0 * u_ro * sqrt(mcr * mcr + mci * mci);
-                if (sqrt(e1r * e1r + e1i * e1i) <= tol1 && sqrt(e2r * e2r + e2i * e2i) <= tol2)
-                    row_converged(fr, f, fronts, st, f0, predictor);
-                else
-                    retry = true;
-            } else if (++fr.passes >= MAX_POLISH) {
-                retry = true;
-            }
-            if (retry) {
-                if (!(fr.tried & TRIED_F32)) {
-                    fr.phase = PH_F32;
-                } else {
-                    // plain FP64 Aberth sweeps over every root from the row's
-                    // start values: Newton steps may have sent two columns to
-                    // one root, which Aberth steps from there would not undo
-                    fr.stamp += 1;
-                    fr.reseed = 1;
-                    fr.phase = PH_F64;
-                    fr.sweeps = 0;
-                    atomicAdd((unsigned long long *)&ctl->rows_fallback, 1ull);
-                }
-            }
-        } else if (fr.reseed) {
-            fr.reseed = 0;   // the restart pass only reloaded the start values
-        } else if (c == 0) {
-            row_converged(fr, f, fronts, st, f0, predictor);
-        } else {
-            fr.sweeps += 1;
-            if (fr.sweeps >= (fr.dir == 0 ? max_cold : max_warm)) {
-                fr.state = FRONT_FAILED;
-                st[f - f0] = FRONT_FAILED;
-                atomicAdd(&ctl->failed_rows, 1);
-                atomicAdd((unsigned long long *)&ctl->unconverged, (unsigned long long)c);
-                if (fr.dir == 0) {
-                    fronts[fr.partner].state = FRONT_FAILED;
-                    st[fr.partner - f0] = FRONT_FAILED;
-                }
-            }
-        }
+        advance_front(fr, f, c, vsum + 2 * f, fronts, st, f0, ctl, reals, unit, max_cold,
+                      max_warm, predictor);
         fronts[f] = fr;
     }
     for (int q = 0; q < 3; ++q) {
@@ -1095,6 +1154,185 @@ __global__ void control_begin(Control *__restrict__ ctl, int32_t *__restrict__ w
 __global__ void control_end(Control *__restrict__ ctl, const int32_t *__restrict__ workflag)
 {
     if (threadIdx.x == 0 && *workflag) ctl->live_sweeps += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent scheduler
+// ---------------------------------------------------------------------------
+//
+// One launch of as many single-wave work groups as fit on the chip.  Work
+// items are (front, block) passes in a device-side ring: a worker claims
+// the next slot, waits until it is filled, runs the pass the front's phase
+// asks for, and the worker that completes the last block of a front's pass
+// advances that front (advance_front) and queues its next pass, so fronts
+// move on independently instead of in global rounds.  Each front keeps its
+// own ping-pong parity; a cold start hands its converged centre row to its
+// partner by copying it into the partner's buffer.  No worker ever waits
+// for another one's pass: it waits only for its claimed slot, which the
+// worker that queued the work fills, and leaves when every front is done,
+// or, failing that, after a wall-clock interval without any pass finishing
+// anywhere (the call then reports an error).
+
+struct PQueue {
+    unsigned long long head;      // next slot to claim
+    unsigned long long tail;      // next slot to fill
+    unsigned long long progress;  // passes completed
+    int32_t done;                 // fronts finished (DONE or FAILED)
+    int32_t abort;                // a worker saw no progress for too long
+};
+
+__device__ __forceinline__ unsigned long long load_acquire(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t load_acquire(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Queues the bpf block passes of front f (whole wave).
+__device__ __forceinline__ void push_front(PQueue *q, int2 *tasks, unsigned long long *seq,
+                                           unsigned long long mask, int f, int bpf)
+{
+    unsigned long long base = 0;
+    if (threadIdx.x == 0) base = atomicAdd(&q->tail, (unsigned long long)bpf);
+    base = __shfl(base, 0, 64);
+    for (int i = threadIdx.x; i < bpf; i += 64) tasks[(base + i) & mask] = make_int2(f, i);
+    __threadfence();
+    for (int i = threadIdx.x; i < bpf; i += 64)
+        __hip_atomic_store(&seq[(base + i) & mask], base + i + 1, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool EQUAL>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MLCC_SWEEP_WAVES, 8)))
+aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ fronts_w,
+                  PQueue *__restrict__ q, int2 *__restrict__ tasks,
+                  unsigned long long *__restrict__ seq, unsigned long long mask,
+                  int32_t *__restrict__ fdone, int32_t n_fronts, int32_t max_cold,
+                  int32_t max_warm, unsigned long long stall_ticks)
+{
+    using T = typename StarRec<EQUAL>::T;
+    __shared__ double4 tiles[128];
+    const int lane = threadIdx.x;
+    for (;;) {
+        int tf = -1, tq = 0;
+        if (lane == 0) {
+            const unsigned long long t = atomicAdd(&q->head, 1ull);
+            unsigned long long seen = load_acquire(&q->progress);
+            unsigned long long t0 = wall_clock64();
+            for (;;) {
+                if (load_acquire(&q->abort)) break;
+                if (load_acquire(&seq[t & mask]) == t + 1) {
+                    const int2 w = tasks[t & mask];
+                    tf = w.x;
+                    tq = w.y;
+                    break;
+                }
+                if (load_acquire(&q->done) >= n_fronts) break;
+                const unsigned long long pnow = load_acquire(&q->progress);
+                const unsigned long long now = wall_clock64();
+                if (pnow != seen) {
+                    seen = pnow;
+                    t0 = now;
+                } else if (now - t0 > stall_ticks) {
+                    atomicExch(&q->abort, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
+            }
+        }
+        tf = __shfl(tf, 0, 64);
+        tq = __shfl(tq, 0, 64);
+        if (tf < 0) return;
+
+        BlockCtx<T> B;
+        if (enter_fq(A, -1, tf, tq, B)) {
+            const int ph = A.fronts[tf].phase;
+            if (ph == PH_F64)
+                sweep_f64_pass<EQUAL>(A, B, tiles);
+            else if (ph == PH_F32)
+                sweep_f32_pass<EQUAL>(A, B, tiles);
+            else
+                polish_pass<EQUAL>(A, B, tiles);
+        }
+        // the last block of the front's pass advances the front
+        __threadfence();
+        const Front *F = A.fronts + tf;
+        const Real *R = A.reals + F->real;
+        const int bpf = (R->n_r + 63) >> 6;
+        int last = 0;
+        if (lane == 0) last = atomicAdd(&fdone[tf], 1) + 1 == bpf;
+        last = __shfl(last, 0, 64);
+        if (!last) continue;
+        __threadfence();
+        Front fr = fronts_w[tf];
+        double4 rs[2] = {make_double4(0, 0, 0, 0), make_double4(0, 0, 0, 0)};
+        if (fr.phase == PH_POLISH) {
+            double v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0, v6 = 0, v7 = 0;
+            for (int b = lane; b < bpf; b += 64) {
+                const double4 t = A.vieta[2 * (fr.blk0 + b)], u = A.vieta[2 * (fr.blk0 + b) + 1];
+                v0 += t.x; v1 += t.y; v2 += t.z; v3 += t.w;
+                v4 += u.x; v5 += u.y; v6 += u.z; v7 += u.w;
+            }
+            wave_sum(v0); wave_sum(v1); wave_sum(v2); wave_sum(v3);
+            wave_sum(v4); wave_sum(v5); wave_sum(v6); wave_sum(v7);
+            rs[0] = make_double4(v0, v1, v2, v3);
+            rs[1] = make_double4(v4, v5, v6, v7);
+        }
+        int partner = -1, state = FRONT_ACTIVE, finished = 0;
+        int64_t p_off = 0;
+        int p_par = 0;
+        if (lane == 0) {
+            fdone[tf] = 0;
+            const unsigned long long u = (unsigned)A.passupd[tf];
+            A.passupd[tf] = 0;
+            const unsigned long long us = u * (unsigned)R->n_stars;
+            if (fr.phase == PH_F64) {
+                atomicAdd(&A.ctl->updates, u);
+                atomicAdd(&A.ctl->star_updates, us);
+            } else if (fr.phase == PH_F32) {
+                atomicAdd(&A.ctl->updates_f32, u);
+                atomicAdd(&A.ctl->star_updates_f32, us);
+            } else {
+                atomicAdd(&A.ctl->polish_updates, u);
+                atomicAdd(&A.ctl->star_updates_polish, us);
+            }
+            const int32_t c = A.counts[tf];
+            A.counts[tf] = 0;
+            const int dir0 = fr.dir;
+            partner = advance_front(fr, tf, c, rs, fronts_w, nullptr, 0, A.ctl, A.reals, A.unit,
+                                    max_cold, max_warm, A.predictor);
+            fr.par ^= 1;   // the pass wrote the other buffer
+            fronts_w[tf] = fr;
+            state = fr.state;
+            if (state != FRONT_ACTIVE) finished = (state == FRONT_FAILED && dir0 == 0) ? 2 : 1;
+            if (partner >= 0) {
+                p_off = fronts_w[partner].it_off;
+                p_par = fronts_w[partner].par;
+            }
+        }
+        partner = __shfl(partner, 0, 64);
+        state = __shfl(state, 0, 64);
+        finished = __shfl(finished, 0, 64);
+        if (partner >= 0) {
+            // the partner starts from the converged centre row
+            p_off = __shfl(p_off, 0, 64);
+            p_par = __shfl(p_par, 0, 64);
+            const int cur_par = __shfl(fr.par, 0, 64);
+            const int64_t my_off = __shfl(fr.it_off, 0, 64);
+            const double2 *src = (cur_par ? A.iter1 : A.iter0) + my_off;
+            double2 *dst = (p_par ? A.iter1 : A.iter0) + p_off;
+            for (int i = lane; i < R->n_r; i += 64) dst[i] = src[i];
+            __threadfence();
+            push_front(q, tasks, seq, mask, partner, bpf);
+        }
+        if (state == FRONT_ACTIVE) push_front(q, tasks, seq, mask, tf, bpf);
+        if (lane == 0) {
+            if (finished) atomicAdd(&q->done, finished);
+            atomicAdd(&q->progress, 1ull);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1438,7 +1676,8 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         (void)hipEventDestroy(done_ev[1]);
     };
 
-    const bool use_graphs = !p->timing;
+    const bool persistent = p->schedule == MLCC_SCHEDULE_PERSISTENT;
+    const bool use_graphs = !p->timing && !persistent;
     int parity = 0;
     int batch_len[2] = {0, 0};
     int G = 4;
@@ -1537,11 +1776,93 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         }
     };
 
+    // The persistent scheduler: one launch, fronts advance independently.
+    auto run_persistent = [&]() -> mlcc_status {
+        int64_t cap = 1024;
+        while (cap < 2 * nblocks) cap <<= 1;
+        const size_t o_tasks = 256, o_seq = o_tasks + (size_t)cap * sizeof(int2);
+        const size_t o_fdone = o_seq + (size_t)cap * sizeof(unsigned long long);
+        MLCC_TRY(c->pq.reserve(o_fdone + (size_t)F * sizeof(int32_t)));
+        char *base = static_cast<char *>(c->pq.p);
+        PQueue *dq = reinterpret_cast<PQueue *>(base);
+        int2 *dtasks = reinterpret_cast<int2 *>(base + o_tasks);
+        unsigned long long *dseq = reinterpret_cast<unsigned long long *>(base + o_seq);
+        int32_t *dfdone = reinterpret_cast<int32_t *>(base + o_fdone);
+        std::vector<int2> t0;
+        std::vector<unsigned long long> s0;
+        for (int f = 0; f < F; ++f) {
+            if (fr[f].state != FRONT_ACTIVE) continue;
+            for (int64_t qb = 0; qb < ceil_div(rd[fr[f].real].n_r, 64); ++qb) {
+                t0.push_back(make_int2(f, (int)qb));
+                s0.push_back((unsigned long long)s0.size() + 1);
+            }
+        }
+        PQueue hq{0ull, (unsigned long long)t0.size(), 0ull, 0, 0};
+        MLCC_HIP(hipMemsetAsync(base, 0, o_fdone + (size_t)F * sizeof(int32_t), rs));
+        MLCC_HIP(hipMemcpyAsync(dq, &hq, sizeof hq, hipMemcpyHostToDevice, rs));
+        MLCC_HIP(hipMemcpyAsync(dtasks, t0.data(), t0.size() * sizeof(int2), hipMemcpyHostToDevice,
+                                rs));
+        MLCC_HIP(hipMemcpyAsync(dseq, s0.data(), s0.size() * sizeof(unsigned long long),
+                                hipMemcpyHostToDevice, rs));
+        int cus = 0, per_cu = 0, clock_khz = 0;
+        MLCC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+        MLCC_HIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, c->device));
+        const void *kfn = equal ? reinterpret_cast<const void *>(&aberth_persistent<true>)
+                                : reinterpret_cast<const void *>(&aberth_persistent<false>);
+        MLCC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 64, 0));
+        if (cus < 1 || per_cu < 1 || clock_khz < 1)
+            return fail(MLCC_ERR_HIP, "cannot size the persistent launch");
+        const unsigned workers = (unsigned)(cus * per_cu);
+        // a worker gives up after 5 s in which no pass finished anywhere
+        const unsigned long long stall = (unsigned long long)clock_khz * 5000ull;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (p->timing) {
+            MLCC_HIP(hipEventCreate(&e0));
+            MLCC_HIP(hipEventCreate(&e1));
+            MLCC_HIP(hipEventRecord(e0, rs));
+        }
+        const double2 *cur0 = c->iter[0].as<double2>();
+        if (equal) {
+            fill(A2, c->stars.as<double2>(), cur0, c->iter[1].as<double2>());
+            A2.persistent = 1;
+            A2.iter0 = c->iter[0].as<double2>();
+            A2.iter1 = c->iter[1].as<double2>();
+            hipLaunchKernelGGL(aberth_persistent<true>, dim3(workers), dim3(64), 0, rs, A2,
+                               c->fronts.as<Front>(), dq, dtasks, dseq,
+                               (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm, stall);
+        } else {
+            fill(A4, c->stars4.as<double4>(), cur0, c->iter[1].as<double2>());
+            A4.persistent = 1;
+            A4.iter0 = c->iter[0].as<double2>();
+            A4.iter1 = c->iter[1].as<double2>();
+            hipLaunchKernelGGL(aberth_persistent<false>, dim3(workers), dim3(64), 0, rs, A4,
+                               c->fronts.as<Front>(), dq, dtasks, dseq,
+                               (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm, stall);
+        }
+        MLCC_HIP(hipGetLastError());
+        if (p->timing) MLCC_HIP(hipEventRecord(e1, rs));
+        MLCC_HIP(hipStreamSynchronize(rs));
+        if (p->timing) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            kind_ms[mixed ? 2 : 0] = ms;
+        }
+        kind_launches[mixed ? 2 : 0] = 1;
+        MLCC_HIP(hipMemcpy(&hq, dq, sizeof hq, hipMemcpyDeviceToHost));
+        if (hq.abort)
+            return fail(MLCC_ERR_HIP, "persistent scheduler: no pass finished for 5 s "
+                                      "(%d of %d fronts done)", hq.done, F);
+        return MLCC_OK;
+    };
+
     mlcc_status st = MLCC_OK;
     int slot = 0;
     auto t_last = std::chrono::steady_clock::now();
-    st = enqueue_batch(slot, G);
-    while (st == MLCC_OK) {
+    if (persistent) st = run_persistent();
+    else st = enqueue_batch(slot, G);
+    while (!persistent && st == MLCC_OK) {
         // keep one batch queued behind the one being polled
         const int next = slot ^ 1;
         if (use_graphs && !gexec[0] && polls == 1 && parity == 0) {
@@ -1676,7 +1997,13 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
 
     if (stats) {
         *stats = mlcc_cc_stats{};
-        stats->sweeps = h.live_sweeps;
+        if (persistent) {   // no global rounds: the longest chain of passes of one front
+            int64_t mp = 0;
+            for (const Front &x : fin) mp = std::max<int64_t>(mp, x.npass);
+            stats->sweeps = mp;
+        } else {
+            stats->sweeps = h.live_sweeps;
+        }
         stats->root_updates = (int64_t)h.updates;
         stats->root_updates_f32 = (int64_t)h.updates_f32;
         stats->polish_updates = (int64_t)h.polish_updates;

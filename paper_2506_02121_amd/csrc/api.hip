@@ -143,7 +143,7 @@ void mlcc_destroy(mlcc_ctx *ctx)
     (void)hipStreamSynchronize(c.stream);
     DevBuf *bufs[] = {&c.stars, &c.mass, &c.stars4, &c.iter[0], &c.iter[1], &c.flagrow, &c.fronts,
                       &c.counts, &c.control, &c.etab, &c.bnd, &c.perm, &c.match_aux,
-                      &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.vsum, &c.passupd, &c.reals_d, &c.bmap, &c.diff,
+                      &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.vsum, &c.pq, &c.passupd, &c.reals_d, &c.bmap, &c.diff,
                       &c.err, &c.edt_col};
     for (DevBuf *b : bufs) b->release();
     if (c.own_stream) (void)hipStreamDestroy(c.own_stream);
@@ -171,6 +171,7 @@ void mlcc_cc_params_default(mlcc_cc_params *p, int64_t m_steps)
     p->tol_inv_mu = 1e-9;
     p->timing = 0;
     p->predictor = 2;
+    p->schedule = MLCC_SCHEDULE_ROUNDS;
 }
 
 // Compensated (Neumaier) summation.
@@ -342,6 +343,8 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
         return fail(MLCC_ERR_INVALID, "unknown precision %d", p.precision);
     if (p.predictor < 0 || p.predictor > 2)
         return fail(MLCC_ERR_INVALID, "predictor must be 0, 1 or 2 (got %d)", p.predictor);
+    if (p.schedule != MLCC_SCHEDULE_ROUNDS && p.schedule != MLCC_SCHEDULE_PERSISTENT)
+        return fail(MLCC_ERR_INVALID, "unknown schedule %d", p.schedule);
     MLCC_TRY(check_device_ptr(&c, roots_re, "roots_re"));
     MLCC_TRY(check_device_ptr(&c, roots_im, "roots_im"));
     if ((caustics_re == nullptr) != (caustics_im == nullptr))

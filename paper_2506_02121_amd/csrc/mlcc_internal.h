@@ -73,6 +73,8 @@ struct Front {
     int32_t stall;    // FP32 sweeps since that count last fell
     int32_t passes_row; // passes of any kind on the current row
     int32_t reseed;   // 1: the next FP64 pass restarts the row from its start values
+    int32_t par;      // persistent scheduler: which iterate buffer holds the current values
+    int32_t npass;    // passes run by this front (all rows)
     int64_t it_off;   // first element of its roots in the iterate and flag arrays
 };
 
@@ -149,6 +151,7 @@ struct Ctx {
     DevBuf vieta;     // double4[2 * blocks]: per-block row sums and error terms (mixed mode)
     DevBuf errbuf;    // double[F * n_r]: estimated error of each polished root
     DevBuf vsum;      // double4[2 * F]: each front's row sums (mixed mode)
+    DevBuf pq;        // persistent scheduler: queue header, task ring, slot sequence, pass counts
     DevBuf reals_d;   // Real[n_real]
     DevBuf bmap;      // int2[blocks]: (front, block within front)
 

@@ -44,7 +44,8 @@ class CCParams(ctypes.Structure):
                 ("max_iter_cold", ctypes.c_int32), ("max_iter_warm", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("tol_step", ctypes.c_double),
                 ("tol_inv_mu", ctypes.c_double), ("timing", ctypes.c_int32),
-                ("predictor", ctypes.c_int32)]
+                ("predictor", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class CCStats(ctypes.Structure):
@@ -208,7 +209,8 @@ class Context:
                              max_iter_warm: int = 100, timing: bool = False,
                              chain_next: bool = True, caustics: bool = False, out=None,
                              caustics_out=None, raise_on_error: bool = True,
-                             precision: str = "fp64", predictor: int = 2):
+                             precision: str = "fp64", predictor: int = 2,
+                             schedule: str = "rounds"):
         """Returns (roots_re, roots_im, chain_next, stats, status), or with
         caustics=True (roots_re, roots_im, caus_re, caus_im, chain_next, stats,
         status).  One field: arrays are (m_steps + 1, 2N) float64 device
@@ -223,6 +225,7 @@ class Context:
         p.timing = int(bool(timing))
         p.precision = {"fp64": MLCC_FP64, "mixed": MLCC_MIXED}[precision]
         p.predictor = int(predictor)
+        p.schedule = {"rounds": 0, "persistent": 1}[schedule]
         n_r = 2 * self.n
         shape = (m_steps + 1, n_r) if self.star_offsets is None else ((m_steps + 1) * n_r,)
         if out is None:
