@@ -8,9 +8,10 @@ image of every root mapped in the same pass) + caustic_crossings +
 caustic_distances on one seeded synthetic field whose inputs are already in
 HBM.  Prints one JSON line:
   value           roots/s = m * 2N / (seconds per step)
-  roofline        the root-finder sweep kernel: algorithmic FP64 FLOP per
-                  sweep launch / its HIP-event-timed duration, against the
-                  FP64 vector peak
+  roofline        the root finder's dominant kernel (the persistent launch
+                  that runs every pass, by default): algorithmic FLOP per
+                  launch / its HIP-event-timed duration, against the vector
+                  peak of each part's precision
   cpu_baseline    the CPU oracle on a bounded sample of the same workload
 """
 from __future__ import annotations
@@ -60,7 +61,7 @@ def parse():
                     help="warm-row start: 0 previous row, 1 linear, 2 quadratic extrapolation")
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
-    ap.add_argument("--schedule", default="rounds", choices=["rounds", "persistent"],
+    ap.add_argument("--schedule", default="persistent", choices=["rounds", "persistent"],
                     help="root-finder scheduling: global rounds, or one persistent launch")
     ap.add_argument("--cpu-rows", type=int, default=4,
                     help="warm rows of the oracle timed for the CPU baseline")
@@ -150,7 +151,7 @@ def main():
             ts = time.perf_counter()
             stats.append(step(prec))
             torch.cuda.synchronize()
-            log(f"{prec} step {i}: {time.perf_counter() - ts:.3f} s, {stats[-1]['sweeps']} rounds")
+            log(f"{prec} step {i}: {time.perf_counter() - ts:.3f} s, {stats[-1]['sweeps']} passes / rounds")
         torch.cuda.synchronize()
         return time.perf_counter() - t0, stats
 
@@ -190,7 +191,7 @@ def main():
             "peak": dominant["peak"],
             "unit": "TFLOP/s",
             "frac": dominant["frac"],
-            "traffic": measured_traffic(args.workload) if dominant["kernel"] == "aberth_sweep_f64" else None,
+            "traffic": measured_traffic(dominant["kernel"], args.workload),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": dominant["avg_launch_ms"],
             "launches": dominant["launches"],
@@ -251,6 +252,21 @@ def kernel_line(stats, name, flop_key, ms_key, n_key, peak, dtype):
 
 
 def root_kernels(stats, precision):
+    if any(s["persistent_launches"] for s in stats):
+        # one launch runs every pass kind: its roofline prices the FP64 and
+        # the FP32 work each at its own peak
+        f64 = sum(s["algorithmic_flop"] + s["algorithmic_flop_polish"] for s in stats)
+        f32 = sum(s["algorithmic_flop_f32"] for s in stats)
+        ms = sum(s["persistent_ms"] for s in stats)
+        launches = sum(s["persistent_launches"] for s in stats)
+        t_peak = f64 / (FP64_VECTOR_PEAK_TFLOPS * 1e12) + f32 / (FP32_VECTOR_PEAK_TFLOPS * 1e12)
+        peak = (f64 + f32) / t_peak / 1e12 if t_peak > 0 else FP64_VECTOR_PEAK_TFLOPS
+        achieved = (f64 + f32) / (ms * 1e-3) / 1e12 if ms > 0 else None
+        return [{"kernel": "aberth_persistent", "dtype": "f64" if f32 == 0 else "f32+f64",
+                 "achieved": achieved, "peak": peak,
+                 "frac": achieved / peak if achieved else None, "time_s": ms * 1e-3,
+                 "avg_launch_ms": ms / launches, "launches": launches,
+                 "flop_f64": f64, "flop_f32": f32}]
     ks = [kernel_line(stats, "aberth_sweep_f64", "algorithmic_flop", "sweep_ms",
                       "sweep_launches", FP64_VECTOR_PEAK_TFLOPS, "f64")]
     if precision == "mixed":
@@ -309,7 +325,7 @@ def bench_batched(args, wl, precision):
         ts = time.perf_counter()
         stats.append(step())
         torch.cuda.synchronize()
-        log(f"step {i}: {time.perf_counter() - ts:.3f} s, {stats[-1]['sweeps']} rounds")
+        log(f"step {i}: {time.perf_counter() - ts:.3f} s, {stats[-1]['sweeps']} passes / rounds")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     roots_per_step = m_steps * 2 * n_tot
@@ -371,12 +387,12 @@ def bench_batched(args, wl, precision):
     print(json.dumps(out), flush=True)
 
 
-def measured_traffic(workload):
-    """HBM bytes per sweep launch from the committed counter summary, or None
-    when the workload differs or the kernel source changed since the counters
-    were taken."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none for this workload or the kernel source changed
+    since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "aberth_sweep_f64_n10k_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
     vals = {}

@@ -63,11 +63,14 @@ typedef enum {
 
 typedef enum {
     MLCC_SCHEDULE_ROUNDS = 0,     /* global rounds: every front's pass, then a control kernel
-                                     advancing all fronts; batches of rounds run as hipGraphs */
-    MLCC_SCHEDULE_PERSISTENT = 1  /* one persistent launch: (front, block) passes from a
-                                     device-side queue, each front advanced by the work group
-                                     that finishes its pass, no global rounds.  Same results
-                                     bit for bit. */
+                                     advancing all fronts; batches of rounds run as hipGraphs;
+                                     per-kind kernel times in the stats */
+    MLCC_SCHEDULE_PERSISTENT = 1  /* the default: one persistent launch, (front, block) passes
+                                     from a device-side queue, each front advanced by the work
+                                     group that finishes its pass, no global rounds.  Same
+                                     results bit for bit; no front waits for the slowest pass
+                                     of a round.  A launch in which no pass finishes for 5 s
+                                     ends with MLCC_ERR_HIP. */
 } mlcc_schedule;
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream` (a
@@ -128,7 +131,8 @@ typedef struct {
     double tol_step;       /* flag a root once |z^{a+1} - z^a| < tol_step; > 0 */
     double tol_inv_mu;     /* ... or once the App. C bound |F|(|F| + 2|1-kappa_s|) on
                               |1/mu| is below tol_inv_mu; 0 disables this test */
-    int32_t timing;        /* nonzero: time every sweep launch with HIP events */
+    int32_t timing;        /* nonzero: time the root-finder launches with HIP events (the
+                              round schedule then launches eagerly, without graphs) */
     int32_t predictor;     /* start of a warm row's first pass, for each root:
                               0 = its value in the previous row (the warm start of
                               Sec. 3.2); 1 = linear, 2 = quadratic extrapolation
@@ -142,11 +146,13 @@ typedef struct {
 
 /* The paper's cutoffs (Sec. 3.2 footnote: 1e-9 and |mu| > 1e9),
  * library-chosen subchains, FP64, quadratic chain predictor (predictor = 0
- * gives the paper's warm start from the previous row). */
+ * gives the paper's warm start from the previous row), persistent schedule. */
 void mlcc_cc_params_default(mlcc_cc_params *p, int64_t m_steps);
 
 typedef struct {
-    int64_t sweeps;          /* rounds that did work (one round = every pass kind once) */
+    int64_t sweeps;          /* MLCC_SCHEDULE_ROUNDS: rounds that did work (one round = every
+                                pass kind once); MLCC_SCHEDULE_PERSISTENT: passes of the
+                                front that made the most */
     int64_t root_updates;    /* FP64 Aberth root updates */
     int64_t root_updates_f32;/* FP32 Aberth root updates (MLCC_MIXED) */
     int64_t polish_updates;  /* FP64 Newton polish updates (MLCC_MIXED) */
@@ -166,6 +172,9 @@ typedef struct {
                                 add/mul/reciprocal = 1 */
     double algorithmic_flop_f32;    /* FP32 sweeps: root_updates_f32 * (29 N + 10 (2N - 1)) */
     double algorithmic_flop_polish; /* polish: polish_updates * 29 N (star terms only) */
+    double persistent_ms;    /* MLCC_SCHEDULE_PERSISTENT: GPU time of the one launch that runs
+                                every pass (timing != 0); the per-kind times above stay 0 */
+    int64_t persistent_launches;    /* 1 with MLCC_SCHEDULE_PERSISTENT, else 0 */
 } mlcc_cc_stats;
 
 /*

@@ -1173,13 +1173,22 @@ __global__ void control_end(Control *__restrict__ ctl, const int32_t *__restrict
 // or, failing that, after a wall-clock interval without any pass finishing
 // anywhere (the call then reports an error).
 
+// Queue header; every counter sits on a cache line of its own, so workers
+// polling one of them do not slow the atomics on another.
 struct PQueue {
     unsigned long long head;      // next slot to claim
+    unsigned long long pad0[31];
     unsigned long long tail;      // next slot to fill
+    unsigned long long pad1[31];
     unsigned long long progress;  // passes completed
+    unsigned long long pad2[31];
     int32_t done;                 // fronts finished (DONE or FAILED)
+    int32_t pad3[63];
     int32_t abort;                // a worker saw no progress for too long
+    int32_t pad4[63];
 };
+// Slot sequence numbers are spread one per 64-byte line.
+constexpr int SEQ_STRIDE = 8;
 
 __device__ __forceinline__ unsigned long long load_acquire(const unsigned long long *p)
 {
@@ -1188,6 +1197,14 @@ __device__ __forceinline__ unsigned long long load_acquire(const unsigned long l
 __device__ __forceinline__ int32_t load_acquire(const int32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long load_relaxed(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t load_relaxed(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Queues the bpf block passes of front f (whole wave).
@@ -1198,10 +1215,11 @@ __device__ __forceinline__ void push_front(PQueue *q, int2 *tasks, unsigned long
     if (threadIdx.x == 0) base = atomicAdd(&q->tail, (unsigned long long)bpf);
     base = __shfl(base, 0, 64);
     for (int i = threadIdx.x; i < bpf; i += 64) tasks[(base + i) & mask] = make_int2(f, i);
-    __threadfence();
+    // publishes the tasks and everything the wave wrote before them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     for (int i = threadIdx.x; i < bpf; i += 64)
-        __hip_atomic_store(&seq[(base + i) & mask], base + i + 1, __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&seq[((base + i) & mask) * SEQ_STRIDE], base + i + 1,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <bool EQUAL>
@@ -1219,27 +1237,31 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
         int tf = -1, tq = 0;
         if (lane == 0) {
             const unsigned long long t = atomicAdd(&q->head, 1ull);
-            unsigned long long seen = load_acquire(&q->progress);
+            const unsigned long long *my = &seq[(t & mask) * SEQ_STRIDE];
+            unsigned long long seen = load_relaxed(&q->progress);
             unsigned long long t0 = wall_clock64();
-            for (;;) {
-                if (load_acquire(&q->abort)) break;
-                if (load_acquire(&seq[t & mask]) == t + 1) {
+            for (unsigned it = 1;; ++it) {
+                if (load_relaxed(my) == t + 1) {
+                    (void)load_acquire(my);
                     const int2 w = tasks[t & mask];
                     tf = w.x;
                     tq = w.y;
                     break;
                 }
-                if (load_acquire(&q->done) >= n_fronts) break;
-                const unsigned long long pnow = load_acquire(&q->progress);
-                const unsigned long long now = wall_clock64();
-                if (pnow != seen) {
-                    seen = pnow;
-                    t0 = now;
-                } else if (now - t0 > stall_ticks) {
-                    atomicExch(&q->abort, 1);
-                    break;
+                if ((it & 31) == 0) {   // the shared counters, now and then
+                    if (load_relaxed(&q->abort)) break;
+                    if (load_relaxed(&q->done) >= n_fronts) break;
+                    const unsigned long long pnow = load_relaxed(&q->progress);
+                    const unsigned long long now = wall_clock64();
+                    if (pnow != seen) {
+                        seen = pnow;
+                        t0 = now;
+                    } else if (now - t0 > stall_ticks) {
+                        atomicExch(&q->abort, 1);
+                        break;
+                    }
                 }
-                __builtin_amdgcn_s_sleep(4);
+                __builtin_amdgcn_s_sleep(2);
             }
         }
         tf = __shfl(tf, 0, 64);
@@ -1256,8 +1278,9 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
             else
                 polish_pass<EQUAL>(A, B, tiles);
         }
-        // the last block of the front's pass advances the front
-        __threadfence();
+        // the last block of the front's pass advances the front; every
+        // block publishes its writes before counting itself done
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const Front *F = A.fronts + tf;
         const Real *R = A.reals + F->real;
         const int bpf = (R->n_r + 63) >> 6;
@@ -1265,7 +1288,7 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
         if (lane == 0) last = atomicAdd(&fdone[tf], 1) + 1 == bpf;
         last = __shfl(last, 0, 64);
         if (!last) continue;
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         Front fr = fronts_w[tf];
         double4 rs[2] = {make_double4(0, 0, 0, 0), make_double4(0, 0, 0, 0)};
         if (fr.phase == PH_POLISH) {
@@ -1324,7 +1347,6 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
             const double2 *src = (cur_par ? A.iter1 : A.iter0) + my_off;
             double2 *dst = (p_par ? A.iter1 : A.iter0) + p_off;
             for (int i = lane; i < R->n_r; i += 64) dst[i] = src[i];
-            __threadfence();
             push_front(q, tasks, seq, mask, partner, bpf);
         }
         if (state == FRONT_ACTIVE) push_front(q, tasks, seq, mask, tf, bpf);
@@ -1683,6 +1705,8 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     int G = 4;
     double kind_ms[KINDS] = {0.0, 0.0, 0.0};
     int64_t kind_launches[KINDS] = {0, 0, 0};
+    double persistent_ms = 0.0;
+    int64_t persistent_launches = 0;
     int32_t polls = 0;
     // Every front finishes within max_cold + (L/2 + 1) * (max_warm + polish
     // rounds) rounds; the extra margin covers the batches enqueued ahead of
@@ -1780,8 +1804,9 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     auto run_persistent = [&]() -> mlcc_status {
         int64_t cap = 1024;
         while (cap < 2 * nblocks) cap <<= 1;
-        const size_t o_tasks = 256, o_seq = o_tasks + (size_t)cap * sizeof(int2);
-        const size_t o_fdone = o_seq + (size_t)cap * sizeof(unsigned long long);
+        const size_t o_tasks = (sizeof(PQueue) + 255) & ~(size_t)255;
+        const size_t o_seq = o_tasks + (size_t)cap * sizeof(int2);
+        const size_t o_fdone = o_seq + (size_t)cap * SEQ_STRIDE * sizeof(unsigned long long);
         MLCC_TRY(c->pq.reserve(o_fdone + (size_t)F * sizeof(int32_t)));
         char *base = static_cast<char *>(c->pq.p);
         PQueue *dq = reinterpret_cast<PQueue *>(base);
@@ -1789,15 +1814,15 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         unsigned long long *dseq = reinterpret_cast<unsigned long long *>(base + o_seq);
         int32_t *dfdone = reinterpret_cast<int32_t *>(base + o_fdone);
         std::vector<int2> t0;
-        std::vector<unsigned long long> s0;
         for (int f = 0; f < F; ++f) {
             if (fr[f].state != FRONT_ACTIVE) continue;
-            for (int64_t qb = 0; qb < ceil_div(rd[fr[f].real].n_r, 64); ++qb) {
+            for (int64_t qb = 0; qb < ceil_div(rd[fr[f].real].n_r, 64); ++qb)
                 t0.push_back(make_int2(f, (int)qb));
-                s0.push_back((unsigned long long)s0.size() + 1);
-            }
         }
-        PQueue hq{0ull, (unsigned long long)t0.size(), 0ull, 0, 0};
+        std::vector<unsigned long long> s0(t0.size() * SEQ_STRIDE, 0ull);
+        for (size_t i = 0; i < t0.size(); ++i) s0[i * SEQ_STRIDE] = i + 1;
+        PQueue hq{};
+        hq.tail = (unsigned long long)t0.size();
         MLCC_HIP(hipMemsetAsync(base, 0, o_fdone + (size_t)F * sizeof(int32_t), rs));
         MLCC_HIP(hipMemcpyAsync(dq, &hq, sizeof hq, hipMemcpyHostToDevice, rs));
         MLCC_HIP(hipMemcpyAsync(dtasks, t0.data(), t0.size() * sizeof(int2), hipMemcpyHostToDevice,
@@ -1847,9 +1872,9 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
             (void)hipEventElapsedTime(&ms, e0, e1);
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
-            kind_ms[mixed ? 2 : 0] = ms;
+            persistent_ms = ms;
         }
-        kind_launches[mixed ? 2 : 0] = 1;
+        persistent_launches = 1;
         MLCC_HIP(hipMemcpy(&hq, dq, sizeof hq, hipMemcpyDeviceToHost));
         if (hq.abort)
             return fail(MLCC_ERR_HIP, "persistent scheduler: no pass finished for 5 s "
@@ -2026,6 +2051,8 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         stats->sweep_launches = kind_launches[0];
         stats->sweep_f32_launches = kind_launches[1];
         stats->polish_launches = kind_launches[2];
+        stats->persistent_ms = persistent_ms;
+        stats->persistent_launches = persistent_launches;
         // algorithmic FLOP of one update of a root of a field of N stars
         // (FMA = 2, add/mul/reciprocal = 1): 29 per star term (difference,
         // |d|^2, reciprocal, u, u^2, u^3 and their sums) and 10 per root

@@ -171,7 +171,7 @@ void mlcc_cc_params_default(mlcc_cc_params *p, int64_t m_steps)
     p->tol_inv_mu = 1e-9;
     p->timing = 0;
     p->predictor = 2;
-    p->schedule = MLCC_SCHEDULE_ROUNDS;
+    p->schedule = MLCC_SCHEDULE_PERSISTENT;
 }
 
 // Compensated (Neumaier) summation.

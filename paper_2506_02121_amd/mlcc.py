@@ -60,7 +60,8 @@ class CCStats(ctypes.Structure):
                 ("sweep_launches", ctypes.c_int64), ("sweep_f32_launches", ctypes.c_int64),
                 ("polish_launches", ctypes.c_int64),
                 ("algorithmic_flop", ctypes.c_double), ("algorithmic_flop_f32", ctypes.c_double),
-                ("algorithmic_flop_polish", ctypes.c_double)]
+                ("algorithmic_flop_polish", ctypes.c_double),
+                ("persistent_ms", ctypes.c_double), ("persistent_launches", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -210,7 +211,7 @@ class Context:
                              chain_next: bool = True, caustics: bool = False, out=None,
                              caustics_out=None, raise_on_error: bool = True,
                              precision: str = "fp64", predictor: int = 2,
-                             schedule: str = "rounds"):
+                             schedule: str = "persistent"):
         """Returns (roots_re, roots_im, chain_next, stats, status), or with
         caustics=True (roots_re, roots_im, caus_re, caus_im, chain_next, stats,
         status).  One field: arrays are (m_steps + 1, 2N) float64 device

@@ -179,7 +179,7 @@ def test_batched_invalid(ctx, mlcc):
 
 
 def test_graph_and_eager_rounds_agree(ctx):
-    """Without per-launch timing the rounds are replayed from captured
+    """Round schedule: without per-launch timing the rounds are replayed from captured
     hipGraphs (on the caller's stream, or on the context's own stream when
     the caller's is the null stream); with timing they are launched one by
     one.  All three give the same bits."""
@@ -192,7 +192,8 @@ def test_graph_and_eager_rounds_agree(ctx):
         s = torch.cuda.Stream() if side else torch.cuda.current_stream()
         with torch.cuda.stream(s):
             rr, ri, cr, ci, cn, st, code = ctx.find_critical_curves(
-                m_steps, n_subchains=S, caustics=True, precision="mixed", timing=timing)
+                m_steps, n_subchains=S, caustics=True, precision="mixed", timing=timing,
+                schedule="rounds")
         s.synchronize()
         out.append((rr.cpu().numpy(), ri.cpu().numpy(), cr.cpu().numpy(), ci.cpu().numpy(),
                     cn.cpu().numpy()))
