@@ -168,13 +168,17 @@ typedef struct {
     double sweep_f32_ms;     /* same, FP32 sweep launches */
     double polish_ms;        /* same, polish launches */
     int64_t sweep_launches, sweep_f32_launches, polish_launches;   /* launches that did work */
-    double algorithmic_flop; /* FP64 sweeps: root_updates * (29 N + 10 (2N - 1)); FMA = 2,
+    double algorithmic_flop; /* FP64 sweeps, FP64 part: root_updates * 29 N (star terms) plus
+                                10 (2N - 1) per update whose root-root terms run in FP64
+                                (cold starts, the mixed form's restarts); FMA = 2,
                                 add/mul/reciprocal = 1 */
     double algorithmic_flop_f32;    /* FP32 sweeps: root_updates_f32 * (29 N + 10 (2N - 1)) */
     double algorithmic_flop_polish; /* polish: polish_updates * 29 N (star terms only) */
     double persistent_ms;    /* MLCC_SCHEDULE_PERSISTENT: GPU time of the one launch that runs
                                 every pass (timing != 0); the per-kind times above stay 0 */
     int64_t persistent_launches;    /* 1 with MLCC_SCHEDULE_PERSISTENT, else 0 */
+    double algorithmic_flop_sweep_roots; /* FP64 sweeps, FP32 part: 10 (2N - 1) per update of
+                                a warm MLCC_FP64 row (its root-root terms run in FP32) */
 } mlcc_cc_stats;
 
 /*

@@ -183,6 +183,31 @@ __device__ __forceinline__ void add_root(Sums &S, double zr, double zi, const do
     S.Ri = fma(-dy, inv, S.Ri);
 }
 
+// The same root-root term with FP32 arithmetic, for the dense sweep.  Each
+// coordinate enters as an FP32 pair hi + lo (hi = the FP64 value rounded to
+// FP32, lo = the rounded remainder), and the difference is formed as
+// (hi_k - hi_r) + (lo_k - lo_r): the first difference is exact for nearby
+// roots, so the distance carries FP32 relative accuracy (~2^-24) at any
+// separation, as does the FP32 reciprocal.  That matches the ~2^-24 of the
+// unrefined FP64 reciprocal above; the term runs at the FP32 issue rate.
+struct SplitRoot {
+    __device__ __forceinline__ float4 operator()(const double2 &o) const
+    {
+        const float hx = (float)o.x, hy = (float)o.y;
+        return make_float4(hx, hy, (float)(o.x - (double)hx), (float)(o.y - (double)hy));
+    }
+};
+
+__device__ __forceinline__ void add_root_hl(float &Rr, float &Ri, const float4 &z,
+                                            const float4 &o)
+{
+    const float dx = (z.x - o.x) + (z.z - o.z);
+    const float dy = (z.y - o.y) + (z.w - o.w);
+    const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, dy * dy));
+    Rr = fmaf(dx, inv, Rr);
+    Ri = fmaf(-dy, inv, Ri);
+}
+
 struct Update {
     double zr, zi;   // new iterate
     double wr, wi;   // its image under the lens map
@@ -388,6 +413,15 @@ __device__ __forceinline__ void put(const RoundArgs<T> &A, const BlockCtx<T> &B,
     }
 }
 
+// Which FP64 Aberth passes take the root-root sum in FP32 (add_root_hl):
+// warm rows of the FP64 form.  Cold starts, where the repulsion between the
+// iterates steers global convergence from the seeds, and the mixed form's
+// FP64 restarts of difficult rows keep it in FP64 (add_root).
+__device__ __forceinline__ bool fast_roots_pass(const Front &fr)
+{
+    return fr.dir != 0 && fr.mode == PH_F64;
+}
+
 // One FP64 Aberth pass of a block (the block context is set by enter()).
 // `tiles` holds two tiles of up to 32-byte records.
 template <bool EQUAL>
@@ -477,21 +511,48 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
         zero(S);
         stream_tiles(stars, n_stars, reinterpret_cast<T *>(tiles),
                      [&](int, const T &s) { add_star<EQUAL>(S, zr, zi, s); });
-        double2 *rtiles = reinterpret_cast<double2 *>(tiles);
-        auto other = [&](int, const double2 &o) { add_root(S, zr, zi, o); };
+        if (!fast_roots_pass(A.fronts[B.f])) {
+            double2 *rtiles = reinterpret_cast<double2 *>(tiles);
+            auto other = [&](int, const double2 &o) { add_root(S, zr, zi, o); };
+            const int own_hi = min(k0 + 64, n_r);
+            stream_tiles(zsrc, k0, rtiles, other);
+            stream_tiles(zsrc + k0, own_hi - k0, rtiles, [&](int j, const double2 &o) {
+                Sums T2 = S;
+                add_root(T2, zr, zi, o);
+                const bool self = j == lane;
+                S.Rr = self ? S.Rr : T2.Rr;
+                S.Ri = self ? S.Ri : T2.Ri;
+            });
+            stream_tiles(zsrc + own_hi, n_r - own_hi, rtiles, other);
+            const Update u = finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k);
+            if (act) store(k, u);
+            n_after = __popcll(__ballot(act && !u.flag));
+        } else {
+        // root-root sum in FP32 (add_root_hl), summed per tile and carried
+        // across tiles in FP64
+        float4 *rtiles = reinterpret_cast<float4 *>(tiles);
+        const float4 zs = SplitRoot{}(make_double2(zr, zi));
+        float pr = 0.f, pi = 0.f;
+        auto other = [&](int, const float4 &o) { add_root_hl(pr, pi, zs, o); };
+        auto carry = [&]() {
+            S.Rr += (double)pr;
+            S.Ri += (double)pi;
+            pr = pi = 0.f;
+        };
         const int own_hi = min(k0 + 64, n_r);
-        stream_tiles(zsrc, k0, rtiles, other);
-        stream_tiles(zsrc + k0, own_hi - k0, rtiles, [&](int j, const double2 &o) {
-            Sums T2 = S;
-            add_root(T2, zr, zi, o);
+        stream_tiles_ex(zsrc, k0, rtiles, SplitRoot{}, other, carry);
+        stream_tiles_ex(zsrc + k0, own_hi - k0, rtiles, SplitRoot{}, [&](int j, const float4 &o) {
+            float tr = pr, ti = pi;
+            add_root_hl(tr, ti, zs, o);
             const bool self = j == lane;
-            S.Rr = self ? S.Rr : T2.Rr;
-            S.Ri = self ? S.Ri : T2.Ri;
-        });
-        stream_tiles(zsrc + own_hi, n_r - own_hi, rtiles, other);
+            pr = self ? pr : tr;
+            pi = self ? pi : ti;
+        }, carry);
+        stream_tiles_ex(zsrc + own_hi, n_r - own_hi, rtiles, SplitRoot{}, other, carry);
         const Update u = finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k);
         if (act) store(k, u);
         n_after = __popcll(__ballot(act && !u.flag));
+        }
     }
     if (lane == 0) {
         if (n_after) atomicAdd(&A.counts[B.f], n_after);
@@ -1079,7 +1140,7 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
 {
     __shared__ int32_t st[4096];
     __shared__ int32_t s_active, s_live;
-    __shared__ unsigned long long s_upd[3], s_star[3];
+    __shared__ unsigned long long s_upd[4], s_star[4];   // by phase; [3]: fast-root FP64 passes
     const int tid = threadIdx.x;
     const int f0 = blockIdx.x * fronts_per_group;
     const int f1 = min(n_fronts, f0 + fronts_per_group);
@@ -1087,8 +1148,8 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
         s_active = 0;
         s_live = 0;
     }
-    if (tid < 3) s_upd[tid] = s_star[tid] = 0ull;
-    unsigned long long my_upd[3] = {0ull, 0ull, 0ull}, my_star[3] = {0ull, 0ull, 0ull};
+    if (tid < 4) s_upd[tid] = s_star[tid] = 0ull;
+    unsigned long long my_upd[4] = {0ull, 0ull, 0ull, 0ull}, my_star[4] = {0ull, 0ull, 0ull, 0ull};
     for (int f = f0 + tid; f < f1; f += CONTROL_THREADS) st[f - f0] = fronts[f].state;
     __syncthreads();
     for (int f = f0 + tid; f < f1; f += CONTROL_THREADS) {
@@ -1098,8 +1159,13 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
         {   // this round's updates of the front, by pass kind (FLOP counts weigh them by N)
             const unsigned long long u = (unsigned)passupd[f];
             passupd[f] = 0;
+            const unsigned long long us = u * (unsigned)reals[fr.real].n_stars;
             my_upd[fr.phase] += u;
-            my_star[fr.phase] += u * (unsigned)reals[fr.real].n_stars;
+            my_star[fr.phase] += us;
+            if (fr.phase == PH_F64 && fast_roots_pass(fr)) {
+                my_upd[3] += u;
+                my_star[3] += us;
+            }
         }
         const int32_t c = counts[f];
         counts[f] = 0;
@@ -1107,7 +1173,7 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
                       max_warm, predictor);
         fronts[f] = fr;
     }
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 4; ++q) {
         if (my_upd[q]) {
             atomicAdd(&s_upd[q], my_upd[q]);
             atomicAdd(&s_star[q], my_star[q]);
@@ -1126,6 +1192,10 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
         if (s_upd[PH_POLISH]) {
             atomicAdd(&ctl->polish_updates, s_upd[PH_POLISH]);
             atomicAdd(&ctl->star_updates_polish, s_star[PH_POLISH]);
+        }
+        if (s_upd[3]) {
+            atomicAdd(&ctl->updates_fast, s_upd[3]);
+            atomicAdd(&ctl->star_updates_fast, s_star[3]);
         }
     }
     int mine = 0;
@@ -1314,6 +1384,10 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
             if (fr.phase == PH_F64) {
                 atomicAdd(&A.ctl->updates, u);
                 atomicAdd(&A.ctl->star_updates, us);
+                if (fast_roots_pass(fr)) {
+                    atomicAdd(&A.ctl->updates_fast, u);
+                    atomicAdd(&A.ctl->star_updates_fast, us);
+                }
             } else if (fr.phase == PH_F32) {
                 atomicAdd(&A.ctl->updates_f32, u);
                 atomicAdd(&A.ctl->star_updates_f32, us);
@@ -2059,7 +2133,12 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         // term, 29 N + 10 (2N - 1) for an Aberth update, 29 N for a polish
         // update (star terms only); the device counts updates and
         // updates x N, which gives the sums over mixed field sizes
-        stats->algorithmic_flop = 49.0 * (double)h.star_updates - 10.0 * (double)h.updates;
+        // star terms in FP64; root terms in FP64 except in fast-root passes
+        stats->algorithmic_flop = 29.0 * (double)h.star_updates +
+                                  20.0 * (double)(h.star_updates - h.star_updates_fast) -
+                                  10.0 * (double)(h.updates - h.updates_fast);
+        stats->algorithmic_flop_sweep_roots =
+            20.0 * (double)h.star_updates_fast - 10.0 * (double)h.updates_fast;
         stats->algorithmic_flop_f32 =
             49.0 * (double)h.star_updates_f32 - 10.0 * (double)h.updates_f32;
         stats->algorithmic_flop_polish = 29.0 * (double)h.star_updates_polish;

@@ -116,6 +116,8 @@ struct Control {
     unsigned long long star_updates;  // sum over FP64 updates of the field's star count
     unsigned long long star_updates_f32;
     unsigned long long star_updates_polish;
+    unsigned long long updates_fast;      // FP64 Aberth updates of warm FP64-mode rows, whose
+    unsigned long long star_updates_fast; // root-root terms run in FP32 (and their star counts)
 };
 
 struct Ctx {
