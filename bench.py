@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--compare", dest="compare", action="store_true", default=True,
                     help="also run the other precision (mixed vs FP64) on the same field")
     ap.add_argument("--no-compare", dest="compare", action="store_false")
+    ap.add_argument("--serial", dest="serial", action="store_true", default=True,
+                    help="batched workload: also solve every field alone, one call each")
+    ap.add_argument("--no-serial", dest="serial", action="store_false")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (to scale "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -128,15 +131,31 @@ def main():
     torch.cuda.synchronize()
 
     def step(prec):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
         ctx.set_lenses(x, y, mm, f.kappa_s, f.gamma)
         # roots and, in the same pass, their caustic images
         _, _, _, _, cn, st, _ = ctx.find_critical_curves(
             m_steps, n_subchains=args.subchains, timing=True, caustics=True,
             out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=prec,
             predictor=args.predictor, schedule=args.schedule)
+        ev[1].record()
         ctx.caustic_crossings(w_re, w_im, cn, grid, out=ncc)
+        ev[2].record()
         ctx.caustic_distances(grid, ncc, out=(dist, bl))
+        ev[3].record()
+        st["_events"] = ev
         return st
+
+    def stage_ms(stats):
+        """Per-stage GPU time (HIP events on the context's stream), averaged."""
+        out = {"lenses_roots_caustics": 0.0, "crossing_map": 0.0, "distance_map": 0.0}
+        for s_ in stats:
+            ev = s_.pop("_events")
+            out["lenses_roots_caustics"] += ev[0].elapsed_time(ev[1]) / len(stats)
+            out["crossing_map"] += ev[1].elapsed_time(ev[2]) / len(stats)
+            out["distance_map"] += ev[2].elapsed_time(ev[3]) / len(stats)
+        return out
 
     def run(prec, warmup, steps):
         for i in range(warmup):
@@ -153,11 +172,30 @@ def main():
             torch.cuda.synchronize()
             log(f"{prec} step {i}: {time.perf_counter() - ts:.3f} s, {stats[-1]['sweeps']} passes / rounds")
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, stats
+        el = time.perf_counter() - t0
+        return el, stats
 
     elapsed, stats = run(precision, args.warmup, args.steps)
     ms_per_step = 1e3 * elapsed / args.steps
     roots_per_step = m_steps * n_r
+    stages = stage_ms(stats)
+    # the standalone lens mapping on a sample of the roots (the step uses the
+    # fused mapping): points/s and algorithmic TFLOP/s at 12 N FLOP per point
+    n_map = min(rows, max(1, (1 << 26) // n_r))
+    zr_s, zi_s = roots_re[:n_map].reshape(-1), roots_im[:n_map].reshape(-1)
+    wr_s, wi_s = torch.empty_like(zr_s), torch.empty_like(zi_s)
+    ctx.set_lenses(x, y, mm, f.kappa_s, f.gamma)
+    ctx.map_caustics(zr_s, zi_s, out=(wr_s, wi_s))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    ctx.map_caustics(zr_s, zi_s, out=(wr_s, wi_s))
+    ev[1].record()
+    torch.cuda.synchronize()
+    map_ms = ev[0].elapsed_time(ev[1])
+    stages["map_caustics_standalone"] = {
+        "points": n_map * n_r, "ms": map_ms, "points_per_s": n_map * n_r / (map_ms * 1e-3),
+        "tflops": 12.0 * n * n_map * n_r / (map_ms * 1e-3) / 1e12}
+    del zr_s, zi_s, wr_s, wi_s
     value = roots_per_step / (elapsed / args.steps)
 
     kernels = root_kernels(stats, precision)
@@ -197,7 +235,10 @@ def main():
             "launches": dominant["launches"],
             "flop_per_root_update": 29 * n + 10 * (n_r - 1),
             "kernels": kernels,
+            "measured_peak": measured_peaks(dominant),
         },
+        "stage_ms": stages,
+        "root_updates_per_s": (s0_updates(stats[-1])) / (elapsed / args.steps),
         "stats": {"sweeps_per_step": s0["sweeps"], "root_updates_per_step": s0["root_updates"],
                   "root_updates_f32_per_step": s0["root_updates_f32"],
                   "polish_updates_per_step": s0["polish_updates"],
@@ -237,6 +278,28 @@ def main():
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(f, m_steps, args.cpu_rows)
     print(json.dumps(out), flush=True)
+
+
+def s0_updates(st):
+    """Root updates of every kind in one call."""
+    return st["root_updates"] + st["root_updates_f32"] + st["polish_updates"]
+
+
+def measured_peaks(k):
+    """The device's measured FMA-chain rates beside the published peaks, and
+    the dominant kernel's fraction of them (FP64 and FP32 parts each priced
+    at their measured rate)."""
+    from paper_2506_02121_amd import mlcc
+    p64 = mlcc.measure_valu_peak(0, "fp64")
+    p32 = mlcc.measure_valu_peak(0, "fp32")
+    out = {"fp64_fma_tflops": p64, "fp32_fma_tflops": p32,
+           "method": "8 independent FMA chains per lane, 8 waves per SIMD, HIP events"}
+    f64 = k.get("flop_f64")
+    f32 = k.get("flop_f32")
+    if f64 is not None and k["time_s"] > 0:
+        t = f64 / (p64 * 1e12) + f32 / (p32 * 1e12)
+        out["kernel_frac_of_measured"] = t / k["time_s"]
+    return out
 
 
 def kernel_line(stats, name, flop_key, ms_key, n_key, peak, dtype, f32_key=None):
@@ -359,24 +422,54 @@ def bench_batched(args, wl, precision):
                                      "polish_updates", "rows_fallback", "n_subchains",
                                      "cold_sweeps", "max_row_sweeps", "match_maxdist")},
     }
+    from scipy.spatial import cKDTree
+    blocks = ctx.field_blocks(m_steps)
+    picks = np.linspace(0, len(fs) - 1, 8).astype(int)
+    rows = np.linspace(0, m_steps, 9).astype(np.int64)
+
+    def sample():
+        got = []
+        for i in picks:
+            o, _, n_r = blocks[i]
+            for j in rows:
+                a = slice(o + j * n_r, o + (j + 1) * n_r)
+                got.append(np.stack([roots_re[a].cpu().numpy(), roots_im[a].cpu().numpy()], 1))
+        return got
+    ref = sample()
+    if args.serial:
+        # the same fields one call each through the single-field path, same
+        # precision, writing their blocks of the same output arrays
+        def serial_pass():
+            for i, f in enumerate(fs):
+                o, _, n_r = blocks[i]
+                sl = slice(o, o + (m_steps + 1) * n_r)
+                shape = (m_steps + 1, n_r)
+                ctx.set_lenses(x[off[i]:off[i + 1]], y[off[i]:off[i + 1]], mm[off[i]:off[i + 1]],
+                               f.kappa_s, f.gamma)
+                ctx.find_critical_curves(
+                    m_steps, caustics=True, precision=precision, predictor=args.predictor,
+                    schedule=args.schedule,
+                    out=(roots_re[sl].view(shape), roots_im[sl].view(shape)),
+                    caustics_out=(w_re[sl].view(shape), w_im[sl].view(shape)))
+            torch.cuda.synchronize()
+        serial_pass()   # warm-up: buffers grow to the largest field once
+        t0 = time.perf_counter()
+        serial_pass()
+        el_s = time.perf_counter() - t0
+        dmax_s = max(float(cKDTree(b).query(a)[0].max()) for a, b in zip(ref, sample()))
+        out["serial"] = {
+            "what": "every field alone, one find_critical_curves call each (roots and caustics)",
+            "value": roots_per_step / el_s, "ms_per_step": 1e3 * el_s,
+            "speedup_of_batched": el_s / (elapsed / args.steps),
+            "max_root_distance_to_batched_run": dmax_s,
+            "sampled": f"{len(picks)} fields x {len(rows)} rows"}
+        log(f"serial: {el_s:.3f} s for {len(fs)} calls, max root distance {dmax_s:.2e}")
+        step()   # the batched result again, for the comparison below
+        ref = sample()
     if args.compare:
         # the other precision on the same fields: throughput, and how far its
         # roots lie from this run's on sampled rows of sampled fields
-        from scipy.spatial import cKDTree
         other = "mixed" if precision == "fp64" else "fp64"
-        blocks = ctx.field_blocks(m_steps)
-        picks = np.linspace(0, len(fs) - 1, 8).astype(int)
-        rows = np.linspace(0, m_steps, 9).astype(np.int64)
-
-        def sample():
-            got = []
-            for i in picks:
-                o, _, n_r = blocks[i]
-                for j in rows:
-                    a = slice(o + j * n_r, o + (j + 1) * n_r)
-                    got.append(np.stack([roots_re[a].cpu().numpy(), roots_im[a].cpu().numpy()], 1))
-            return got
-        ref = sample()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st2 = [step(other) for _ in range(args.steps)]

@@ -294,6 +294,17 @@ mlcc_status mlcc_caustic_crossings(mlcc_ctx *ctx, int64_t rows, int64_t n_r,
 mlcc_status mlcc_caustic_distances(mlcc_ctx *ctx, const mlcc_grid *grid, const int32_t *ncc,
                                    double *dist, uint8_t *border_limited);
 
+/*
+ * measure_valu_peak -- a measurement aid, not an operation of the paper: the
+ * vector-ALU rate this device reaches on independent FMA chains (kind 0 =
+ * FP64 v_fma_f64, 1 = FP32 v_fma_f32, unpacked), in TFLOP/s (FMA = 2 FLOP),
+ * the achievable reference beside the published peaks in the rooflines of
+ * the root-finder kernels.  Runs ~0.1 s of kernels on a stream of its own on
+ * `device` (allocates and frees 2 MB); synchronous.
+ *   tflops  host double, written on success
+ */
+mlcc_status mlcc_measure_valu_peak(int device, int kind, double *tflops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,7 +35,7 @@ EXPORTED = [
     "mlcc_create", "mlcc_destroy", "mlcc_set_stream", "mlcc_last_error", "mlcc_set_lenses",
     "mlcc_set_lenses_batched", "mlcc_cc_params_default", "mlcc_find_critical_curves",
     "mlcc_find_critical_curves_batched", "mlcc_map_caustics",
-    "mlcc_caustic_crossings", "mlcc_caustic_distances",
+    "mlcc_caustic_crossings", "mlcc_caustic_distances", "mlcc_measure_valu_peak",
 ]
 
 
@@ -93,6 +93,7 @@ _SIG = {
     "mlcc_caustic_crossings": ([_vp, _i64, _i64, _vp, _vp, _vp, ctypes.POINTER(GridC), _vp],
                                ctypes.c_int),
     "mlcc_caustic_distances": ([_vp, ctypes.POINTER(GridC), _vp, _vp, _vp], ctypes.c_int),
+    "mlcc_measure_valu_peak": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(_d)], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIG.items():
     _f = getattr(_lib, _name)
@@ -109,6 +110,17 @@ class MlccError(RuntimeError):
 def _check(code: int):
     if code != MLCC_OK:
         raise MlccError(code, _lib.mlcc_last_error().decode())
+
+
+def measure_valu_peak(device: int = 0, kind: str = "fp64") -> float:
+    """TFLOP/s this device reaches on independent FMA chains ("fp64" or
+    "fp32", unpacked): the measured reference beside the published peaks."""
+    kinds = {"fp64": 0, "fp32": 1}
+    if kind not in kinds:
+        raise ValueError(f"kind must be one of {sorted(kinds)}")
+    out = _d(0.0)
+    _check(_lib.mlcc_measure_valu_peak(int(device), kinds[kind], ctypes.byref(out)))
+    return out.value
 
 
 def _ptr(t: Optional[torch.Tensor]):

@@ -166,3 +166,18 @@ def test_mixed_restart_after_doubled_root(ctx):
     print("[stats]", {k: st[k] for k in ("rows_fallback", "polish_updates", "root_updates")})
     assert st["rows_fallback"] >= 1
     against_oracle(f, R, W, cn, m_steps, S, colwise=False)
+
+
+def test_measured_valu_peak_is_plausible(mlcc):
+    """The FMA-chain probe reports a rate between a third of and just above
+    the published FP64 vector peak, 78.6 TFLOP/s, for FP64, and for unpacked
+    FP32 (the published 157.3 TFLOP/s counts packed FP32 instructions, which
+    issue two FMAs per lane)."""
+    say("valu probe")
+    p64 = mlcc.measure_valu_peak(0, "fp64")
+    p32 = mlcc.measure_valu_peak(0, "fp32")
+    print("[probe] FP64", p64, "FP32", p32, flush=True)
+    assert 0.33 * 78.6 < p64 < 1.1 * 78.6
+    assert 0.33 * 78.6 < p32 < 1.1 * 157.3
+    with pytest.raises(ValueError):
+        mlcc.measure_valu_peak(0, "fp16")
