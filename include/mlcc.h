@@ -69,8 +69,8 @@ typedef enum {
                                      from a device-side queue, each front advanced by the work
                                      group that finishes its pass, no global rounds.  Same
                                      results bit for bit; no front waits for the slowest pass
-                                     of a round.  A launch in which no pass finishes for 5 s
-                                     ends with MLCC_ERR_HIP. */
+                                     of a round.  A launch in which no pass finishes for
+                                     watchdog_ms (default 5 s) ends with MLCC_ERR_HIP. */
 } mlcc_schedule;
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream` (a
@@ -141,7 +141,9 @@ typedef struct {
                               exist); the other roots enter that first pass at
                               their previous-row values */
     int32_t schedule;      /* mlcc_schedule */
-    int32_t reserved;      /* 0 */
+    int32_t watchdog_ms;   /* MLCC_SCHEDULE_PERSISTENT: the launch gives up, and the call
+                              returns MLCC_ERR_HIP, once no pass has finished anywhere for this
+                              many milliseconds (0 = 5000; at most 600000) */
 } mlcc_cc_params;
 
 /* The paper's cutoffs (Sec. 3.2 footnote: 1e-9 and |mu| > 1e9),

@@ -1912,8 +1912,10 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         if (cus < 1 || per_cu < 1 || clock_khz < 1)
             return fail(MLCC_ERR_HIP, "cannot size the persistent launch");
         const unsigned workers = (unsigned)(cus * per_cu);
-        // a worker gives up after 5 s in which no pass finished anywhere
-        const unsigned long long stall = (unsigned long long)clock_khz * 5000ull;
+        // a worker gives up after watchdog_ms (default 5 s) in which no pass
+        // finished anywhere
+        const unsigned long long stall =
+            (unsigned long long)clock_khz * (unsigned long long)(p->watchdog_ms > 0 ? p->watchdog_ms : 5000);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (p->timing) {
             MLCC_HIP(hipEventCreate(&e0));
@@ -1951,8 +1953,9 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         persistent_launches = 1;
         MLCC_HIP(hipMemcpy(&hq, dq, sizeof hq, hipMemcpyDeviceToHost));
         if (hq.abort)
-            return fail(MLCC_ERR_HIP, "persistent scheduler: no pass finished for 5 s "
-                                      "(%d of %d fronts done)", hq.done, F);
+            return fail(MLCC_ERR_HIP, "persistent scheduler: no pass finished for %d ms "
+                                      "(%d of %d fronts done)",
+                        p->watchdog_ms > 0 ? p->watchdog_ms : 5000, hq.done, F);
         return MLCC_OK;
     };
 

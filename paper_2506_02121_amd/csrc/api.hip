@@ -345,6 +345,8 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
         return fail(MLCC_ERR_INVALID, "predictor must be 0, 1 or 2 (got %d)", p.predictor);
     if (p.schedule != MLCC_SCHEDULE_ROUNDS && p.schedule != MLCC_SCHEDULE_PERSISTENT)
         return fail(MLCC_ERR_INVALID, "unknown schedule %d", p.schedule);
+    if (p.watchdog_ms < 0 || p.watchdog_ms > 600000)
+        return fail(MLCC_ERR_INVALID, "watchdog_ms=%d outside [0, 600000]", p.watchdog_ms);
     MLCC_TRY(check_device_ptr(&c, roots_re, "roots_re"));
     MLCC_TRY(check_device_ptr(&c, roots_im, "roots_im"));
     if ((caustics_re == nullptr) != (caustics_im == nullptr))

@@ -45,7 +45,7 @@ class CCParams(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("tol_step", ctypes.c_double),
                 ("tol_inv_mu", ctypes.c_double), ("timing", ctypes.c_int32),
                 ("predictor", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("watchdog_ms", ctypes.c_int32)]
 
 
 class CCStats(ctypes.Structure):
@@ -224,7 +224,7 @@ class Context:
                              chain_next: bool = True, caustics: bool = False, out=None,
                              caustics_out=None, raise_on_error: bool = True,
                              precision: str = "fp64", predictor: int = 2,
-                             schedule: str = "persistent"):
+                             schedule: str = "persistent", watchdog_ms: int = 0):
         """Returns (roots_re, roots_im, chain_next, stats, status), or with
         caustics=True (roots_re, roots_im, caus_re, caus_im, chain_next, stats,
         status).  One field: arrays are (m_steps + 1, 2N) float64 device
@@ -240,6 +240,7 @@ class Context:
         p.precision = {"fp64": MLCC_FP64, "mixed": MLCC_MIXED}[precision]
         p.predictor = int(predictor)
         p.schedule = {"rounds": 0, "persistent": 1}[schedule]
+        p.watchdog_ms = int(watchdog_ms)
         n_r = 2 * self.n
         shape = (m_steps + 1, n_r) if self.star_offsets is None else ((m_steps + 1) * n_r,)
         if out is None:

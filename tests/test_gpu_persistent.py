@@ -100,3 +100,24 @@ def test_persistent_cap_reported(ctx, mlcc):
                                                         raise_on_error=False)
         assert code == mlcc.MLCC_ERR_NOT_CONVERGED
         assert st["rows_capped"] >= 1
+
+
+def test_persistent_watchdog_ends_the_launch(ctx, mlcc):
+    """A watchdog of 1 ms on a field whose every pass takes longer: the idle
+    workers see no pass finish within the limit, the launch ends (every
+    worker leaves through the abort flag it polls), the call reports
+    MLCC_ERR_HIP, and the context works normally afterwards."""
+    say("persistent watchdog")
+    f = fields.random_field(12, 40000, kappa_star=0.5, masses="equal")
+    ctx.set_lenses(dev(f.x), dev(f.y), dev(f.m), f.kappa_s, f.gamma)
+    rr, ri, cn, st, code = ctx.find_critical_curves(2, n_subchains=1, schedule="persistent",
+                                                    watchdog_ms=1, raise_on_error=False)
+    torch.cuda.synchronize()
+    assert code == mlcc.MLCC_ERR_HIP
+    assert "no pass finished" in mlcc.library().mlcc_last_error().decode()
+    g = fields.random_field(13, 30)
+    ctx.set_lenses(dev(g.x), dev(g.y), dev(g.m), g.kappa_s, g.gamma)
+    rr, ri, cn, st, code = ctx.find_critical_curves(100, schedule="persistent")
+    assert code == 0
+    with pytest.raises(mlcc.MlccError):
+        ctx.find_critical_curves(100, watchdog_ms=-1)
