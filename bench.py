@@ -530,15 +530,26 @@ def cpu_baseline(f, m_steps, rows):
         z, sw, up, _ = oracle.aberth_row(f, oracle.phase(c + i, m_steps), z0=z)
         ups += up
     dt = time.perf_counter() - t
+    threads = oracle.num_threads()
+    # the same oracle on one thread, one more warm row
+    oracle.set_num_threads(1)
+    t = time.perf_counter()
+    _, _, up1, _ = oracle.aberth_row(f, oracle.phase(c + rows + 1, m_steps), z0=z)
+    dt1 = time.perf_counter() - t
+    oracle.set_num_threads(threads)
+    log(f"cpu baseline: {rows * 2 * f.n / dt:.3e} roots/s on {threads} threads, "
+        f"{2 * f.n / dt1:.3e} on one")
     return {
         "value": rows * 2 * f.n / dt,
         "unit": "roots/s",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "kind": "oracle",
         "sample": (f"{rows} warm rows (phase steps {c + 1}..{c + rows} of {m_steps}, "
                    f"{2 * f.n} roots each, {f.n} stars), each seeded with the previous "
                    f"row, after an untimed cold start at row {c}: {ups} root updates in "
                    f"{dt:.1f} s"),
+        "one_thread": {"value": 2 * f.n / dt1, "unit": "roots/s",
+                       "sample": f"warm row {c + rows + 1}: {up1} root updates in {dt1:.1f} s"},
     }
 
 

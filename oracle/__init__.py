@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
             "orc_edt_brute": [_i64, _i64, _I32, _d, _D, _U8, _I64],
             "orc_edt_twopass": [_i64, _i64, _I32, _d, _D, _U8, _I64],
             "orc_num_threads": [],
+            "orc_set_num_threads": [ctypes.c_int],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -96,6 +97,11 @@ def _star_args(field):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> int:
+    """Threads of the oracle's later parallel loops; returns the count in effect."""
+    return int(lib().orc_set_num_threads(int(n)))
 
 
 def phase(j, m_steps):

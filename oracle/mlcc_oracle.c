@@ -724,3 +724,15 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of later parallel regions (n >= 1); returns the number in effect. */
+int orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
