@@ -1440,13 +1440,17 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
 // gfx950 and picks the cheapest S.
 //
 // Cost of one wave's pass over a field of N stars and n_r = 2N roots, in
-// SIMD cycles (issue costs measured per wave64 instruction: FP64 add/FMA
-// ~4.4-5.4 cycles, v_rcp_f64 ~16, FP32 ~2.3, v_rcp_f32 ~8; the kernels
-// spend ~21 instructions per star term and ~7 per root term in a sweep,
-// ~22 per star term in the polish):
+// SIMD cycles (issue costs measured per wave64 instruction with eight
+// independent chains per lane: FP64 add/mul ~4.8, FMA ~5.3, v_rcp_f64
+// ~16.6; FP32 add/mul ~2.7, FMA ~4.1, v_rcp_f32 ~8.6; the kernels spend ~21
+// instructions per star term and ~7 per root term in a sweep, ~22 per star
+// term in the polish):
 //   FP64 Aberth sweep   114 N + 47 n_r
 //   FP32 Aberth sweep    56 N + 22 n_r
 //   FP64 Newton polish  120 N
+// (Warm FP64 rows take their root terms in FP32, ~40 instead of ~47 cycles
+// per root; the model keeps 47, and S sweeps of measured run times put its
+// choice within 1% of the best S on the workloads tried.)
 // A run does, per field, u (m + S) row passes of every block (u ~ 1.03
 // with the chain predictor, ~2 without; in the mixed form a row without a
 // prediction takes an FP32 sweep and a polish) plus S cold starts of ~27
