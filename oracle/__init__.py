@@ -52,17 +52,21 @@ def lib() -> ctypes.CDLL:
             _build.build()
         L = ctypes.CDLL(_build.LIB)
         sig = {
-            "orc_eval_F": [_i64, _D, _D, _D, _d, _d, _d, _i64, _D, _D, _D, _D, _D, _D],
-            "orc_lens_map": [_i64, _D, _D, _D, _d, _d, _i64, _D, _D, _D, _D],
-            "orc_inv_mu": [_i64, _D, _D, _D, _d, _d, _i64, _D, _D, _D],
-            "orc_seeds": [_i64, _D, _D, _D, _D],
-            "orc_aberth_row": [_i64, _D, _D, _D, _d, _d, _d, _i64, _D, _D, _d, _d, _i64,
+            "orc_eval_F": [_i64, _D, _D, _D, _d, _d, _D, _d, _i64, _D, _D, _D, _D, _D, _D],
+            "orc_lens_map": [_i64, _D, _D, _D, _d, _d, _D, _i64, _D, _D, _D, _D],
+            "orc_inv_mu": [_i64, _D, _D, _D, _d, _d, _D, _i64, _D, _D, _D],
+            "orc_seeds": [_i64, _D, _D, _D, _D, _D],
+            "orc_aberth_row": [_i64, _D, _D, _D, _d, _d, _D, _d, _i64, _D, _D, _d, _d, _i64,
                                ctypes.c_int, _I64, _I64],
-            "orc_subchain": [_i64, _D, _D, _D, _d, _d, _i64, _i64, _i64, _i64, _d, _d, _i64,
+            "orc_subchain": [_i64, _D, _D, _D, _d, _d, _D, _i64, _i64, _i64, _i64, _d, _d, _i64,
                              _i64, ctypes.c_int, _D, _D, _I64],
+            "orc_rect_dalpha": [_D, _i64, _D, _D, _D, _D],
+            "orc_rect_alpha": [_D, ctypes.c_int, _i64, _D, _D, _D, _D],
+            "orc_rect_taylor_degree": [_d, _d, _d, _d, _d],
             "orc_match": [_i64, _D, _D, _D, _D, _I32, _D],
-            "orc_critical_curves": [_i64, _D, _D, _D, _d, _d, _i64, _i64, _d, _d, _i64, _i64,
-                                    ctypes.c_int, _D, _D, _I32, _I64, _D],
+            "orc_critical_curves": [_i64, _D, _D, _D, _d, _d, _D, _i64, _i64, _d, _d, _i64,
+                                    _i64, ctypes.c_int, _D, _D, _I32, _I64, _D],
+            "orc_num_roots": [_i64, _D],
             "orc_ncc_pixels": [_i64, _i64, _D, _D, _I32, _d, _d, _d, _d, _i64, _i64, _I32],
             "orc_ncc_rows": [_i64, _i64, _D, _D, _I32, _d, _d, _d, _d, _i64, _i64, _I32],
             "orc_ncc_at": [_i64, _i64, _D, _D, _I32, _d, _d, _d, _d, _i64, _i64, _i64, _I64,
@@ -76,7 +80,7 @@ def lib() -> ctypes.CDLL:
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
-            f.restype = ctypes.c_int
+            f.restype = ctypes.c_int64 if name == "orc_num_roots" else ctypes.c_int
         _lib = L
     return _lib
 
@@ -89,10 +93,55 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def _sheet(field):
+    """(kappa_star, c1, c2, t) of a rectangular field as a float64 array, or
+    None for a circular one."""
+    sh = getattr(field, "sheet", None)
+    return None if sh is None else np.ascontiguousarray(np.asarray(sh, dtype=np.float64))
+
+
 def _star_args(field):
     x, y, m = _f64(field.x), _f64(field.y), _f64(field.m)
-    return (x, y, m), (x.shape[0], _p(x, _D), _p(y, _D), _p(m, _D),
-                       float(field.kappa_s), float(field.gamma))
+    sh = _sheet(field)
+    return (x, y, m, sh), (x.shape[0], _p(x, _D), _p(y, _D), _p(m, _D),
+                           float(field.kappa_s), float(field.gamma), _p(sh, _D))
+
+
+def num_roots(field) -> int:
+    """Roots per phase: 2N, plus t - 1 for a rectangular field (App. B)."""
+    keep, sa = _star_args(field)
+    return int(lib().orc_num_roots(sa[0], sa[6]))
+
+
+def rect_taylor_degree(kappa_star, c1, c2, s, eps) -> int:
+    """App. B truncation degree for accuracy eps where |z| s < |c|."""
+    t = int(lib().orc_rect_taylor_degree(float(kappa_star), float(c1), float(c2), float(s),
+                                         float(eps)))
+    if t < 0:
+        raise OracleError(t, "rect_taylor_degree")
+    return t
+
+
+def rect_dalpha_dzbar(sheet, z):
+    """d alpha_s / d zbar of the rectangular sheet (App. B closed form)."""
+    sh = np.ascontiguousarray(np.asarray(sheet, dtype=np.float64))
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128).ravel())
+    zr, zi = _f64(z.real), _f64(z.imag)
+    dr, di = np.empty(z.shape[0]), np.empty(z.shape[0])
+    lib().orc_rect_dalpha(_p(sh, _D), z.shape[0], _p(zr, _D), _p(zi, _D), _p(dr, _D), _p(di, _D))
+    return dr + 1j * di
+
+
+def rect_alpha(sheet, z, exact=False):
+    """alpha_s of the rectangular sheet: App. B series truncated at t, or its
+    closed form (exact=True)."""
+    sh = np.ascontiguousarray(np.asarray(sheet, dtype=np.float64))
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128).ravel())
+    zr, zi = _f64(z.real), _f64(z.imag)
+    ar, ai = np.empty(z.shape[0]), np.empty(z.shape[0])
+    lib().orc_rect_alpha(_p(sh, _D), int(bool(exact)), z.shape[0], _p(zr, _D), _p(zi, _D),
+                         _p(ar, _D), _p(ai, _D))
+    return ar + 1j * ai
 
 
 def num_threads() -> int:
@@ -144,8 +193,9 @@ def inv_mu(field, z):
 def seeds(field):
     keep, sa = _star_args(field)
     n = sa[0]
-    zr, zi = np.empty(2 * n), np.empty(2 * n)
-    lib().orc_seeds(n, sa[1], sa[2], _p(zr, _D), _p(zi, _D))
+    n_r = num_roots(field)
+    zr, zi = np.empty(n_r), np.empty(n_r)
+    lib().orc_seeds(n, sa[1], sa[2], sa[6], _p(zr, _D), _p(zi, _D))
     return zr + 1j * zi
 
 
@@ -172,7 +222,7 @@ def subchain(field, m_steps, lo, center, hi, tol_step=TOL_STEP, tol_mu=TOL_INV_M
     """Rows lo..hi of the chain matrix grown from a cold start at `center`
     (Sec. 4.3).  Returns (roots (hi-lo+1, 2N) complex, stats dict)."""
     keep, sa = _star_args(field)
-    n_r = 2 * sa[0]
+    n_r = num_roots(field)
     rows = hi - lo + 1
     rr, ri = np.empty(rows * n_r), np.empty(rows * n_r)
     st = np.zeros(5, dtype=np.int64)
@@ -194,7 +244,7 @@ def critical_curves(field, m_steps, n_sub=1, tol_step=TOL_STEP, tol_mu=TOL_INV_M
     """The (m_steps+1, 2N) chain matrix of Sec. 4.3 and chain_next.
     Returns (roots complex, chain_next int32, stats dict)."""
     keep, sa = _star_args(field)
-    n_r = 2 * sa[0]
+    n_r = num_roots(field)
     rows = m_steps + 1
     rr, ri = np.empty(rows * n_r), np.empty(rows * n_r)
     cn = np.empty(n_r, dtype=np.int32)

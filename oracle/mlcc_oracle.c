@@ -67,7 +67,100 @@ typedef struct {
     int64_t n;
     const double *x, *y, *m;
     double kappa_s, gamma;
+    /* NULL: the circular field with its sheet extended to infinity (App. A),
+     * alpha_s = -kappa_star z.  Else a rectangular field (Sec. 4.2, App. B):
+     * sheet = {kappa_star, c1, c2, t}, corner c = c1 + i c2, Taylor degree t
+     * (odd), the sheet again extended to infinity (d alpha_s / dz =
+     * -kappa_star) and the logarithms truncated at power t. */
+    const double *sheet;
 } Lens;
+
+/* ---------------------------------------------------------------------- */
+/* Rectangular field (Sec. 4.2, App. A, App. B)                             */
+/* ---------------------------------------------------------------------- */
+
+static int sheet_t(const double *sh) { return (int)sh[3]; }
+
+/* Roots added by the sheet polynomial: t - 1 for odd t >= 3 (App. B: the
+ * power-t term vanishes for odd t), none for t = 1. */
+static int64_t sheet_extra_roots(const double *sh)
+{
+    if (!sh) return 0;
+    int t = sheet_t(sh);
+    return t >= 3 ? (int64_t)(t - 1) : 0;
+}
+
+/* d alpha_s / d zbar of App. B in its first closed form (with arctan):
+ *   -kappa_star i / pi [ zbar^t (1 + (-1)^t) (c^-t - cbar^-t)
+ *                        + sum_{j=1..t} zbar^j / j (1 + (-1)^j) (c^-j - cbar^-j) ]
+ *   + kappa_star - 4 kappa_star arctan(c2 / c1) / pi,
+ * and its derivative in zbar. */
+static void sheet_dalpha_dzbar(const double *sh, cplx zb, cplx *d1, cplx *d2)
+{
+    double ks = sh[0];
+    cplx c = sh[1] + I * sh[2], cb = conj(c);
+    int t = sheet_t(sh);
+    cplx acc = 0, accd = 0, zp = 1, zt1 = 1;   /* zp = zbar^(j-1) in the loop */
+    for (int j = 1; j <= t; ++j) {
+        double sgn = (j & 1) ? -1.0 : 1.0;
+        cplx k = (1.0 + sgn) * (1.0 / cpow(c, j) - 1.0 / cpow(cb, j));
+        acc += zp * zb / j * k;
+        accd += zp * k;
+        if (j == t) zt1 = zp;
+        zp *= zb;
+    }
+    /* the separate power-t term; zp = zbar^t, zt1 = zbar^(t-1) */
+    {
+        double sgn = (t & 1) ? -1.0 : 1.0;
+        cplx k = (1.0 + sgn) * (1.0 / cpow(c, t) - 1.0 / cpow(cb, t));
+        acc += zp * k;
+        accd += (double)t * zt1 * k;
+    }
+    *d1 = (-ks * I / M_PI) * acc + ks - 4.0 * ks * atan(sh[2] / sh[1]) / M_PI;
+    if (d2) *d2 = (-ks * I / M_PI) * accd;
+}
+
+/* alpha_s of App. B: the four logarithms Taylor-expanded about the origin
+ * and truncated at power t (exact = 0), or (exact = 1) summed in closed
+ * form as log(a) + log(1 - zbar/a), the continuation of the series from the
+ * origin, valid for |z| < |c|; plus -kappa_star (c + cbar + zbar + z). */
+static cplx sheet_alpha(const double *sh, cplx z, int exact)
+{
+    double ks = sh[0];
+    cplx c = sh[1] + I * sh[2];
+    cplx zb = conj(z);
+    int t = sheet_t(sh);
+    cplx a[4] = {c, conj(c), -c, -conj(c)};
+    double sgn[4] = {1.0, -1.0, 1.0, -1.0};
+    cplx acc = 0;
+    for (int q = 0; q < 4; ++q) {
+        cplx lg;
+        if (exact) {
+            lg = clog(a[q]) + clog(1.0 - zb / a[q]);
+        } else {
+            cplx s = 0, p = 1;
+            for (int j = 1; j <= t; ++j) {
+                p *= zb / a[q];
+                s += p / j;
+            }
+            lg = clog(a[q]) - s;
+        }
+        acc += sgn[q] * (a[q] - zb) * lg;
+    }
+    return (-ks * I / M_PI) * acc - ks * (c + conj(c) + zb + z);
+}
+
+/* Start values of the t - 1 extra roots: evenly spread on the circle through
+ * the field's corners, |z| = |c|, at angles 2 pi (k + 1/2) / (t - 1). */
+static void sheet_seeds(const double *sh, cplx *out)
+{
+    int64_t e = sheet_extra_roots(sh);
+    double r = cabs(sh[1] + I * sh[2]);
+    for (int64_t k = 0; k < e; ++k) {
+        double a = 2.0 * M_PI * ((double)k + 0.5) / (double)e;
+        out[k] = r * (cos(a) + I * sin(a));
+    }
+}
 
 /* F, F' and S1 = sum 1/(z - z_i) at one point (Sec. 3.1 and Sec. 3.2). */
 static void eval_F(const Lens *L, cplx e, cplx z, cplx *F, cplx *Fp, cplx *S1)
@@ -83,6 +176,17 @@ static void eval_F(const Lens *L, cplx e, cplx z, cplx *F, cplx *Fp, cplx *S1)
     *F = L->gamma + s2 - e;
     *Fp = -2.0 * s3;
     *S1 = s1;
+    if (L->sheet) {
+        /* F = gamma + sum m/(z - z_i)^2 - conj(d alpha_s/d zbar)
+         *     - (1 - kappa - d alpha_s/dz) e^{-i phi}, with d alpha_s/dz =
+         * -kappa_star, so the last factor is 1 - kappa_s as for the circle
+         * (Sec. 3.1); conj(d alpha_s/d zbar) is a polynomial in z whose
+         * z-derivative is conj of the zbar-derivative. */
+        cplx d1, d2;
+        sheet_dalpha_dzbar(L->sheet, conj(z), &d1, &d2);
+        *F -= conj(d1);
+        *Fp -= conj(d2);
+    }
 }
 
 /* Neumaier-compensated complex accumulator, used where a sum of many terms
@@ -108,6 +212,12 @@ static cplx lens_map(const Lens *L, cplx z)
         neu_add(&si, cimag(t));
     }
     cplx s = (sr.s + sr.c) + I * (si.s + si.c);
+    if (L->sheet) {
+        /* w = (1 - kappa) z + gamma conj(z) - sum - alpha_s(z), kappa =
+         * kappa_s + kappa_star (Sec. 3.1), alpha_s the truncated App. B form */
+        double kappa = L->kappa_s + L->sheet[0];
+        return (1.0 - kappa) * z + L->gamma * conj(z) - s - sheet_alpha(L->sheet, z, 0);
+    }
     return (1.0 - L->kappa_s) * z + L->gamma * conj(z) - s;
 }
 
@@ -121,6 +231,11 @@ static double inv_mu(const Lens *L, cplx z)
         s += L->m[i] / (dbar * dbar);
     }
     cplx g = L->gamma + s;
+    if (L->sheet) {
+        cplx d1;
+        sheet_dalpha_dzbar(L->sheet, conj(z), &d1, NULL);
+        g -= d1;   /* dw/dzbar = gamma + sum m/conj(z - z_i)^2 - d alpha_s/d zbar */
+    }
     double a = 1.0 - L->kappa_s;
     return a * a - creal(g * conj(g));
 }
@@ -132,6 +247,14 @@ static int lens_ok(const Lens *L)
         if (!isfinite(L->x[i]) || !isfinite(L->y[i]) || !isfinite(L->m[i]) || !(L->m[i] > 0))
             return 0;
     if (!isfinite(L->kappa_s) || !isfinite(L->gamma)) return 0;
+    if (L->sheet) {
+        const double *sh = L->sheet;
+        int t = sheet_t(sh);
+        if (!(sh[0] > 0) || !(sh[1] > 0) || !(sh[2] > 0) || t < 1 || !(t & 1) ||
+            (double)t != sh[3])
+            return 0;
+        return 1;
+    }
     /* c(phi) = gamma - (1 - kappa_s) e^{-i phi} vanishes on the grid when
      * |gamma| = |1 - kappa_s| (App. A footnote); reject that case. */
     if (fabs(fabs(L->gamma) - fabs(1.0 - L->kappa_s)) == 0.0) return 0;
@@ -139,11 +262,12 @@ static int lens_ok(const Lens *L)
 }
 
 int orc_eval_F(int64_t n, const double *x, const double *y, const double *m,
-               double kappa_s, double gamma, double phi, int64_t count,
+               double kappa_s, double gamma, const double *sheet, double phi,
+               int64_t count,
                const double *zr, const double *zi,
                double *Fr, double *Fi, double *Fpr, double *Fpi)
 {
-    Lens L = {n, x, y, m, kappa_s, gamma};
+    Lens L = {n, x, y, m, kappa_s, gamma, sheet};
     cplx e = phase_term(kappa_s, phi);
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < count; ++k) {
@@ -156,10 +280,10 @@ int orc_eval_F(int64_t n, const double *x, const double *y, const double *m,
 }
 
 int orc_lens_map(int64_t n, const double *x, const double *y, const double *m,
-                 double kappa_s, double gamma, int64_t count,
+                 double kappa_s, double gamma, const double *sheet, int64_t count,
                  const double *zr, const double *zi, double *wr, double *wi)
 {
-    Lens L = {n, x, y, m, kappa_s, gamma};
+    Lens L = {n, x, y, m, kappa_s, gamma, sheet};
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < count; ++k) {
         cplx w = lens_map(&L, zr[k] + I * zi[k]);
@@ -169,10 +293,10 @@ int orc_lens_map(int64_t n, const double *x, const double *y, const double *m,
 }
 
 int orc_inv_mu(int64_t n, const double *x, const double *y, const double *m,
-               double kappa_s, double gamma, int64_t count,
+               double kappa_s, double gamma, const double *sheet, int64_t count,
                const double *zr, const double *zi, double *out)
 {
-    Lens L = {n, x, y, m, kappa_s, gamma};
+    Lens L = {n, x, y, m, kappa_s, gamma, sheet};
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < count; ++k) out[k] = inv_mu(&L, zr[k] + I * zi[k]);
     return ORC_OK;
@@ -184,14 +308,74 @@ int orc_inv_mu(int64_t n, const double *x, const double *y, const double *m,
 
 /* Cold-start seeds (Sec. 3.2): the star positions shifted by +1 and -1
  * (theta_star = 1) along the real axis; root 2i <- z_i + 1, 2i+1 <- z_i - 1.
- * With the infinite sheet there are exactly n_r = 2N roots. */
-int orc_seeds(int64_t n, const double *x, const double *y, double *zr, double *zi)
+ * With the infinite sheet there are exactly n_r = 2N roots.  A rectangular
+ * field adds t - 1 roots (App. B), seeded on a circle around the stars
+ * (Sec. 3.2), roots 2N .. 2N + t - 2. */
+int orc_seeds(int64_t n, const double *x, const double *y, const double *sheet, double *zr,
+              double *zi)
 {
     for (int64_t i = 0; i < n; ++i) {
         zr[2 * i] = x[i] + 1.0; zi[2 * i] = y[i];
         zr[2 * i + 1] = x[i] - 1.0; zi[2 * i + 1] = y[i];
     }
+    int64_t e = sheet_extra_roots(sheet);
+    if (e) {
+        cplx *ex = malloc(sizeof(cplx) * e);
+        sheet_seeds(sheet, ex);
+        for (int64_t k = 0; k < e; ++k) { zr[2 * n + k] = creal(ex[k]); zi[2 * n + k] = cimag(ex[k]); }
+        free(ex);
+    }
     return ORC_OK;
+}
+
+/* App. B for callers: d alpha_s / d zbar, and alpha_s truncated (exact = 0)
+ * or summed in closed form (exact = 1), at `count` points. */
+int orc_rect_dalpha(const double *sheet, int64_t count, const double *zr, const double *zi,
+                    double *dr, double *di)
+{
+    for (int64_t k = 0; k < count; ++k) {
+        cplx d1;
+        sheet_dalpha_dzbar(sheet, zr[k] - I * zi[k], &d1, NULL);
+        dr[k] = creal(d1); di[k] = cimag(d1);
+    }
+    return ORC_OK;
+}
+
+int orc_rect_alpha(const double *sheet, int exact, int64_t count, const double *zr,
+                   const double *zi, double *ar, double *ai)
+{
+    for (int64_t k = 0; k < count; ++k) {
+        cplx a = sheet_alpha(sheet, zr[k] + I * zi[k], exact);
+        ar[k] = creal(a); ai[k] = cimag(a);
+    }
+    return ORC_OK;
+}
+
+/* Taylor degree for a rectangular field (App. B): the smallest t whose
+ * truncation bound (kappa_star / pi) (4 / (t + 1)) s^-(t+1) |c| (s + 1)/(s - 1)
+ * is at most eps (for |z| s < |c|), made odd, then raised by 2 until
+ * (t - 1) Arg(c) mod pi lies at least 10% of pi away from 0 and from pi.
+ * Returns -1 for invalid arguments. */
+int orc_rect_taylor_degree(double kappa_star, double c1, double c2, double s, double eps)
+{
+    if (!(kappa_star > 0) || !(c1 > 0) || !(c2 > 0) || !(s > 1) || !(eps > 0)) return -1;
+    double ac = hypot(c1, c2), th = atan2(c2, c1);
+    int t = 1;
+    while (kappa_star / M_PI * 4.0 / (t + 1) * pow(s, -(t + 1)) * ac * (s + 1) / (s - 1) > eps) {
+        if (++t > 100000) return -1;
+    }
+    if (!(t & 1)) ++t;
+    for (int guard = 0; guard < 100000; ++guard, t += 2) {
+        double r = fmod((t - 1) * th, M_PI);
+        if (r >= 0.1 * M_PI && r <= 0.9 * M_PI) return t;
+    }
+    return -1;
+}
+
+/* Number of roots per phase: 2N, plus t - 1 for a rectangular field. */
+int64_t orc_num_roots(int64_t n, const double *sheet)
+{
+    return 2 * n + sheet_extra_roots(sheet);
 }
 
 /* One Aberth-Ehrlich solve for one phase (Sec. 3.2).
@@ -211,12 +395,12 @@ int orc_seeds(int64_t n, const double *x, const double *y, double *zr, double *z
  * tolerance the GPU path is held to.
  */
 int orc_aberth_row(int64_t n, const double *x, const double *y, const double *m,
-                   double kappa_s, double gamma, double phi, int64_t n_r,
+                   double kappa_s, double gamma, const double *sheet, double phi, int64_t n_r,
                    double *zr, double *zi, double tol_step, double tol_mu,
                    int64_t max_iter, int polish, int64_t *sweeps_out,
                    int64_t *updates_out)
 {
-    Lens L = {n, x, y, m, kappa_s, gamma};
+    Lens L = {n, x, y, m, kappa_s, gamma, sheet};
     if (!lens_ok(&L) || n_r < 1) return ORC_ERR_INVALID;
     cplx e = phase_term(kappa_s, phi);
     double a1 = fabs(1.0 - kappa_s);
@@ -290,18 +474,18 @@ int orc_aberth_row(int64_t n, const double *x, const double *y, const double *m,
  * [1] root updates, [2] rows that hit the iteration cap, [3] max sweeps in a
  * warm row, [4] sweeps of the cold start. */
 int orc_subchain(int64_t n, const double *x, const double *y, const double *m,
-                 double kappa_s, double gamma, int64_t m_steps, int64_t lo,
+                 double kappa_s, double gamma, const double *sheet, int64_t m_steps, int64_t lo,
                  int64_t center, int64_t hi, double tol_step, double tol_mu,
                  int64_t max_iter_cold, int64_t max_iter_warm, int polish,
                  double *out_re, double *out_im, int64_t *stats)
 {
-    int64_t n_r = 2 * n;
+    int64_t n_r = orc_num_roots(n, sheet);
     if (lo > center || center > hi || lo < 0 || hi > m_steps) return ORC_ERR_INVALID;
     int64_t st[5] = {0, 0, 0, 0, 0};
     double *cr = out_re + (center - lo) * n_r, *ci = out_im + (center - lo) * n_r;
-    orc_seeds(n, x, y, cr, ci);
+    orc_seeds(n, x, y, sheet, cr, ci);
     int64_t sw, up;
-    int rc = orc_aberth_row(n, x, y, m, kappa_s, gamma, phase_of_row(center, m_steps), n_r,
+    int rc = orc_aberth_row(n, x, y, m, kappa_s, gamma, sheet, phase_of_row(center, m_steps), n_r,
                             cr, ci, tol_step, tol_mu, max_iter_cold, polish, &sw, &up);
     st[0] += sw; st[1] += up; st[4] = sw;
     if (rc == ORC_ERR_NOT_CONVERGED) st[2]++;
@@ -313,7 +497,7 @@ int orc_subchain(int64_t n, const double *x, const double *y, const double *m,
             double *rr = out_re + (j - lo) * n_r, *ri = out_im + (j - lo) * n_r;
             memcpy(rr, pr, sizeof(double) * n_r);
             memcpy(ri, pi, sizeof(double) * n_r);
-            rc = orc_aberth_row(n, x, y, m, kappa_s, gamma, phase_of_row(j, m_steps), n_r,
+            rc = orc_aberth_row(n, x, y, m, kappa_s, gamma, sheet, phase_of_row(j, m_steps), n_r,
                                 rr, ri, tol_step, tol_mu, max_iter_warm, polish, &sw, &up);
             st[0] += sw; st[1] += up;
             if (sw > st[3]) st[3] = sw;
@@ -366,14 +550,15 @@ int orc_match(int64_t n, const double *ar, const double *ai, const double *br,
  * equals phase 0, so the two rows hold the same roots): the start of one
  * chain is the end of another.  stats: as orc_subchain, summed. */
 int orc_critical_curves(int64_t n, const double *x, const double *y, const double *m,
-                        double kappa_s, double gamma, int64_t m_steps, int64_t n_sub,
+                        double kappa_s, double gamma, const double *sheet, int64_t m_steps,
+                        int64_t n_sub,
                         double tol_step, double tol_mu, int64_t max_iter_cold,
                         int64_t max_iter_warm, int polish, double *roots_re,
                         double *roots_im, int32_t *chain_next, int64_t *stats,
                         double *match_maxdist)
 {
     if (m_steps < 2 || (m_steps & 1) || n_sub < 1 || (m_steps / 2) % n_sub) return ORC_ERR_INVALID;
-    int64_t n_r = 2 * n, L = m_steps / n_sub;
+    int64_t n_r = orc_num_roots(n, sheet), L = m_steps / n_sub;
     int64_t tot[5] = {0, 0, 0, 0, 0};
     double md = 0.0;
     double *br = malloc(sizeof(double) * (L + 1) * n_r), *bi = malloc(sizeof(double) * (L + 1) * n_r);
@@ -382,7 +567,8 @@ int orc_critical_curves(int64_t n, const double *x, const double *y, const doubl
     for (int64_t s = 0; s < n_sub; ++s) {
         int64_t lo = s * L, hi = lo + L, c = lo + L / 2;
         int64_t st[5];
-        int rc = orc_subchain(n, x, y, m, kappa_s, gamma, m_steps, lo, c, hi, tol_step, tol_mu,
+        int rc = orc_subchain(n, x, y, m, kappa_s, gamma, sheet, m_steps, lo, c, hi, tol_step,
+                              tol_mu,
                               max_iter_cold, max_iter_warm, polish, br, bi, st);
         for (int q = 0; q < 3; ++q) tot[q] += st[q];
         if (st[3] > tot[3]) tot[3] = st[3];

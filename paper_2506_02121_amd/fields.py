@@ -37,6 +37,9 @@ class StarField:
     gamma: float
     kappa_star: float
     radius: float
+    # rectangular field: (kappa_star, c1, c2, t), corner c1 + i c2 and the
+    # Taylor degree t of the sheet; None for a circular field
+    sheet: Optional[tuple] = None
 
     @property
     def n(self) -> int:
@@ -99,6 +102,36 @@ def make_field(rng: np.random.Generator, n: int, kappa_star: float, kappa_s: flo
     return StarField(x=np.ascontiguousarray(x), y=np.ascontiguousarray(y),
                      m=np.ascontiguousarray(m), kappa_s=float(kappa_s),
                      gamma=float(gamma), kappa_star=float(kappa_star), radius=radius)
+
+
+def make_rect_field(rng: np.random.Generator, n: int, kappa_star: float, kappa_s: float,
+                    gamma: float, aspect: float, t: int, masses: str = "equal") -> StarField:
+    """A rectangular field (Sec. 4.2): positions uniform in [-c1, c1] x
+    [-c2, c2] with c2 = aspect * c1 and area 4 c1 c2 = pi sum(m_i) / kappa_star
+    (the same definition of kappa_star as for the disk)."""
+    if masses == "equal":
+        m = np.ones(n)
+    elif masses == "salpeter":
+        m = salpeter_masses(rng, n)
+    else:
+        raise ValueError(f"unknown mass function {masses!r}")
+    area = np.pi * m.sum() / kappa_star
+    c1 = float(np.sqrt(area / (4.0 * aspect)))
+    c2 = float(aspect * c1)
+    x = (2.0 * rng.random(n) - 1.0) * c1
+    y = (2.0 * rng.random(n) - 1.0) * c2
+    return StarField(x=np.ascontiguousarray(x), y=np.ascontiguousarray(y),
+                     m=np.ascontiguousarray(m), kappa_s=float(kappa_s), gamma=float(gamma),
+                     kappa_star=float(kappa_star), radius=float(np.hypot(c1, c2)),
+                     sheet=(float(kappa_star), c1, c2, int(t)))
+
+
+def rect_field(seed: int, n: int, kappa_star: float = 0.4, kappa_s: float = 0.0,
+               gamma: float = 0.3, aspect: float = 1.5, t: int = 9, masses: str = "equal",
+               tag: int = 98) -> StarField:
+    """A free-form seeded rectangular field for tests (config id `tag`)."""
+    return make_rect_field(rng_for(seed, tag, n), n, kappa_star, kappa_s, gamma, aspect, t,
+                           masses)
 
 
 def random_field(seed: int, n: int, kappa_star: float = 0.4, kappa_s: float = 0.0,
