@@ -103,6 +103,53 @@ mlcc_status mlcc_set_lenses(mlcc_ctx *ctx, int64_t n, const double *x, const dou
                             const double *m, double kappa_s, double gamma);
 
 /*
+ * set_lenses_rect -- one rectangular microlens field (Sec. 4.2): stars in
+ * [-c1, c1] x [-c2, c2] (not checked), corner c = c1 + i c2, and a smooth
+ * sheet of convergence -kappa_star over the rectangle whose deflection has
+ * its logarithms Taylor-expanded about the origin to odd degree t and is
+ * extended to an infinite sheet for d alpha_s / dz (App. A, App. B).  Then
+ *   d alpha_s / dz = -kappa_star,  conj(d alpha_s / d zbar) = d0 + sum_{j=2,4,..,t-1} d_j z^j,
+ *   d0  = kappa_star (1 - 4 Arg(c) / pi),
+ *   d_j = -(4 kappa_star / pi) sin(j Arg(c)) / (j |c|^j)   (App. B, last form),
+ *   F(z,p) = gamma - d0 + sum_i m_i / (z - z_i)^2 - sum_j d_j z^j - (1 - kappa_s) e^{-i p},
+ *   w(z)   = (1 - kappa_s) z + (gamma - d0) conj(z) - sum_j d_j conj(z)^(j+1) / (j+1)
+ *            - sum_i m_i / conj(z - z_i),
+ * and each phase has n_r = 2N + t - 1 roots (mlcc_num_roots): the t - 1
+ * extra ones start evenly spread on the circle |z| = |c| (Sec. 3.2), at
+ * angles 2 pi (k + 1/2) / (t - 1), k = 0 .. t - 2, after the 2N star seeds.
+ * Outside the rectangle the expansion, and the curves found there, are not
+ * the field's (App. A).
+ *   n, x, y, m       as mlcc_set_lenses
+ *   kappa_star       > 0, the sheet's convergence (the stars' mean
+ *                    convergence pi sum m_i / (4 c1 c2) for a matched sheet)
+ *   c1, c2           > 0
+ *   t                odd, 1 .. 129 (mlcc_rect_taylor_degree picks one)
+ * Rejected (MLCC_ERR_INVALID): the mlcc_set_lenses conditions (except the
+ * |gamma| rule, which applies to gamma - d0 and only for t = 1), even or
+ * out-of-range t, and (t - 1) Arg(c) within 10% of pi of a multiple of pi
+ * (the leading coefficient nearly vanishes; App. B).  Only MLCC_FP64 solves
+ * it.  Copies the inputs; synchronous.
+ */
+mlcc_status mlcc_set_lenses_rect(mlcc_ctx *ctx, int64_t n, const double *x, const double *y,
+                                 const double *m, double kappa_s, double gamma, double kappa_star,
+                                 double c1, double c2, int32_t t);
+
+/*
+ * rect_taylor_degree -- App. B's choice of t: the smallest t with
+ *   (kappa_star / pi) (4 / (t + 1)) s^-(t+1) |c| (s + 1) / (s - 1) <= eps
+ * (the bound on the truncation error of alpha_s where |z| s < |c|), made
+ * odd, then raised by 2 until (t - 1) Arg(c) mod pi lies in [0.1 pi, 0.9 pi].
+ *   s > 1, eps > 0; *t receives the degree.  MLCC_ERR_INVALID if no t up to
+ *   129 qualifies.  Host only.
+ */
+mlcc_status mlcc_rect_taylor_degree(double kappa_star, double c1, double c2, double s,
+                                    double eps, int32_t *t);
+
+/* Roots per phase of the current lenses: sum over fields of 2N (+ t - 1 for
+ * a rectangular field); the row length of mlcc_find_critical_curves. */
+mlcc_status mlcc_num_roots(mlcc_ctx *ctx, int64_t *n_r);
+
+/*
  * set_lenses_batched -- several independent star fields, each with its own
  * stars, kappa_s and gamma (the model of mlcc_set_lenses per field), solved
  * together by one mlcc_find_critical_curves call.  Field r holds stars

@@ -228,10 +228,52 @@ __device__ __forceinline__ void nudge(Update &u, double zr, double zi, int k)
 // lens map at the new iterate.  The map reuses the sums: with
 // z' = z - D, sum m_i/(z' - z_i) = s0 + D s2 + D^2 s3 + O(D^3 sum m_i u_i^4),
 // and D is below the convergence cutoffs once a root is flagged.
+// Rectangular field (Sec. 4.2, App. B): the sheet adds -P(z) to F and
+// -P'(z) to F', with P(z) = sum_{k=1..n} d_2k z^2k (real d_2k, see
+// sheet_poly): P = w h(w), P' = 2 z g(w), w = z^2, h = sum d_2k w^(k-1),
+// g = sum k d_2k w^(k-1), both by Horner's rule.
+__device__ __forceinline__ void sheet_terms(const double *__restrict__ d, int n, double zr,
+                                            double zi, double &Pr, double &Pi, double &Qr,
+                                            double &Qi)
+{
+    const double wr = zr * zr - zi * zi, wi = 2.0 * zr * zi;
+    double hr = d[n - 1], hi = 0.0, gr = n * d[n - 1], gi = 0.0;
+    for (int k = n - 2; k >= 0; --k) {
+        const double th = hr * wr - hi * wi + d[k];
+        hi = hr * wi + hi * wr;
+        hr = th;
+        const double tg = gr * wr - gi * wi + (k + 1) * d[k];
+        gi = gr * wi + gi * wr;
+        gr = tg;
+    }
+    Pr = hr * wr - hi * wi;
+    Pi = hr * wi + hi * wr;
+    Qr = 2.0 * (gr * zr - gi * zi);
+    Qi = 2.0 * (gr * zi + gi * zr);
+}
+
+// Its term of the lens map: sum_k d_2k / (2k + 1) z^(2k+1) = z^3 H(z^2) with
+// H = sum (d_2k / (2k + 1)) w^(k-1); the map subtracts its conjugate.
+__device__ __forceinline__ void sheet_map_term(const double *__restrict__ dm, int n, double zr,
+                                               double zi, double &Qr, double &Qi)
+{
+    const double wr = zr * zr - zi * zi, wi = 2.0 * zr * zi;
+    double hr = dm[n - 1], hi = 0.0;
+    for (int k = n - 2; k >= 0; --k) {
+        const double th = hr * wr - hi * wi + dm[k];
+        hi = hr * wi + hi * wr;
+        hr = th;
+    }
+    const double qr = hr * wr - hi * wi, qi = hr * wi + hi * wr;   // z^2 H
+    Qr = qr * zr - qi * zi;
+    Qi = qr * zi + qi * zr;
+}
+
 template <bool EQUAL>
 __device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0, double2 e,
                                          double gamma, double a, double a1, double tol_step2,
-                                         double tol_mu, int k)
+                                         double tol_mu, int k, const double *sheet = nullptr,
+                                         int n_poly = 0)
 {
     S.s2i *= -2.0;
     if (EQUAL) {   // every mass equals m0: the sums above left it out
@@ -243,8 +285,16 @@ __device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0
         S.s3i *= m0;
     }
     // F = gamma + S2 - (1 - kappa_s) e^{-i phi}, F' = -2 S3
-    const double Fr = gamma + S.s2r - e.x, Fi = S.s2i - e.y;
-    const double Fpr = -2.0 * S.s3r, Fpi = -2.0 * S.s3i;
+    double Fr = gamma + S.s2r - e.x, Fi = S.s2i - e.y;
+    double Fpr = -2.0 * S.s3r, Fpi = -2.0 * S.s3i;
+    if (n_poly > 0) {   // rectangular field: F -= P(z), F' -= P'(z)
+        double Pr, Pi, Qr, Qi;
+        sheet_terms(sheet, n_poly, zr, zi, Pr, Pi, Qr, Qi);
+        Fr -= Pr;
+        Fi -= Pi;
+        Fpr -= Qr;
+        Fpi -= Qi;
+    }
     // Aberth step: 1 / (F'/F + 2 S1 - R) = F / (F' + F (2 S1 - R))
     const double Gr = 2.0 * S.s1r - S.Rr, Gi = 2.0 * S.s1i - S.Ri;
     const double Dr = Fpr + (Fr * Gr - Fi * Gi);
@@ -265,6 +315,12 @@ __device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0
     // w = (1 - kappa_s) z' + gamma conj(z') - conj(T)
     u.wr = fma(a, u.zr, gamma * u.zr) - Tr;
     u.wi = fma(a, u.zi, -gamma * u.zi) + Ti;
+    if (n_poly > 0) {   // rectangular field: - conj(sum_k d_2k / (2k + 1) z'^(2k+1))
+        double Qr, Qi;
+        sheet_map_term(sheet + n_poly, n_poly, u.zr, u.zi, Qr, Qi);
+        u.wr -= Qr;
+        u.wi += Qi;
+    }
     return u;
 }
 
@@ -310,11 +366,14 @@ template <class T> struct RoundArgs {
     int32_t predictor;
     int32_t persistent; // the persistent scheduler: iterates by per-front parity
     double2 *iter0, *iter1;
+    const double *sheet; // rectangular fields' sheet records (Real::sheet_off)
 };
 
 // What one block knows about its front and star field.
 template <class T> struct BlockCtx {
     int f, q, k0, k, lane, n_r, n_stars, row, stamp, dir, pred;
+    int n_poly, n_extra;   // rectangular field: sheet terms and extra roots (else 0)
+    const double *sheet;   // its record: d_2k, then d_2k / (2k + 1), then extra seeds
     int vslot;   // this block's slot in the per-block row sums (front order)
     bool valid, boundary;
     int64_t base_f, out_off, bnd_row_off;
@@ -341,6 +400,9 @@ __device__ __forceinline__ bool enter_fq(const RoundArgs<T> &A, int phase, int f
     B.pred = (F->fresh && F->dir != 0 && F->hist >= 2) ? min(A.predictor, F->hist - 1) : 0;
     B.n_r = R->n_r;
     B.n_stars = R->n_stars;
+    B.n_poly = R->n_poly;
+    B.n_extra = R->n_extra;
+    B.sheet = R->n_poly > 0 ? A.sheet + R->sheet_off : nullptr;
     B.stars = A.stars + R->star_off;
     B.m0 = R->m0;
     B.gamma = R->gamma;
@@ -435,7 +497,10 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
         // cold start, the previous row of the subchain otherwise
         if (B.valid) {
             double2 z;
-            if (B.dir == 0) {
+            if (B.dir == 0 && B.k >= 2 * B.n_stars) {   // a rectangular sheet's extra root
+                const int x = B.k - 2 * B.n_stars;
+                z = make_double2(B.sheet[2 * B.n_poly + 2 * x], B.sheet[2 * B.n_poly + 2 * x + 1]);
+            } else if (B.dir == 0) {
                 const T st = B.stars[B.k >> 1];
                 z = make_double2(st.x + ((B.k & 1) ? -1.0 : 1.0), st.y);
             } else {
@@ -502,7 +567,8 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
             wave_sum(S.s2r); wave_sum(S.s2i);
             wave_sum(S.s3r); wave_sum(S.s3i);
             wave_sum(S.Rr); wave_sum(S.Ri);
-            const Update u = finish<EQUAL>(S, xk, yk, m0, e, gamma, a, a1, tol_step2, tol_mu, kk);
+            const Update u = finish<EQUAL>(S, xk, yk, m0, e, gamma, a, a1, tol_step2, tol_mu, kk,
+                                           B.sheet, B.n_poly);
             if (lane == l) store(kk, u);
             n_after += u.flag ? 0 : 1;
         }
@@ -524,7 +590,8 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
                 S.Ri = self ? S.Ri : T2.Ri;
             });
             stream_tiles(zsrc + own_hi, n_r - own_hi, rtiles, other);
-            const Update u = finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k);
+            const Update u = finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k,
+                                           B.sheet, B.n_poly);
             if (act) store(k, u);
             n_after = __popcll(__ballot(act && !u.flag));
         } else {
@@ -549,7 +616,8 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
             pi = self ? pi : ti;
         }, carry);
         stream_tiles_ex(zsrc + own_hi, n_r - own_hi, rtiles, SplitRoot{}, other, carry);
-        const Update u = finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k);
+        const Update u = finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k,
+                                       B.sheet, B.n_poly);
         if (act) store(k, u);
         n_after = __popcll(__ballot(act && !u.flag));
         }
@@ -905,7 +973,7 @@ newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
 template <class T>
 __global__ void seed_centres(const T *__restrict__ stars, const Real *__restrict__ reals,
                              const Front *__restrict__ fronts, const int2 *__restrict__ bmap,
-                             double2 *__restrict__ iter)
+                             const double *__restrict__ sheet, double2 *__restrict__ iter)
 {
     const int2 fq = bmap[blockIdx.x];
     const Front *F = fronts + fq.x;
@@ -913,6 +981,11 @@ __global__ void seed_centres(const T *__restrict__ stars, const Real *__restrict
     const Real *R = reals + F->real;
     const int k = fq.y * 64 + threadIdx.x;
     if (k >= R->n_r) return;
+    if (k >= 2 * R->n_stars) {   // a rectangular sheet's extra root (Sec. 3.2: on a circle)
+        const double *sx = sheet + R->sheet_off + 2 * R->n_poly + 2 * (k - 2 * R->n_stars);
+        iter[F->it_off + k] = make_double2(sx[0], sx[1]);
+        return;
+    }
     const T z = stars[R->star_off + (k >> 1)];
     iter[F->it_off + k] = make_double2(z.x + ((k & 1) ? -1.0 : 1.0), z.y);
 }
@@ -1547,13 +1620,15 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
 
     // fronts, blocks and offsets of every field
     std::vector<Real> rd(n_real);
+    std::vector<double> sheet_host;   // rectangular fields' sheet records
     std::vector<Front> fr;
     std::vector<int2> bmap;
     int64_t it_total = 0, bnd_total = 0, max_nr = 0;
     const int32_t warm_phase = mixed ? PH_F32 : PH_F64;
     for (int r = 0; r < n_real; ++r) {
         const RealHost &h = c->reals[r];
-        const int64_t n_r = 2 * h.n;
+        const SheetPoly sp = sheet_poly(h);
+        const int64_t n_r = 2 * h.n + sp.n_extra;
         if (n_r > ((int64_t)1 << 30)) return fail(MLCC_ERR_INVALID, "too many roots");
         max_nr = std::max(max_nr, n_r);
         Real &R = rd[r];
@@ -1564,7 +1639,22 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         R.n_stars = (int32_t)h.n;
         R.n_r = (int32_t)n_r;
         R.m0 = h.m0;
-        R.gamma = h.gamma;
+        R.gamma = h.gamma - sp.d0;   // a rectangular sheet's constant term joins the shear
+        R.n_poly = sp.n;
+        R.n_extra = sp.n_extra;
+        R.sheet_off = (int64_t)sheet_host.size();
+        if (sp.n > 0) {
+            // d_2k, then the lens-map terms, then the extra roots' start values:
+            // evenly spread on the circle through the corners (Sec. 3.2), at
+            // angles 2 pi (k + 1/2) / (t - 1)
+            sheet_host.insert(sheet_host.end(), sp.d, sp.d + sp.n);
+            sheet_host.insert(sheet_host.end(), sp.dmap, sp.dmap + sp.n);
+            for (int k = 0; k < sp.n_extra; ++k) {
+                const double ang = 2.0 * M_PI * ((double)k + 0.5) / (double)sp.n_extra;
+                sheet_host.push_back(sp.seed_r * std::cos(ang));
+                sheet_host.push_back(sp.seed_r * std::sin(ang));
+            }
+        }
         R.a = 1.0 - h.kappa_s;
         R.a1 = std::fabs(R.a);
         R.sz_r = h.sum_z.x;
@@ -1657,6 +1747,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     MLCC_TRY(c->vsum.reserve((size_t)2 * F * sizeof(double4)));
     if (mixed) MLCC_TRY(c->errbuf.reserve((size_t)it_total * sizeof(double)));
     MLCC_TRY(c->reals_d.reserve((size_t)n_real * sizeof(Real)));
+    MLCC_TRY(c->sheet.reserve(std::max<size_t>(1, sheet_host.size()) * sizeof(double)));
     MLCC_TRY(c->bmap.reserve((size_t)ngrid * sizeof(int2)));
     MLCC_TRY(c->workflags.reserve(2 * MAX_BATCH * sizeof(int32_t)));
     MLCC_TRY(ensure_pinned(c, 2 * (sizeof(Control) + MAX_BATCH * sizeof(int32_t))));
@@ -1674,6 +1765,9 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
                             hipMemcpyHostToDevice, c->stream));
     MLCC_HIP(hipMemcpyAsync(c->fronts.p, fr.data(), (F + 1) * sizeof(Front), hipMemcpyHostToDevice,
                             c->stream));
+    if (!sheet_host.empty())
+        MLCC_HIP(hipMemcpyAsync(c->sheet.p, sheet_host.data(), sheet_host.size() * sizeof(double),
+                                hipMemcpyHostToDevice, c->stream));
     MLCC_HIP(hipMemcpyAsync(c->reals_d.p, rd.data(), n_real * sizeof(Real), hipMemcpyHostToDevice,
                             c->stream));
     MLCC_HIP(hipMemcpyAsync(c->bmap.p, bmap.data(), ngrid * sizeof(int2), hipMemcpyHostToDevice,
@@ -1685,11 +1779,11 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     if (equal)
         hipLaunchKernelGGL(seed_centres<double2>, dim3((unsigned)ngrid), dim3(64), 0, c->stream,
                            c->stars.as<double2>(), c->reals_d.as<Real>(), c->fronts.as<Front>(),
-                           c->bmap.as<int2>(), c->iter[0].as<double2>());
+                           c->bmap.as<int2>(), c->sheet.as<double>(), c->iter[0].as<double2>());
     else
         hipLaunchKernelGGL(seed_centres<double4>, dim3((unsigned)ngrid), dim3(64), 0, c->stream,
                            c->stars4.as<double4>(), c->reals_d.as<Real>(), c->fronts.as<Front>(),
-                           c->bmap.as<int2>(), c->iter[0].as<double2>());
+                           c->bmap.as<int2>(), c->sheet.as<double>(), c->iter[0].as<double2>());
     MLCC_HIP(hipGetLastError());
     // Host copies must finish before the vectors above go out of scope.
     MLCC_HIP(hipStreamSynchronize(c->stream));
@@ -1727,6 +1821,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         A.vieta = c->vieta.as<double4>();
         A.predictor = p->predictor;
         A.errbuf = mixed ? c->errbuf.as<double>() : nullptr;
+        A.sheet = c->sheet.as<double>();
     };
     const dim3 grid((unsigned)ngrid);
     auto launch_kind = [&](int kind, const double2 *cur, double2 *nxt) {
@@ -2146,6 +2241,11 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
                                   10.0 * (double)(h.updates - h.updates_fast);
         stats->algorithmic_flop_sweep_roots =
             20.0 * (double)h.star_updates_fast - 10.0 * (double)h.updates_fast;
+        if (n_real == 1) {   // a rectangular field's extra roots: 10 FLOP per root term each
+            const double ex = 10.0 * (double)sheet_poly(c->reals[0]).n_extra;
+            stats->algorithmic_flop += ex * (double)(h.updates - h.updates_fast);
+            stats->algorithmic_flop_sweep_roots += ex * (double)h.updates_fast;
+        }
         stats->algorithmic_flop_f32 =
             49.0 * (double)h.star_updates_f32 - 10.0 * (double)h.updates_f32;
         stats->algorithmic_flop_polish = 29.0 * (double)h.star_updates_polish;

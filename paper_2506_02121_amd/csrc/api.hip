@@ -109,6 +109,44 @@ static mlcc_status check_grid(const mlcc_grid *g, bool square)
     return MLCC_OK;
 }
 
+// The sheet polynomial of a rectangular field.  App. B gives d alpha_s / d zbar
+// as -kappa_star i / pi sum_{j=1..t} (1/j) (zbar/c)^j (1 + (-1)^j)
+// (1 - e^{2 i Arg(c) j}) + kappa_star - 4 kappa_star Arg(c) / pi (the power-t term
+// vanishes for odd t).  Only even j survive, and with c = |c| e^{i th},
+// (1 - e^{2 i th j}) / c^j = -2 i sin(j th) / |c|^j, so its conjugate is the
+// real-coefficient polynomial
+//   d0 + sum_{j = 2, 4, ..., t-1} d_j z^j,  d_j = -(4 kappa_star / pi) sin(j th) / (j |c|^j),
+//   d0 = kappa_star (1 - 4 th / pi).
+// Integrating d alpha_s / d zbar (and d alpha_s / dz = -kappa_star) from the
+// origin, where the sheet's deflection vanishes by symmetry, gives alpha_s =
+// -kappa_star z + d0 conj(z) + sum_j d_j conj(z)^(j+1) / (j+1).
+SheetPoly sheet_poly(const RealHost &h)
+{
+    SheetPoly p;
+    if (h.t <= 0) return p;
+    const double th = std::atan2(h.c2, h.c1), ac = std::hypot(h.c1, h.c2);
+    p.d0 = h.kappa_star * (1.0 - 4.0 * th / M_PI);
+    p.n = (h.t - 1) / 2;
+    p.n_extra = h.t - 1;
+    p.seed_r = ac;
+    for (int k = 1; k <= p.n; ++k) {
+        const int j = 2 * k;
+        p.d[k - 1] = -(4.0 * h.kappa_star / M_PI) * std::sin(j * th) / (j * std::pow(ac, j));
+        p.dmap[k - 1] = p.d[k - 1] / (j + 1);
+    }
+    return p;
+}
+
+// (t - 1) Arg(c) must stay at least 10% of pi away from a multiple of pi, or
+// the leading coefficient of the sheet polynomial (~ sin((t-1) Arg c)) nearly
+// vanishes and roots escape to infinity (App. B).
+static bool arg_rule_ok(int t, double c1, double c2)
+{
+    if (t < 3) return true;
+    const double r = std::fmod((t - 1) * std::atan2(c2, c1), M_PI);
+    return r >= 0.1 * M_PI && r <= 0.9 * M_PI;
+}
+
 } // namespace mlcc
 
 using namespace mlcc;
@@ -141,10 +179,10 @@ void mlcc_destroy(mlcc_ctx *ctx)
     Ctx &c = ctx->impl;
     (void)hipSetDevice(c.device);
     (void)hipStreamSynchronize(c.stream);
-    DevBuf *bufs[] = {&c.stars, &c.mass, &c.stars4, &c.iter[0], &c.iter[1], &c.flagrow, &c.fronts,
-                      &c.counts, &c.control, &c.etab, &c.bnd, &c.perm, &c.match_aux,
-                      &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.vsum, &c.pq, &c.passupd, &c.reals_d, &c.bmap, &c.diff,
-                      &c.err, &c.edt_col};
+    DevBuf *bufs[] = {&c.stars, &c.mass, &c.stars4, &c.sheet_d, &c.sheet, &c.iter[0], &c.iter[1],
+                      &c.flagrow, &c.fronts, &c.counts, &c.control, &c.etab, &c.bnd, &c.perm,
+                      &c.match_aux, &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.vsum,
+                      &c.pq, &c.passupd, &c.reals_d, &c.bmap, &c.diff, &c.err, &c.edt_col};
     for (DevBuf *b : bufs) b->release();
     if (c.own_stream) (void)hipStreamDestroy(c.own_stream);
     if (c.pinned) (void)hipHostFree(c.pinned);
@@ -191,7 +229,7 @@ struct Neumaier {
 // against.
 static mlcc_status load_fields(Ctx &c, int32_t n_fields, const int64_t *off, const double *x,
                                const double *y, const double *m, const double *kappa_s,
-                               const double *gamma, bool batched)
+                               const double *gamma, bool batched, bool rect = false)
 {
     MLCC_TRY(use_device(&c));
     if (n_fields < 1 || n_fields > 65536)
@@ -208,7 +246,7 @@ static mlcc_status load_fields(Ctx &c, int32_t n_fields, const int64_t *off, con
     for (int32_t r = 0; r < n_fields; ++r) {
         if (!std::isfinite(kappa_s[r]) || !std::isfinite(gamma[r]))
             return fail(MLCC_ERR_INVALID, "field %d: kappa_s and gamma must be finite", r);
-        if (std::fabs(gamma[r]) == std::fabs(1.0 - kappa_s[r]))
+        if (!rect && std::fabs(gamma[r]) == std::fabs(1.0 - kappa_s[r]))
             return fail(MLCC_ERR_INVALID,
                         "field %d: |gamma| == |1 - kappa_s|: gamma - (1-kappa_s) e^{-i phi} "
                         "vanishes on the phase circle", r);
@@ -282,11 +320,91 @@ static mlcc_status load_fields(Ctx &c, int32_t n_fields, const int64_t *off, con
     MLCC_HIP(hipStreamSynchronize(c.stream));
     c.reals = std::move(reals);
     c.batched = batched;
+    c.rect = false;
     c.n = n;
     c.kappa_s = kappa_s[0];
     c.gamma = gamma[0];
     c.equal_mass = c.reals[0].equal && !batched;
     c.mass0 = hm[0];
+    clear_error();
+    return MLCC_OK;
+}
+
+mlcc_status mlcc_rect_taylor_degree(double kappa_star, double c1, double c2, double s, double eps,
+                                    int32_t *t_out)
+{
+    if (!t_out) return fail(MLCC_ERR_INVALID, "t is NULL");
+    if (!(kappa_star > 0) || !(c1 > 0) || !(c2 > 0) || !(s > 1) || !(eps > 0) ||
+        !std::isfinite(kappa_star) || !std::isfinite(c1) || !std::isfinite(c2) ||
+        !std::isfinite(s))
+        return fail(MLCC_ERR_INVALID, "need kappa_star, c1, c2, eps > 0 and s > 1");
+    const double ac = std::hypot(c1, c2);
+    // App. B: |error| <= kappa_star / pi * 4 / (t + 1) * s^-(t+1) * |c| (s + 1) / (s - 1)
+    // where |z| s < |c|; smallest such t, odd, then the Arg rule
+    auto bound = [&](int t) {
+        return kappa_star / M_PI * 4.0 / (t + 1) * std::pow(s, -(t + 1)) * ac * (s + 1) / (s - 1);
+    };
+    int t = 1;
+    while (bound(t) > eps)
+        if (++t > 2 * MAX_SHEET_TERMS + 1)
+            return fail(MLCC_ERR_INVALID, "the App. B bound needs t > %d", 2 * MAX_SHEET_TERMS + 1);
+    if (!(t & 1)) ++t;
+    while (!arg_rule_ok(t, c1, c2)) {
+        t += 2;
+        if (t > 2 * MAX_SHEET_TERMS + 1)
+            return fail(MLCC_ERR_INVALID, "no admissible odd t <= %d", 2 * MAX_SHEET_TERMS + 1);
+    }
+    *t_out = t;
+    clear_error();
+    return MLCC_OK;
+}
+
+mlcc_status mlcc_set_lenses_rect(mlcc_ctx *ctx, int64_t n, const double *x, const double *y,
+                                 const double *m, double kappa_s, double gamma, double kappa_star,
+                                 double c1, double c2, int32_t t)
+{
+    if (!ctx) return fail(MLCC_ERR_INVALID, "ctx is NULL");
+    if (n < 1) return fail(MLCC_ERR_INVALID, "need at least one star (n=%lld)", (long long)n);
+    if (n > (int64_t)1 << 28) return fail(MLCC_ERR_INVALID, "too many stars (%lld)", (long long)n);
+    if (!(kappa_star > 0) || !(c1 > 0) || !(c2 > 0) || !std::isfinite(kappa_star) ||
+        !std::isfinite(c1) || !std::isfinite(c2))
+        return fail(MLCC_ERR_INVALID, "need finite kappa_star, c1, c2 > 0");
+    if (t < 1 || !(t & 1) || t > 2 * MAX_SHEET_TERMS + 1)
+        return fail(MLCC_ERR_INVALID, "t must be odd, 1..%d (got %d)", 2 * MAX_SHEET_TERMS + 1, t);
+    if (!arg_rule_ok(t, c1, c2))
+        return fail(MLCC_ERR_INVALID,
+                    "(t - 1) Arg(c) lies within 10%% of pi of a multiple of pi: the sheet "
+                    "polynomial's leading coefficient nearly vanishes; raise t by 2");
+    RealHost probe;
+    probe.t = t;
+    probe.kappa_star = kappa_star;
+    probe.c1 = c1;
+    probe.c2 = c2;
+    if (t == 1) {
+        const double g = gamma - sheet_poly(probe).d0;
+        if (std::fabs(g) == std::fabs(1.0 - kappa_s))
+            return fail(MLCC_ERR_INVALID, "t = 1 and |gamma - d0| == |1 - kappa_s|");
+    }
+    const int64_t off[2] = {0, n};
+    Ctx &c = ctx->impl;
+    MLCC_TRY(load_fields(c, 1, off, x, y, m, &kappa_s, &gamma, false, true));
+    RealHost &h = c.reals[0];
+    h.t = t;
+    h.kappa_star = kappa_star;
+    h.c1 = c1;
+    h.c2 = c2;
+    c.rect = true;
+    return MLCC_OK;
+}
+
+mlcc_status mlcc_num_roots(mlcc_ctx *ctx, int64_t *n_r)
+{
+    if (!ctx || !n_r) return fail(MLCC_ERR_INVALID, "ctx or n_r is NULL");
+    const Ctx &c = ctx->impl;
+    if (c.n < 1) return fail(MLCC_ERR_STATE, "call mlcc_set_lenses first");
+    int64_t tot = 0;
+    for (const RealHost &h : c.reals) tot += 2 * h.n + sheet_poly(h).n_extra;
+    *n_r = tot;
     clear_error();
     return MLCC_OK;
 }
@@ -347,6 +465,8 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
         return fail(MLCC_ERR_INVALID, "unknown schedule %d", p.schedule);
     if (p.watchdog_ms < 0 || p.watchdog_ms > 600000)
         return fail(MLCC_ERR_INVALID, "watchdog_ms=%d outside [0, 600000]", p.watchdog_ms);
+    if (c.rect && p.precision != MLCC_FP64)
+        return fail(MLCC_ERR_INVALID, "a rectangular field is solved in MLCC_FP64 only");
     MLCC_TRY(check_device_ptr(&c, roots_re, "roots_re"));
     MLCC_TRY(check_device_ptr(&c, roots_im, "roots_im"));
     if ((caustics_re == nullptr) != (caustics_im == nullptr))

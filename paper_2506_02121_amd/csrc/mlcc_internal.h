@@ -78,6 +78,10 @@ struct Front {
     int64_t it_off;   // first element of its roots in the iterate and flag arrays
 };
 
+// Rectangular field: the sheet polynomial (see sheet_poly in api.hip) has at
+// most this many terms, so the Taylor degree is at most 2 MAX_SHEET_TERMS + 1.
+constexpr int MAX_SHEET_TERMS = 64;
+
 // One star field of a (possibly batched) root-finder call, as the kernels
 // see it.
 struct Real {
@@ -89,6 +93,11 @@ struct Real {
     double gamma, a, a1;   // shear, 1 - kappa_s, |1 - kappa_s|
     double sz_r, sz_i, sz2_r, sz2_i, M;   // sum z_i, sum z_i^2, sum m_i (row identities)
     double tol1, tol2;  // rounding of the reference values of the two row identities
+    int32_t n_poly;     // rectangular field: sheet terms (gamma holds gamma - d0); else 0
+    int32_t n_extra;    // roots beyond 2 N: t - 1 for a rectangular field
+    int64_t sheet_off;  // its record in the sheet array: d_2..d_{t-1} (n_poly), the lens-map
+                        // terms d_2k / (2k + 1) (n_poly), start values of the extra roots
+                        // (2 n_extra: re, im)
 };
 
 // Host-side description of one star field.
@@ -98,7 +107,25 @@ struct RealHost {
     bool equal = false;
     double2 sum_z{0, 0}, sum_z2{0, 0};
     double sum_abs_z = 0, sum_abs_z2 = 0, max_abs_z = 0, mass_total = 0;
+    // rectangular field (t > 0): sheet of convergence -kappa_star, corner
+    // c1 + i c2, Taylor degree t
+    int32_t t = 0;
+    double kappa_star = 0, c1 = 0, c2 = 0;
 };
+
+// The sheet polynomial of a rectangular field, as the kernels use it:
+//   conj(d alpha_s / d zbar) = d0 + sum_{k=1..n} d[k-1] z^(2k), d real,
+// and in the lens map alpha_s(z) = -kappa_star z + d0 conj(z)
+//   + sum_k d[k-1] conj(z)^(2k+1) / (2k+1).
+struct SheetPoly {
+    int32_t n = 0;          // terms (t - 1) / 2; 0 for a circular field
+    int32_t n_extra = 0;    // roots the sheet adds: t - 1
+    double d0 = 0;          // constant term (folded into gamma by the caller)
+    double seed_r = 0;      // radius of the extra roots' start values, |c|
+    double d[MAX_SHEET_TERMS] = {};
+    double dmap[MAX_SHEET_TERMS] = {};   // d[k-1] / (2k + 1)
+};
+SheetPoly sheet_poly(const RealHost &h);
 enum { FRONT_IDLE = 0, FRONT_ACTIVE = 1, FRONT_DONE = 2, FRONT_FAILED = 3 };
 enum { PH_F64 = 0, PH_F32 = 1, PH_POLISH = 2 };
 enum { TRIED_F32 = 1, TRIED_POLISH = 2 };
@@ -128,6 +155,7 @@ struct Ctx {
     // lenses: one field (set_lenses) or a batch (set_lenses_batched), stars
     // concatenated
     bool batched = false;
+    bool rect = false;  // set_lenses_rect: one rectangular field
     std::vector<RealHost> reals;
     int64_t n = 0;      // total stars
     double kappa_s = 0.0, gamma = 0.0;  // the single field's macro-model
@@ -136,6 +164,8 @@ struct Ctx {
     DevBuf stars;  // double2[n]: (x, y)
     DevBuf mass;   // double[n]
     DevBuf stars4; // double4[n]: (x, y, m, 0)
+    DevBuf sheet_d; // double[MAX_SHEET_TERMS]: lens-map terms of a rectangular field's sheet
+    DevBuf sheet;   // double[]: the root finder's sheet records (Real::sheet_off)
 
     // root-finder workspace
     DevBuf iter[2];   // double2[F * n_r]: Jacobi iterates, ping-pong

@@ -36,6 +36,7 @@ EXPORTED = [
     "mlcc_set_lenses_batched", "mlcc_cc_params_default", "mlcc_find_critical_curves",
     "mlcc_find_critical_curves_batched", "mlcc_map_caustics",
     "mlcc_caustic_crossings", "mlcc_caustic_distances", "mlcc_measure_valu_peak",
+    "mlcc_set_lenses_rect", "mlcc_rect_taylor_degree", "mlcc_num_roots",
 ]
 
 
@@ -94,6 +95,11 @@ _SIG = {
                                ctypes.c_int),
     "mlcc_caustic_distances": ([_vp, ctypes.POINTER(GridC), _vp, _vp, _vp], ctypes.c_int),
     "mlcc_measure_valu_peak": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(_d)], ctypes.c_int),
+    "mlcc_set_lenses_rect": ([_vp, _i64, _vp, _vp, _vp, _d, _d, _d, _d, _d, ctypes.c_int32],
+                             ctypes.c_int),
+    "mlcc_rect_taylor_degree": ([_d, _d, _d, _d, _d, ctypes.POINTER(ctypes.c_int32)],
+                                ctypes.c_int),
+    "mlcc_num_roots": ([_vp, ctypes.POINTER(_i64)], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIG.items():
     _f = getattr(_lib, _name)
@@ -121,6 +127,15 @@ def measure_valu_peak(device: int = 0, kind: str = "fp64") -> float:
     out = _d(0.0)
     _check(_lib.mlcc_measure_valu_peak(int(device), kinds[kind], ctypes.byref(out)))
     return out.value
+
+
+def rect_taylor_degree(kappa_star: float, c1: float, c2: float, s: float, eps: float) -> int:
+    """App. B truncation degree of a rectangular field's sheet for accuracy
+    eps where |z| s < |c| (odd, and clear of the Arg(c) degeneracy)."""
+    t = ctypes.c_int32(0)
+    _check(_lib.mlcc_rect_taylor_degree(float(kappa_star), float(c1), float(c2), float(s),
+                                        float(eps), ctypes.byref(t)))
+    return int(t.value)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -187,6 +202,26 @@ class Context:
         self.n = x.numel()
         self.star_offsets = None
 
+    def set_lenses_rect(self, x: torch.Tensor, y: torch.Tensor, m: torch.Tensor, kappa_s: float,
+                        gamma: float, kappa_star: float, c1: float, c2: float, t: int):
+        """A rectangular field (corner c1 + i c2, sheet of convergence
+        -kappa_star Taylor-expanded to odd degree t): 2N + t - 1 roots per
+        phase (num_roots())."""
+        for a, w in ((x, "x"), (y, "y"), (m, "m")):
+            _need(a, torch.float64, self.device, w)
+        self._stream()
+        _check(_lib.mlcc_set_lenses_rect(self._h, x.numel(), _ptr(x), _ptr(y), _ptr(m),
+                                         float(kappa_s), float(gamma), float(kappa_star),
+                                         float(c1), float(c2), int(t)))
+        self.n = x.numel()
+        self.star_offsets = None
+
+    def num_roots(self) -> int:
+        """Roots per phase of the current lenses."""
+        n_r = _i64(0)
+        _check(_lib.mlcc_num_roots(self._h, ctypes.byref(n_r)))
+        return int(n_r.value)
+
     def set_lenses_batched(self, star_offsets, x: torch.Tensor, y: torch.Tensor, m: torch.Tensor,
                            kappa_s, gamma):
         """Several fields: field r holds stars star_offsets[r]:star_offsets[r+1]
@@ -227,8 +262,8 @@ class Context:
                              schedule: str = "persistent", watchdog_ms: int = 0):
         """Returns (roots_re, roots_im, chain_next, stats, status), or with
         caustics=True (roots_re, roots_im, caus_re, caus_im, chain_next, stats,
-        status).  One field: arrays are (m_steps + 1, 2N) float64 device
-        tensors.  Several fields: flat tensors of (m_steps + 1) * 2 * (total
+        status).  One field: arrays are (m_steps + 1, n_r) float64 device
+        tensors (n_r = 2N, or 2N + t - 1 for a rectangular field).  Several fields: flat tensors of (m_steps + 1) * 2 * (total
         stars) elements; field_blocks() gives each field's offsets."""
         p = self.default_params(m_steps)
         p.n_subchains = int(n_subchains)
@@ -241,7 +276,7 @@ class Context:
         p.predictor = int(predictor)
         p.schedule = {"rounds": 0, "persistent": 1}[schedule]
         p.watchdog_ms = int(watchdog_ms)
-        n_r = 2 * self.n
+        n_r = self.num_roots()
         shape = (m_steps + 1, n_r) if self.star_offsets is None else ((m_steps + 1) * n_r,)
         if out is None:
             rr = torch.empty(shape, dtype=torch.float64, device=self.device)
