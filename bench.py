@@ -41,6 +41,11 @@ WORKLOAD_TEXT = {
                   "check, FP64 sweeps for anything not accepted, FP64 lens mapping",
     "tiny": "N=10 equal-mass stars, kappa_star=0.3, kappa_s=0, gamma=0.3; 1,000 phase steps; "
             "caustics; N_cc 256^2 over 16x16 theta_E",
+    "rect": "rectangular field (Sec. 4.2) over the region the n10k source map sees: N=437 "
+            "equal-mass stars uniform in [-19.2, 19.2] x [-35.7, 35.7] theta_E, kappa_star=0.5 "
+            "(sheet Taylor degree t=87, App. B error 1e-8 within |c|/1.25), kappa_s=0, "
+            "gamma=0.3; 20,000 phase steps (20,001 rows x 960 roots); caustics; N_cc int32 "
+            "2048^2 and FP64 distance map over 40x40 theta_E",
     "batched": "256 independent fields, N log-uniform in [50, 5000], kappa_star U[0.1, 0.8], "
                "gamma U[0, 0.6], kappa_s=0, Salpeter masses on [0.08,1]; 4,000 phase steps "
                "each; one root-finder call over all fields in mixed precision; caustics",
@@ -113,11 +118,22 @@ def main():
         wl.grid = fields.Grid(0.0, 0.0, 8.0, 8.0, 256, 256)
     m_steps = wl.m_steps
     n = f.n
-    n_r = 2 * n
     dev = torch.device("cuda", 0)
     x = torch.as_tensor(f.x, device=dev)
     y = torch.as_tensor(f.y, device=dev)
     mm = torch.as_tensor(f.m, device=dev)
+
+    def load(c):
+        if f.sheet is None:
+            c.set_lenses(x, y, mm, f.kappa_s, f.gamma)
+        else:
+            ks, c1, c2, t = f.sheet
+            c.set_lenses_rect(x, y, mm, f.kappa_s, f.gamma, ks, c1, c2, t)
+
+    probe = mlcc.Context(0)
+    load(probe)
+    n_r = probe.num_roots()   # 2N, or 2N + t - 1 for a rectangular field
+    probe.close()
     rows = m_steps + 1
     roots_re = torch.empty((rows, n_r), dtype=torch.float64, device=dev)
     roots_im = torch.empty_like(roots_re)
@@ -133,7 +149,7 @@ def main():
     def step(prec):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record()
-        ctx.set_lenses(x, y, mm, f.kappa_s, f.gamma)
+        load(ctx)
         # roots and, in the same pass, their caustic images
         _, _, _, _, cn, st, _ = ctx.find_critical_curves(
             m_steps, n_subchains=args.subchains, timing=True, caustics=True,
@@ -184,7 +200,7 @@ def main():
     n_map = min(rows, max(1, (1 << 26) // n_r))
     zr_s, zi_s = roots_re[:n_map].reshape(-1), roots_im[:n_map].reshape(-1)
     wr_s, wi_s = torch.empty_like(zr_s), torch.empty_like(zi_s)
-    ctx.set_lenses(x, y, mm, f.kappa_s, f.gamma)
+    load(ctx)
     ctx.map_caustics(zr_s, zi_s, out=(wr_s, wi_s))
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev[0].record()
@@ -248,7 +264,7 @@ def main():
                   "max_row_sweeps": s0["max_row_sweeps"], "match_maxdist": s0["match_maxdist"],
                   "ncc_max": int(ncc_h.max()), "ncc_min": int(ncc_h.min())},
     }
-    if args.compare:
+    if args.compare and f.sheet is None:   # a rectangular field is solved in FP64 only
         # the other precision on the same field: throughput, and how far its
         # roots lie from this run's on sampled rows (same sets, any order)
         from scipy.spatial import cKDTree
@@ -515,12 +531,13 @@ def cpu_baseline(f, m_steps, rows):
     """The oracle as it stands, timed on the host's cores, on a bounded
     sample of the same workload: the centre row of the phase grid cold-started
     from the seeds (not timed), then `rows` warm rows, each seeded with the
-    previous row as the paper grows a chain (timed).  roots/s = rows x 2N /
-    time."""
+    previous row as the paper grows a chain (timed).  roots/s = rows x n_r /
+    time (n_r = 2N, + t - 1 for a rectangular field)."""
     import numpy as np
 
     import oracle
     c = m_steps // 2
+    n_r = oracle.num_roots(f)
     log(f"cpu baseline: oracle cold start at row {c}, then {rows} timed warm rows on "
         f"{oracle.num_threads()} threads")
     z, sw0, up0, _ = oracle.aberth_row(f, oracle.phase(c, m_steps))
@@ -537,18 +554,18 @@ def cpu_baseline(f, m_steps, rows):
     _, _, up1, _ = oracle.aberth_row(f, oracle.phase(c + rows + 1, m_steps), z0=z)
     dt1 = time.perf_counter() - t
     oracle.set_num_threads(threads)
-    log(f"cpu baseline: {rows * 2 * f.n / dt:.3e} roots/s on {threads} threads, "
-        f"{2 * f.n / dt1:.3e} on one")
+    log(f"cpu baseline: {rows * n_r / dt:.3e} roots/s on {threads} threads, "
+        f"{n_r / dt1:.3e} on one")
     return {
-        "value": rows * 2 * f.n / dt,
+        "value": rows * n_r / dt,
         "unit": "roots/s",
         "cores": threads,
         "kind": "oracle",
         "sample": (f"{rows} warm rows (phase steps {c + 1}..{c + rows} of {m_steps}, "
-                   f"{2 * f.n} roots each, {f.n} stars), each seeded with the previous "
+                   f"{n_r} roots each, {f.n} stars), each seeded with the previous "
                    f"row, after an untimed cold start at row {c}: {ups} root updates in "
                    f"{dt:.1f} s"),
-        "one_thread": {"value": 2 * f.n / dt1, "unit": "roots/s",
+        "one_thread": {"value": n_r / dt1, "unit": "roots/s",
                        "sample": f"warm row {c + rows + 1}: {up1} root updates in {dt1:.1f} s"},
     }
 

@@ -146,7 +146,7 @@ def tiny_field(seed: int = 0) -> StarField:
 
 
 def workload(name: str, seed: int = 0) -> Workload:
-    """The five named workloads.
+    """The six named workloads.
 
     tiny     N=10 equal masses, 1,000 phase steps (oracle finishes in seconds)
     n1k      N=1,000 Salpeter, kappa_star=0.4, kappa_s=0.2, gamma=0.45,
@@ -157,7 +157,17 @@ def workload(name: str, seed: int = 0) -> Workload:
     batched  256 realisations, N log-uniform in [50, 5000], kappa_star in
              U[0.1, 0.8], gamma in U[0, 0.6], kappa_s=0, Salpeter masses,
              4,000 steps each
+    rect     a rectangular field (Sec. 4.2) over the region that the n10k
+             source map (40x40 at kappa_s=0, gamma=0.3) sees without stars,
+             |x| <= 20/(1+gamma), |y| <= 20/(1-gamma), enlarged by s = 1.25:
+             N=437 equal masses, kappa_star=0.5, c2/c1 = (1+gamma)/(1-gamma),
+             sheet Taylor degree t = 87 (App. B's rule for error 1e-8 where
+             |z| < |c|/1.25), 20,000 steps, the n10k grid
     """
+    if name == "rect":
+        g = 0.3
+        f = make_rect_field(rng_for(seed, 5), 437, 0.5, 0.0, g, (1 + g) / (1 - g), 87, "equal")
+        return Workload(name, f, 20000, Grid(0.0, 0.0, 20.0, 20.0, 2048, 2048))
     if name == "tiny":
         return Workload(name, tiny_field(seed), 1000)
     if name == "n1k":

@@ -1,5 +1,6 @@
 """Host logic of the rectangular-field entry points (no GPU): the App. B
 Taylor-degree rule of the library against the oracle's reading."""
+import numpy as np
 import pytest
 
 import oracle
@@ -24,3 +25,17 @@ def test_taylor_degree_rejects_bad_arguments(mlcc):
                  (0.4, 2.0, 3.0, 1.3, 0.0), (0.4, 2.0, 3.0, 1.001, 1e-300)]:
         with pytest.raises(mlcc.MlccError):
             mlcc.rect_taylor_degree(*args)
+
+
+def test_rect_workload_uses_app_b_degree(mlcc):
+    """The rect workload's Taylor degree is the App. B rule's for error 1e-8
+    where |z| < |c| / 1.25."""
+    from paper_2506_02121_amd import fields
+    f = fields.workload("rect").field
+    ks, c1, c2, t = f.sheet
+    assert t == mlcc.rect_taylor_degree(ks, c1, c2, 1.25, 1e-8) == oracle.rect_taylor_degree(
+        ks, c1, c2, 1.25, 1e-8)
+    # the corner sits 1.25 times beyond the corner of the star-free image of the
+    # 40 x 40 source map, |x| <= 20 / 1.3, |y| <= 20 / 0.7 (to the rounding of N)
+    assert abs(np.hypot(c1, c2) / (1.25 * np.hypot(20 / 1.3, 20 / 0.7)) - 1) < 2e-3
+    assert abs(c2 / c1 - 1.3 / 0.7) < 1e-12
