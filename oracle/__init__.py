@@ -67,6 +67,9 @@ def lib() -> ctypes.CDLL:
             "orc_critical_curves": [_i64, _D, _D, _D, _d, _d, _D, _i64, _i64, _d, _d, _i64,
                                     _i64, ctypes.c_int, _D, _D, _I32, _I64, _D],
             "orc_num_roots": [_i64, _D],
+            "orc_directional_distance": [_i64, _i64, _I32, _d, _d, _d, _D, _U8],
+            "orc_distance_histogram": [_i64, _D, _U8, _I32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, _d, _I64],
             "orc_ncc_pixels": [_i64, _i64, _D, _D, _I32, _d, _d, _d, _d, _i64, _i64, _I32],
             "orc_ncc_rows": [_i64, _i64, _D, _D, _I32, _d, _d, _d, _d, _i64, _i64, _I32],
             "orc_ncc_at": [_i64, _i64, _D, _D, _I32, _d, _d, _d, _d, _i64, _i64, _i64, _I64,
@@ -348,3 +351,33 @@ def edt_brute(ncc, h):
 def edt_twopass(ncc, h):
     """(distance, border_limited, squared pixel distance), two-pass exact."""
     return _edt(lib().orc_edt_twopass, ncc, h)
+
+
+def directional_distance(ncc, h, angle):
+    """Moving source (Sec. 5.2): distance along the direction `angle` (from
+    the +y1 axis) to the first caustic pixel entered, by brute force.
+    Returns (dist, border_limited)."""
+    ncc = np.ascontiguousarray(ncc, dtype=np.int32)
+    ny, nx = ncc.shape
+    dist = np.empty((ny, nx))
+    bl = np.empty((ny, nx), dtype=np.uint8)
+    rc = lib().orc_directional_distance(nx, ny, _p(ncc, _I32), float(h), float(np.cos(angle)),
+                                        float(np.sin(angle)), _p(dist, _D), _p(bl, _U8))
+    if rc != OK:
+        raise OracleError(rc, "directional_distance")
+    return dist, bl
+
+
+def distance_histogram(dist, border_limited, n_bins, d_max, ncc=None, ncc_lo=0, n_classes=1):
+    """Counts per distance bin of width d_max / n_bins (last column: d >=
+    d_max), per N_cc class when ncc is given; border-limited pixels skipped."""
+    dist = np.ascontiguousarray(dist, dtype=np.float64).ravel()
+    bl = np.ascontiguousarray(border_limited, dtype=np.uint8).ravel()
+    nc = None if ncc is None else np.ascontiguousarray(ncc, dtype=np.int32).ravel()
+    counts = np.zeros((n_classes, n_bins + 1), dtype=np.int64)
+    rc = lib().orc_distance_histogram(dist.shape[0], _p(dist, _D), _p(bl, _U8), _p(nc, _I32),
+                                      int(ncc_lo), int(n_classes), int(n_bins),
+                                      float(n_bins / d_max), _p(counts, _I64))
+    if rc != OK:
+        raise OracleError(rc, "distance_histogram")
+    return counts

@@ -902,6 +902,95 @@ int orc_edt_twopass(int64_t nx, int64_t ny, const int32_t *ncc, double h, double
     return ORC_OK;
 }
 
+/* ---------------------------------------------------------------------- */
+/* Moving source (Sec. 5.2, Figs. 5 bottom, 6, 7)                           */
+/* ---------------------------------------------------------------------- */
+
+/* Distance a source moving from the centre of pixel p along (ca, sa) (a unit
+ * vector; angle from the +y1 axis) travels before its centre enters a
+ * caustic pixel (a pixel with a 4-neighbour of different N_cc, as for the
+ * expanding source), in units of the pixel size h: the entry parameter of
+ * the ray into the pixel's square, the largest of its two near-slab
+ * crossings, taken over every caustic pixel whose square the ray passes
+ * through (strictly: a ray that only touches a corner does not enter).  0 on
+ * a caustic pixel.  If none is entered, the ray's exit from the map and
+ * border_limited = 1 (the map border is not a caustic, Fig. 5 caption).
+ * Brute force over all caustic pixels; each parameter is one division of an
+ * exact half-integer offset. */
+static double slab(double lo, double hi, double p, double c, double *tfar)
+{
+    /* near and far crossing of lo <= p + t c <= hi */
+    if (c == 0.0) {
+        *tfar = (p > lo && p < hi) ? INFINITY : -INFINITY;
+        return (p > lo && p < hi) ? -INFINITY : INFINITY;
+    }
+    double t1 = (lo - p) / c, t2 = (hi - p) / c;
+    *tfar = t1 > t2 ? t1 : t2;
+    return t1 < t2 ? t1 : t2;
+}
+
+int orc_directional_distance(int64_t nx, int64_t ny, const int32_t *ncc, double h, double ca,
+                             double sa, double *dist, uint8_t *border_limited)
+{
+    if (nx < 1 || ny < 1 || !(h > 0)) return ORC_ERR_INVALID;
+    uint8_t *mask = malloc((size_t)(nx * ny));
+    orc_caustic_mask(nx, ny, ncc, mask);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < ny; ++r)
+        for (int64_t c = 0; c < nx; ++c) {
+            const int64_t i = r * nx + c;
+            if (mask[i]) { dist[i] = 0.0; border_limited[i] = 0; continue; }
+            double best = INFINITY;
+            for (int64_t qr = 0; qr < ny; ++qr)
+                for (int64_t qc = 0; qc < nx; ++qc) {
+                    if (!mask[qr * nx + qc]) continue;
+                    double fx, fy;
+                    /* the square of pixel q, relative to p's centre */
+                    double nxp = slab((double)(qc - c) - 0.5, (double)(qc - c) + 0.5, 0.0, ca, &fx);
+                    double nyp = slab((double)(qr - r) - 0.5, (double)(qr - r) + 0.5, 0.0, sa, &fy);
+                    double tn = nxp > nyp ? nxp : nyp, tf = fx < fy ? fx : fy;
+                    if (tn < tf && tf > 0.0 && tn >= 0.0 && tn < best) best = tn;
+                }
+            if (best < INFINITY) {
+                dist[i] = best * h;
+                border_limited[i] = 0;
+            } else {
+                /* exit from the map [-1/2, nx - 1/2] x [-1/2, ny - 1/2] */
+                double fx, fy;
+                slab(-0.5 - (double)c, (double)(nx - c) - 0.5, 0.0, ca, &fx);
+                slab(-0.5 - (double)r, (double)(ny - r) - 0.5, 0.0, sa, &fy);
+                dist[i] = (fx < fy ? fx : fy) * h;
+                border_limited[i] = 1;
+            }
+        }
+    free(mask);
+    return ORC_OK;
+}
+
+/* Histogram of distances (Figs. 6, 7): pixels not border-limited, bin
+ * k = floor(d * inv_w) for d * inv_w < n_bins, else the overflow bin n_bins;
+ * with ncc given, one row of n_bins + 1 counts per N_cc class ncc_lo ..
+ * ncc_lo + n_classes - 1 (pixels of other classes are not counted). */
+int orc_distance_histogram(int64_t npix, const double *dist, const uint8_t *border_limited,
+                           const int32_t *ncc, int32_t ncc_lo, int32_t n_classes, int32_t n_bins,
+                           double inv_w, int64_t *counts)
+{
+    if (n_bins < 1 || n_classes < 1 || !(inv_w > 0)) return ORC_ERR_INVALID;
+    memset(counts, 0, sizeof(int64_t) * (size_t)n_classes * (size_t)(n_bins + 1));
+    for (int64_t i = 0; i < npix; ++i) {
+        if (border_limited[i]) continue;
+        int64_t cls = 0;
+        if (ncc) {
+            cls = (int64_t)ncc[i] - ncc_lo;
+            if (cls < 0 || cls >= n_classes) continue;
+        }
+        double x = dist[i] * inv_w;
+        int64_t k = x < (double)n_bins ? (int64_t)floor(x) : n_bins;
+        counts[cls * (n_bins + 1) + k] += 1;
+    }
+    return ORC_OK;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
