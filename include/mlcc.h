@@ -344,6 +344,44 @@ mlcc_status mlcc_caustic_distances(mlcc_ctx *ctx, const mlcc_grid *grid, const i
                                    double *dist, uint8_t *border_limited);
 
 /*
+ * caustic_distances_directional -- distance to the caustics for a moving source
+ * (Sec. 5.2, Fig. 5 bottom): from every pixel centre, the distance travelled
+ * along the direction (cos angle, sin angle) (angle from the +y1 axis, in
+ * radians) before the source centre enters a caustic pixel (a pixel with a
+ * 4-neighbour of different N_cc, as for mlcc_caustic_distances).  A square
+ * the path only touches at a corner is not entered; a caustic pixel gets 0.
+ * If the path leaves the map first (the border is not a caustic, Fig. 5
+ * caption), the distance is the exit distance and border_limited is 1.
+ * Square pixels as for mlcc_caustic_distances; nx + ny <= 10^6.
+ *   ncc             device int32[ny * nx]
+ *   dist            device float64[ny * nx], in units of hx
+ *   border_limited  device uint8[ny * nx] or NULL
+ * Enqueues only.
+ */
+mlcc_status mlcc_caustic_distances_directional(mlcc_ctx *ctx, const mlcc_grid *grid,
+                                               const int32_t *ncc, double angle, double *dist,
+                                               uint8_t *border_limited);
+
+/*
+ * distance_histogram -- the distributions of Figs. 6 and 7: counts of pixels
+ * by distance (bin k holds k w <= d < (k+1) w, w = d_max / n_bins, computed as
+ * floor(d * (n_bins / d_max)); column n_bins counts d >= d_max), skipping
+ * border-limited pixels, and with ncc given, by N_cc class (row k holds
+ * N_cc = ncc_lo + k; other values are skipped).  P(d | angle) is one call per
+ * angle of mlcc_caustic_distances_directional; P(d | N_cc) one call with ncc.
+ *   count           pixels
+ *   dist, border_limited  device float64[count], uint8[count]
+ *   ncc             device int32[count] or NULL (then n_classes = 1)
+ *   counts          device int64[n_classes * (n_bins + 1)], overwritten;
+ *                   n_classes * (n_bins + 1) <= 8192
+ * Enqueues only.
+ */
+mlcc_status mlcc_distance_histogram(mlcc_ctx *ctx, int64_t count, const double *dist,
+                                    const uint8_t *border_limited, const int32_t *ncc,
+                                    int32_t ncc_lo, int32_t n_classes, int32_t n_bins,
+                                    double d_max, int64_t *counts);
+
+/*
  * measure_valu_peak -- a measurement aid, not an operation of the paper: the
  * vector-ALU rate this device reaches on independent FMA chains (kind 0 =
  * FP64 v_fma_f64, 1 = FP32 v_fma_f32, unpacked), in TFLOP/s (FMA = 2 FLOP),

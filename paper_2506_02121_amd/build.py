@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libmlcc.so")
 ARCH = os.environ.get("MLCC_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.hip", "aberth.hip", "chains.hip", "caustics.hip", "crossings.hip", "edt.hip",
-           "probe.hip"]
+           "directional.hip", "probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -182,7 +182,8 @@ void mlcc_destroy(mlcc_ctx *ctx)
     DevBuf *bufs[] = {&c.stars, &c.mass, &c.stars4, &c.sheet_d, &c.sheet, &c.iter[0], &c.iter[1],
                       &c.flagrow, &c.fronts, &c.counts, &c.control, &c.etab, &c.bnd, &c.perm,
                       &c.match_aux, &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.vsum,
-                      &c.pq, &c.passupd, &c.reals_d, &c.bmap, &c.diff, &c.err, &c.edt_col};
+                      &c.pq, &c.passupd, &c.reals_d, &c.bmap, &c.diff, &c.err, &c.edt_col,
+                      &c.dmask};
     for (DevBuf *b : bufs) b->release();
     if (c.own_stream) (void)hipStreamDestroy(c.own_stream);
     if (c.pinned) (void)hipHostFree(c.pinned);
@@ -551,6 +552,49 @@ mlcc_status mlcc_caustic_distances(mlcc_ctx *ctx, const mlcc_grid *grid, const i
     if (border_limited) MLCC_TRY(check_device_ptr(&c, border_limited, "border_limited"));
     clear_error();
     return launch_caustic_distances(&c, grid, ncc, dist, border_limited);
+}
+
+mlcc_status mlcc_caustic_distances_directional(mlcc_ctx *ctx, const mlcc_grid *grid,
+                                               const int32_t *ncc, double angle, double *dist,
+                                               uint8_t *border_limited)
+{
+    if (!ctx) return fail(MLCC_ERR_INVALID, "ctx is NULL");
+    Ctx &c = ctx->impl;
+    MLCC_TRY(use_device(&c));
+    MLCC_TRY(check_grid(grid, true));
+    if (!std::isfinite(angle)) return fail(MLCC_ERR_INVALID, "angle must be finite");
+    if ((int64_t)grid->nx + grid->ny > 1000000)
+        return fail(MLCC_ERR_INVALID, "moving-source distances need nx + ny <= 10^6");
+    MLCC_TRY(check_device_ptr(&c, ncc, "ncc"));
+    MLCC_TRY(check_device_ptr(&c, dist, "dist"));
+    if (border_limited) MLCC_TRY(check_device_ptr(&c, border_limited, "border_limited"));
+    clear_error();
+    return launch_directional_distances(&c, grid, ncc, angle, dist, border_limited);
+}
+
+mlcc_status mlcc_distance_histogram(mlcc_ctx *ctx, int64_t count, const double *dist,
+                                    const uint8_t *border_limited, const int32_t *ncc,
+                                    int32_t ncc_lo, int32_t n_classes, int32_t n_bins,
+                                    double d_max, int64_t *counts)
+{
+    if (!ctx) return fail(MLCC_ERR_INVALID, "ctx is NULL");
+    Ctx &c = ctx->impl;
+    MLCC_TRY(use_device(&c));
+    if (count < 0) return fail(MLCC_ERR_INVALID, "count < 0");
+    if (n_bins < 1 || n_classes < 1 || (int64_t)n_classes * (n_bins + 1) > 8192)
+        return fail(MLCC_ERR_INVALID, "need n_bins, n_classes >= 1 and n_classes * (n_bins + 1) "
+                                      "<= 8192");
+    if (!ncc && n_classes != 1) return fail(MLCC_ERR_INVALID, "n_classes must be 1 without ncc");
+    if (!(d_max > 0) || !std::isfinite(d_max)) return fail(MLCC_ERR_INVALID, "d_max must be > 0");
+    if (count > 0) {
+        MLCC_TRY(check_device_ptr(&c, dist, "dist"));
+        MLCC_TRY(check_device_ptr(&c, border_limited, "border_limited"));
+        if (ncc) MLCC_TRY(check_device_ptr(&c, ncc, "ncc"));
+    }
+    MLCC_TRY(check_device_ptr(&c, counts, "counts"));
+    clear_error();
+    return launch_distance_histogram(&c, count, dist, border_limited, ncc, ncc_lo, n_classes,
+                                     n_bins, d_max, counts);
 }
 
 } // extern "C"

@@ -191,6 +191,7 @@ struct Ctx {
     DevBuf diff;      // int32 per-row difference map
     DevBuf err;       // int32 error flag
     DevBuf edt_col;   // int32 column distances
+    DevBuf dmask;     // uint8 caustic-pixel mask (moving-source distances)
 
     void *pinned = nullptr; // host-pinned readback area
     size_t pinned_bytes = 0;
@@ -204,6 +205,12 @@ mlcc_status ensure_pinned(Ctx *c, size_t bytes);
 mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *roots_re,
                                       double *roots_im, double *caus_re, double *caus_im,
                                       int32_t *chain_next, mlcc_cc_stats *stats);
+mlcc_status launch_directional_distances(Ctx *c, const mlcc_grid *grid, const int32_t *ncc,
+                                         double angle, double *dist, uint8_t *border_limited);
+mlcc_status launch_distance_histogram(Ctx *c, int64_t count, const double *dist,
+                                      const uint8_t *border_limited, const int32_t *ncc,
+                                      int32_t ncc_lo, int32_t n_classes, int32_t n_bins,
+                                      double d_max, int64_t *counts);
 mlcc_status launch_map_caustics(Ctx *c, int64_t count, const double *zr, const double *zi,
                                 double *wr, double *wi);
 mlcc_status run_caustic_crossings(Ctx *c, int64_t rows, int64_t n_r, const double *wr,

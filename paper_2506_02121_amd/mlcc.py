@@ -37,6 +37,7 @@ EXPORTED = [
     "mlcc_find_critical_curves_batched", "mlcc_map_caustics",
     "mlcc_caustic_crossings", "mlcc_caustic_distances", "mlcc_measure_valu_peak",
     "mlcc_set_lenses_rect", "mlcc_rect_taylor_degree", "mlcc_num_roots",
+    "mlcc_caustic_distances_directional", "mlcc_distance_histogram",
 ]
 
 
@@ -100,6 +101,10 @@ _SIG = {
     "mlcc_rect_taylor_degree": ([_d, _d, _d, _d, _d, ctypes.POINTER(ctypes.c_int32)],
                                 ctypes.c_int),
     "mlcc_num_roots": ([_vp, ctypes.POINTER(_i64)], ctypes.c_int),
+    "mlcc_caustic_distances_directional": ([_vp, ctypes.POINTER(GridC), _vp, _d, _vp, _vp],
+                                           ctypes.c_int),
+    "mlcc_distance_histogram": ([_vp, _i64, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int32, _d, _vp], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIG.items():
     _f = getattr(_lib, _name)
@@ -350,6 +355,40 @@ class Context:
         _check(_lib.mlcc_caustic_distances(self._h, ctypes.byref(gc), _ptr(ncc), _ptr(dist),
                                            _ptr(bl)))
         return dist, bl
+
+    def caustic_distances_directional(self, grid, ncc: torch.Tensor, angle: float,
+                                      border_limited: bool = True, out=None):
+        """Moving source: distance along direction `angle` (radians from +y1)
+        to the first caustic pixel entered; (dist, border_limited)."""
+        _need(ncc, torch.int32, self.device, "ncc")
+        g = as_grid(grid)
+        if out is None:
+            dist = torch.empty((g.ny, g.nx), dtype=torch.float64, device=self.device)
+            bl = torch.empty((g.ny, g.nx), dtype=torch.uint8, device=self.device) if border_limited else None
+        else:
+            dist, bl = out
+        self._stream()
+        gc = g.c()
+        _check(_lib.mlcc_caustic_distances_directional(self._h, ctypes.byref(gc), _ptr(ncc),
+                                                       float(angle), _ptr(dist), _ptr(bl)))
+        return dist, bl
+
+    def distance_histogram(self, dist: torch.Tensor, border_limited: torch.Tensor, n_bins: int,
+                           d_max: float, ncc: Optional[torch.Tensor] = None, ncc_lo: int = 0,
+                           n_classes: int = 1, out=None):
+        """int64 (n_classes, n_bins + 1) counts of non-border-limited pixels by
+        distance bin (last column: d >= d_max), per N_cc class with ncc."""
+        _need(dist, torch.float64, self.device, "dist")
+        _need(border_limited, torch.uint8, self.device, "border_limited")
+        if ncc is not None:
+            _need(ncc, torch.int32, self.device, "ncc")
+        counts = out if out is not None else torch.empty((n_classes, n_bins + 1),
+                                                         dtype=torch.int64, device=self.device)
+        self._stream()
+        _check(_lib.mlcc_distance_histogram(self._h, dist.numel(), _ptr(dist), _ptr(border_limited),
+                                            _ptr(ncc), int(ncc_lo), int(n_classes), int(n_bins),
+                                            float(d_max), _ptr(counts)))
+        return counts
 
 
 def last_error() -> str:
