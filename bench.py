@@ -73,6 +73,10 @@ def parse():
     ap.add_argument("--compare", dest="compare", action="store_true", default=True,
                     help="also run the other precision (mixed vs FP64) on the same field")
     ap.add_argument("--no-compare", dest="compare", action="store_false")
+    ap.add_argument("--directional", type=int, default=0, metavar="K",
+                    help="after the timed steps, moving-source distance maps of the last step's "
+                         "N_cc map for K directions over [0, 180) degrees, with their histograms "
+                         "(and by N_cc class at 90 degrees)")
     ap.add_argument("--serial", dest="serial", action="store_true", default=True,
                     help="batched workload: also solve every field alone, one call each")
     ap.add_argument("--no-serial", dest="serial", action="store_false")
@@ -264,6 +268,8 @@ def main():
                   "max_row_sweeps": s0["max_row_sweeps"], "match_maxdist": s0["match_maxdist"],
                   "ncc_max": int(ncc_h.max()), "ncc_min": int(ncc_h.min())},
     }
+    if args.directional > 0:
+        out["directional"] = directional_stage(ctx, grid, ncc, args.directional)
     if args.compare and f.sheet is None:   # a rectangular field is solved in FP64 only
         # the other precision on the same field: throughput, and how far its
         # roots lie from this run's on sampled rows (same sets, any order)
@@ -294,6 +300,54 @@ def main():
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(f, m_steps, args.cpu_rows)
     print(json.dumps(out), flush=True)
+
+
+def directional_stage(ctx, grid, ncc, k_angles, n_bins=200, d_max=20.0):
+    """Moving-source distances (Sec. 5.2, Figs. 5-7) on one N_cc map: for K
+    directions over [0, 180) degrees the distance map and its histogram
+    P(d | angle); at 90 degrees also P(d | N_cc).  Times the kernels with
+    HIP events; algorithmic bytes per pixel and direction: the N_cc map read
+    (4 B), the distance (8 B) and border flag (1 B) written."""
+    import numpy as np
+    import torch
+
+    angles = [np.pi * k / k_angles for k in range(k_angles)]
+    dist = torch.empty((grid.ny, grid.nx), dtype=torch.float64, device=ncc.device)
+    bl = torch.empty((grid.ny, grid.nx), dtype=torch.uint8, device=ncc.device)
+    hist = torch.empty((k_angles, 1, n_bins + 1), dtype=torch.int64, device=ncc.device)
+    ctx.caustic_distances_directional(grid, ncc, angles[0], out=(dist, bl))   # warm-up
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for k, a in enumerate(angles):
+        ctx.caustic_distances_directional(grid, ncc, a, out=(dist, bl))
+        ctx.distance_histogram(dist, bl, n_bins, d_max, out=hist[k])
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    h = hist[:, 0, :].cpu().numpy()
+    w = d_max / n_bins
+
+    def median(row):
+        c = np.cumsum(row)
+        return float((np.searchsorted(c, 0.5 * c[-1]) + 0.5) * w) if c[-1] else None
+    med = [median(r) for r in h]
+    # by N_cc class at 90 degrees
+    ctx.caustic_distances_directional(grid, ncc, np.pi / 2, out=(dist, bl))
+    top = int(ncc.max().item())
+    by_ncc = ctx.distance_histogram(dist, bl, n_bins, d_max, ncc=ncc, ncc_lo=0,
+                                    n_classes=min(top + 1, 8192 // (n_bins + 1))).cpu().numpy()
+    npix = grid.nx * grid.ny
+    return {
+        "angles_deg": [180.0 * a / np.pi for a in angles], "ms_total": ms,
+        "ms_per_direction": ms / k_angles,
+        "pixels_per_s": npix * k_angles / (ms * 1e-3),
+        "algorithmic_gbps": 13.0 * npix * k_angles / (ms * 1e-3) / 1e9,
+        "frac_of_hbm": 13.0 * npix * k_angles / (ms * 1e-3) / 8e12,
+        "median_distance_by_angle": med, "bins": n_bins, "d_max": d_max,
+        "not_border_limited_at_0deg": int(h[0].sum()),
+        "median_distance_by_ncc_at_90deg": [median(r) for r in by_ncc],
+    }
 
 
 def s0_updates(st):
