@@ -343,6 +343,194 @@ __device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0
 // Blocks with at most this many unconverged roots take the cooperative path.
 constexpr int SPARSE_MAX = 16;
 
+// ---------------------------------------------------------------------------
+// Fast multipole star sums (Sec. 4.1: near stars directly, far stars through
+// a local Taylor series)
+// ---------------------------------------------------------------------------
+
+// The stars are binned on a G x G grid of square cells of width w covering
+// [c0 - 2R, c0 + 2R]^2, R the largest star distance from c0.  For a point z
+// in cell C, the stars of C's 3 x 3 neighbourhood are summed directly; every
+// other star is at least 1.5 w from C's centre c while |z - c| <= w / sqrt 2,
+// and its terms come from C's local expansions
+//   f_C(z) = sum_far w_i / (z - z_i) = sum_k a_k (z - c)^k,  a_k = -sum w_i / (z_i - c)^(k+1),
+//   g_C(z) = the same with unit weights,
+// (w_i = m_i, or 1 when all masses are equal and the kernels apply the mass
+// once), whose derivatives give the other sums: sum w/(z - z_i)^2 = -f',
+// sum w/(z - z_i)^3 = f''/2.  The ratio |z - c| / |z_i - c| <= 0.47 bounds the
+// truncation after order p by ~0.47^(p+1) of each term.  Points outside the
+// grid (|z - c0| >= 2R) use one expansion about c0 of all stars,
+// f = sum_k M_k / (z - c0)^(k+1), M_k = sum w_i (z_i - c0)^k.  The polish's
+// bound sum w |u|^4 takes, for the far stars, the per-cell constant
+// sum_far w_i / dist(z_i, cell)^4 (or W / (|z - c0| - R)^4 outside).
+struct FmmArgs {
+    int32_t on, G, p, equal;
+    double x0, y0, w;          // grid origin (lower-left corner) and cell width
+    double cx, cy, R, wsum;    // c0, R, sum of the weights
+    const int32_t *cell_start; // [G*G + 1]: stars of cell q are fstars[cell_start[q] ..)
+    const double4 *fstars;     // stars sorted by cell: (x, y, m, 0)
+    const double2 *cf, *cg;    // [G*G][p + 1]: a_k of f and of g
+    const double *qfar;        // [G*G]
+    const double2 *mf, *mg;    // [p + 1]: M_k about c0, weighted and unit
+};
+
+// Horner's rule for sum_k a_k t^k and its first two derivatives.
+__device__ __forceinline__ void horner2(const double2 *__restrict__ a, int p, double tr, double ti,
+                                        double &fr, double &fi, double &dr, double &di,
+                                        double &er, double &ei)
+{
+    fr = a[p].x; fi = a[p].y;
+    dr = di = er = ei = 0.0;
+    for (int k = p - 1; k >= 0; --k) {
+        // e = e t + 2 d, d = d t + f, f = f t + a_k (e = f'', d = f')
+        const double ner = er * tr - ei * ti + 2.0 * dr, nei = er * ti + ei * tr + 2.0 * di;
+        const double ndr = dr * tr - di * ti + fr, ndi = dr * ti + di * tr + fi;
+        const double nfr = fr * tr - fi * ti + a[k].x, nfi = fr * ti + fi * tr + a[k].y;
+        er = ner; ei = nei; dr = ndr; di = ndi; fr = nfr; fi = nfi;
+    }
+}
+
+__device__ __forceinline__ void horner0(const double2 *__restrict__ a, int p, double tr, double ti,
+                                        double &fr, double &fi)
+{
+    fr = a[p].x; fi = a[p].y;
+    for (int k = p - 1; k >= 0; --k) {
+        const double nfr = fr * tr - fi * ti + a[k].x, nfi = fr * ti + fi * tr + a[k].y;
+        fr = nfr; fi = nfi;
+    }
+}
+
+// Far-field sums at z: f, f', f'' of the weighted expansion, g of the unit
+// one, and the bound on sum_far w |u|^4.  Sets `cell` to the cell index, or
+// -1 outside the grid (then every star is far).
+__device__ __forceinline__ void fmm_far(const FmmArgs &M, double zr, double zi, int &cell,
+                                        double2 &f, double2 &f1, double2 &f2, double2 &g,
+                                        double &q)
+{
+    const double fx = floor((zr - M.x0) / M.w), fy = floor((zi - M.y0) / M.w);
+    if (fx >= 0.0 && fy >= 0.0 && fx < (double)M.G && fy < (double)M.G) {
+        const int ix = (int)fx, iy = (int)fy;
+        cell = iy * M.G + ix;
+        const double tr = zr - (M.x0 + (ix + 0.5) * M.w), ti = zi - (M.y0 + (iy + 0.5) * M.w);
+        const double2 *a = M.cf + (int64_t)cell * (M.p + 1);
+        horner2(a, M.p, tr, ti, f.x, f.y, f1.x, f1.y, f2.x, f2.y);
+        if (M.equal) {
+            g = f;
+        } else {
+            horner0(M.cg + (int64_t)cell * (M.p + 1), M.p, tr, ti, g.x, g.y);
+        }
+        q = M.qfar[cell];
+        return;
+    }
+    cell = -1;
+    // t = 1 / (z - c0); f = t A(t), f' = -t^2 B(t), f'' = t^3 C(t) with
+    // A = sum M_k t^k, B = sum (k+1) M_k t^k, C = sum (k+1)(k+2) M_k t^k
+    const double dx = zr - M.cx, dy = zi - M.cy;
+    const double r2 = dx * dx + dy * dy;
+    const double tr = dx / r2, ti = -dy / r2;
+    double Ar = M.mf[M.p].x, Ai = M.mf[M.p].y;
+    double Br = (M.p + 1) * Ar, Bi = (M.p + 1) * Ai;
+    double Cr = (double)(M.p + 1) * (M.p + 2) * Ar, Ci = (double)(M.p + 1) * (M.p + 2) * Ai;
+    double Gr = M.mg[M.p].x, Gi = M.mg[M.p].y;
+    for (int k = M.p - 1; k >= 0; --k) {
+        const double2 mk = M.mf[k];
+        double nr = Ar * tr - Ai * ti + mk.x, ni = Ar * ti + Ai * tr + mk.y;
+        Ar = nr; Ai = ni;
+        nr = Br * tr - Bi * ti + (k + 1) * mk.x; ni = Br * ti + Bi * tr + (k + 1) * mk.y;
+        Br = nr; Bi = ni;
+        const double c = (double)(k + 1) * (k + 2);
+        nr = Cr * tr - Ci * ti + c * mk.x; ni = Cr * ti + Ci * tr + c * mk.y;
+        Cr = nr; Ci = ni;
+        const double2 gk = M.mg[k];
+        nr = Gr * tr - Gi * ti + gk.x; ni = Gr * ti + Gi * tr + gk.y;
+        Gr = nr; Gi = ni;
+    }
+    const double t2r = tr * tr - ti * ti, t2i = 2.0 * tr * ti;
+    const double t3r = t2r * tr - t2i * ti, t3i = t2r * ti + t2i * tr;
+    f = make_double2(tr * Ar - ti * Ai, tr * Ai + ti * Ar);
+    f1 = make_double2(-(t2r * Br - t2i * Bi), -(t2r * Bi + t2i * Br));
+    f2 = make_double2(t3r * Cr - t3i * Ci, t3r * Ci + t3i * Cr);
+    g = M.equal ? f : make_double2(tr * Gr - ti * Gi, tr * Gi + ti * Gr);
+    const double dd = sqrt(r2) - M.R;
+    q = M.wsum / (dd * dd * dd * dd);
+}
+
+// Local expansions of every cell from its far stars: one work group per
+// cell, lane k accumulating a_k = -sum w_i v_i^(k+1), v_i = 1 / (z_i - c),
+// for both weightings, v^(k+1) by binary powering; lane 0 also the bound
+// sum_far w_i / dist(z_i, cell)^4.
+__global__ void __launch_bounds__(64)
+fmm_p2l(int32_t G, int32_t p, double x0, double y0, double w, int32_t equal,
+        const int32_t *__restrict__ cell_start, const double4 *__restrict__ fstars,
+        double2 *__restrict__ cf, double2 *__restrict__ cg, double *__restrict__ qfar)
+{
+    const int cell = blockIdx.x;
+    const int ix = cell % G, iy = cell / G;
+    const double cx = x0 + (ix + 0.5) * w, cy = y0 + (iy + 0.5) * w;
+    const int k = threadIdx.x;
+    const int e = k + 1;
+    double fr = 0.0, fi = 0.0, gr = 0.0, gi = 0.0, q = 0.0;
+    for (int y = 0; y < G; ++y) {
+        // the row's cells outside [ix-1, ix+1] (all of them when |y - iy| > 1)
+        const bool near_row = y >= iy - 1 && y <= iy + 1;
+        for (int part = 0; part < 2; ++part) {
+            int qa, qb;   // cell range [qa, qb) of the row
+            if (!near_row) {
+                if (part) break;
+                qa = y * G; qb = y * G + G;
+            } else if (part == 0) {
+                qa = y * G; qb = y * G + max(ix - 1, 0);
+            } else {
+                qa = y * G + min(ix + 2, G); qb = y * G + G;
+            }
+            for (int i = cell_start[qa]; i < cell_start[qb]; ++i) {
+                const double4 st = fstars[i];
+                const double dx = st.x - cx, dy = st.y - cy;
+                const double r2 = dx * dx + dy * dy;
+                const double vr = dx / r2, vi = -dy / r2;
+                // v^e by binary powering (e <= 64)
+                double pr = 1.0, pi = 0.0, br = vr, bi = vi;
+                for (int b = 0; b < 7; ++b) {
+                    if ((e >> b) & 1) {
+                        const double t = pr * br - pi * bi;
+                        pi = pr * bi + pi * br;
+                        pr = t;
+                    }
+                    const double t = br * br - bi * bi;
+                    bi = 2.0 * br * bi;
+                    br = t;
+                }
+                const double wi = equal ? 1.0 : st.z;
+                fr -= wi * pr; fi -= wi * pi;
+                gr -= pr; gi -= pi;
+                if (k == 0) {
+                    const double ex = fmax(fabs(dx) - 0.5 * w, 0.0), ey = fmax(fabs(dy) - 0.5 * w, 0.0);
+                    const double d2 = ex * ex + ey * ey;
+                    q += wi / (d2 * d2);
+                }
+            }
+        }
+    }
+    if (k <= p) {
+        cf[(int64_t)cell * (p + 1) + k] = make_double2(fr, fi);
+        cg[(int64_t)cell * (p + 1) + k] = make_double2(gr, gi);
+    }
+    if (k == 0) qfar[cell] = q;
+}
+
+// Calls body(star) for the stars of the 3 x 3 cells around `cell`.
+template <class Body>
+__device__ __forceinline__ void fmm_near(const FmmArgs &M, int cell, Body &&body)
+{
+    if (cell < 0) return;
+    const int ix = cell % M.G, iy = cell / M.G;
+    for (int y = max(iy - 1, 0); y <= min(iy + 1, M.G - 1); ++y) {
+        const int q0 = y * M.G + max(ix - 1, 0), q1 = y * M.G + min(ix + 1, M.G - 1);
+        // the cells of one grid row are adjacent in the sorted order
+        for (int i = M.cell_start[q0]; i < M.cell_start[q1 + 1]; ++i) body(M.fstars[i]);
+    }
+}
+
 // Arguments shared by the kernels of a round.  Stars of every realisation
 // are concatenated; each front names its realisation, and the grid maps a
 // block to (front, block within the front) through bmap.
@@ -367,6 +555,7 @@ template <class T> struct RoundArgs {
     int32_t persistent; // the persistent scheduler: iterates by per-front parity
     double2 *iter0, *iter1;
     const double *sheet; // rectangular fields' sheet records (Real::sheet_off)
+    FmmArgs fmm;         // fast multipole star sums (fmm.on = 0: direct sums)
 };
 
 // What one block knows about its front and star field.
@@ -575,8 +764,24 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
     } else {
         Sums S;
         zero(S);
-        stream_tiles(stars, n_stars, reinterpret_cast<T *>(tiles),
-                     [&](int, const T &s) { add_star<EQUAL>(S, zr, zi, s); });
+        if (A.fmm.on) {
+            int cell;
+            double2 f, f1, f2, g;
+            double q;
+            fmm_far(A.fmm, zr, zi, cell, f, f1, f2, g, q);
+            fmm_near(A.fmm, cell, [&](const double4 &s4) {
+                if constexpr (EQUAL) add_star<EQUAL>(S, zr, zi, make_double2(s4.x, s4.y));
+                else add_star<EQUAL>(S, zr, zi, s4);
+            });
+            // far terms in the accumulators' conventions (s2i holds -Im/2)
+            S.s1r += g.x; S.s1i += g.y;
+            if (!EQUAL) { S.s0r += f.x; S.s0i += f.y; }
+            S.s2r -= f1.x; S.s2i += 0.5 * f1.y;
+            S.s3r += 0.5 * f2.x; S.s3i += 0.5 * f2.y;
+        } else {
+            stream_tiles(stars, n_stars, reinterpret_cast<T *>(tiles),
+                         [&](int, const T &s) { add_star<EQUAL>(S, zr, zi, s); });
+        }
         if (!fast_roots_pass(A.fronts[B.f])) {
             double2 *rtiles = reinterpret_cast<double2 *>(tiles);
             auto other = [&](int, const double2 &o) { add_root(S, zr, zi, o); };
@@ -919,8 +1124,23 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
     } else if (n_act > 0) {
         PSums S;
         zero(S);
-        stream_tiles(stars, n_stars, reinterpret_cast<T *>(tiles),
-                     [&](int, const T &s) { add_star_polish<EQUAL>(S, zr, zi, s); });
+        if (A.fmm.on) {
+            int cell;
+            double2 f, f1, f2, g;
+            double q;
+            fmm_far(A.fmm, zr, zi, cell, f, f1, f2, g, q);
+            fmm_near(A.fmm, cell, [&](const double4 &s4) {
+                if constexpr (EQUAL) add_star_polish<EQUAL>(S, zr, zi, make_double2(s4.x, s4.y));
+                else add_star_polish<EQUAL>(S, zr, zi, s4);
+            });
+            S.s0r += f.x; S.s0i += f.y;
+            S.s2r -= f1.x; S.s2i += 0.5 * f1.y;
+            S.s3r += 0.5 * f2.x; S.s3i += 0.5 * f2.y;
+            S.q += q;
+        } else {
+            stream_tiles(stars, n_stars, reinterpret_cast<T *>(tiles),
+                         [&](int, const T &s) { add_star_polish<EQUAL>(S, zr, zi, s); });
+        }
         const Update u = polish_finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k);
         if (act) {
             nxt[base_f + k] = make_double2(u.zr, u.zi);
@@ -1600,6 +1820,92 @@ static int autotune_subchains(const std::vector<RealHost> &reals, int64_t m, boo
 // Host driver
 // ---------------------------------------------------------------------------
 
+// Builds the fast-multipole grid of the (single) field: stars binned and
+// sorted by cell, the expansions about the field centre on the host, the
+// cells' local expansions on the device.
+static mlcc_status build_fmm(Ctx *c, int order, FmmArgs &M)
+{
+    const std::vector<double4> &st = c->hstars;
+    const int64_t n = (int64_t)st.size();
+    const bool equal = c->equal_mass;
+    double xmin = st[0].x, xmax = st[0].x, ymin = st[0].y, ymax = st[0].y;
+    for (const double4 &a : st) {
+        xmin = std::min(xmin, a.x); xmax = std::max(xmax, a.x);
+        ymin = std::min(ymin, a.y); ymax = std::max(ymax, a.y);
+    }
+    const double cx = 0.5 * (xmin + xmax), cy = 0.5 * (ymin + ymax);
+    double R = 0.0, wsum = 0.0;
+    for (const double4 &a : st) {
+        R = std::max(R, std::hypot(a.x - cx, a.y - cy));
+        wsum += equal ? 1.0 : a.z;
+    }
+    if (!(R > 0.0)) R = 1.0;
+    R *= 1.0 + 1e-12;   // every star strictly inside the radius
+    const int G = (int)std::min<double>(256.0, std::max(4.0, std::round(std::sqrt(1.7 * (double)n))));
+    const int pp = order > 0 ? order : 48;
+    const double w = 4.0 * R / G, x0 = cx - 2.0 * R, y0 = cy - 2.0 * R;
+    // counting sort by cell
+    std::vector<int32_t> cell_of(n), start((size_t)G * G + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int ix = std::min(G - 1, std::max(0, (int)std::floor((st[i].x - x0) / w)));
+        const int iy = std::min(G - 1, std::max(0, (int)std::floor((st[i].y - y0) / w)));
+        cell_of[i] = iy * G + ix;
+        start[cell_of[i] + 1] += 1;
+    }
+    for (int q = 0; q < G * G; ++q) start[q + 1] += start[q];
+    std::vector<double4> sorted(n);
+    {
+        std::vector<int32_t> fill(start.begin(), start.end() - 1);
+        for (int64_t i = 0; i < n; ++i) sorted[fill[cell_of[i]]++] = st[i];
+    }
+    // expansions about the centre: M_k = sum w_i (z_i - c0)^k, and unit weights
+    std::vector<double2> mm(2 * (pp + 1), make_double2(0.0, 0.0));
+    for (const double4 &a : st) {
+        const double dx = a.x - cx, dy = a.y - cy, wi = equal ? 1.0 : a.z;
+        double pr = 1.0, pi = 0.0;
+        for (int k = 0; k <= pp; ++k) {
+            mm[k].x += wi * pr; mm[k].y += wi * pi;
+            mm[pp + 1 + k].x += pr; mm[pp + 1 + k].y += pi;
+            const double t = pr * dx - pi * dy;
+            pi = pr * dy + pi * dx;
+            pr = t;
+        }
+    }
+    const size_t ncell = (size_t)G * G;
+    MLCC_TRY(c->fmm_cs.reserve(start.size() * sizeof(int32_t)));
+    MLCC_TRY(c->fmm_st.reserve(std::max<int64_t>(n, 1) * sizeof(double4)));
+    MLCC_TRY(c->fmm_cf.reserve(ncell * (pp + 1) * sizeof(double2)));
+    MLCC_TRY(c->fmm_cg.reserve(ncell * (pp + 1) * sizeof(double2)));
+    MLCC_TRY(c->fmm_q.reserve(ncell * sizeof(double)));
+    MLCC_TRY(c->fmm_m.reserve(mm.size() * sizeof(double2)));
+    MLCC_HIP(hipMemcpyAsync(c->fmm_cs.p, start.data(), start.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, c->stream));
+    MLCC_HIP(hipMemcpyAsync(c->fmm_st.p, sorted.data(), n * sizeof(double4), hipMemcpyHostToDevice,
+                            c->stream));
+    MLCC_HIP(hipMemcpyAsync(c->fmm_m.p, mm.data(), mm.size() * sizeof(double2),
+                            hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(fmm_p2l, dim3((unsigned)ncell), dim3(64), 0, c->stream, G, pp, x0, y0, w,
+                       (int32_t)equal, c->fmm_cs.as<int32_t>(), c->fmm_st.as<double4>(),
+                       c->fmm_cf.as<double2>(), c->fmm_cg.as<double2>(), c->fmm_q.as<double>());
+    MLCC_HIP(hipGetLastError());
+    // host vectors must outlive the copies
+    MLCC_HIP(hipStreamSynchronize(c->stream));
+    M.on = 1;
+    M.G = G;
+    M.p = pp;
+    M.equal = equal;
+    M.x0 = x0; M.y0 = y0; M.w = w;
+    M.cx = cx; M.cy = cy; M.R = R; M.wsum = wsum;
+    M.cell_start = c->fmm_cs.as<int32_t>();
+    M.fstars = c->fmm_st.as<double4>();
+    M.cf = c->fmm_cf.as<double2>();
+    M.cg = c->fmm_cg.as<double2>();
+    M.qfar = c->fmm_q.as<double>();
+    M.mf = c->fmm_m.as<double2>();
+    M.mg = c->fmm_m.as<double2>() + (pp + 1);
+    return MLCC_OK;
+}
+
 mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *roots_re,
                                       double *roots_im, double *caus_re, double *caus_im,
                                       int32_t *chain_next, mlcc_cc_stats *stats)
@@ -1748,6 +2054,8 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     if (mixed) MLCC_TRY(c->errbuf.reserve((size_t)it_total * sizeof(double)));
     MLCC_TRY(c->reals_d.reserve((size_t)n_real * sizeof(Real)));
     MLCC_TRY(c->sheet.reserve(std::max<size_t>(1, sheet_host.size()) * sizeof(double)));
+    FmmArgs fmm{};
+    if (p->star_sums == MLCC_STARS_FMM) MLCC_TRY(build_fmm(c, p->fmm_order, fmm));
     MLCC_TRY(c->bmap.reserve((size_t)ngrid * sizeof(int2)));
     MLCC_TRY(c->workflags.reserve(2 * MAX_BATCH * sizeof(int32_t)));
     MLCC_TRY(ensure_pinned(c, 2 * (sizeof(Control) + MAX_BATCH * sizeof(int32_t))));
@@ -1822,6 +2130,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         A.predictor = p->predictor;
         A.errbuf = mixed ? c->errbuf.as<double>() : nullptr;
         A.sheet = c->sheet.as<double>();
+        A.fmm = fmm;
     };
     const dim3 grid((unsigned)ngrid);
     auto launch_kind = [&](int kind, const double2 *cur, double2 *nxt) {

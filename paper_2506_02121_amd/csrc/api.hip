@@ -183,7 +183,7 @@ void mlcc_destroy(mlcc_ctx *ctx)
                       &c.flagrow, &c.fronts, &c.counts, &c.control, &c.etab, &c.bnd, &c.perm,
                       &c.match_aux, &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.vsum,
                       &c.pq, &c.passupd, &c.reals_d, &c.bmap, &c.diff, &c.err, &c.edt_col,
-                      &c.dmask};
+                      &c.dmask, &c.fmm_cs, &c.fmm_st, &c.fmm_cf, &c.fmm_cg, &c.fmm_q, &c.fmm_m};
     for (DevBuf *b : bufs) b->release();
     if (c.own_stream) (void)hipStreamDestroy(c.own_stream);
     if (c.pinned) (void)hipHostFree(c.pinned);
@@ -309,6 +309,8 @@ static mlcc_status load_fields(Ctx &c, int32_t n_fields, const int64_t *off, con
         xym[4 * i + 2] = hm[i];
         xym[4 * i + 3] = 0.0;
     }
+    c.hstars.resize(n);
+    for (int64_t i = 0; i < n; ++i) c.hstars[i] = make_double4(hx[i], hy[i], hm[i], 0.0);
     MLCC_TRY(c.stars4.reserve(4 * n * sizeof(double)));
     MLCC_TRY(c.stars.reserve(2 * n * sizeof(double)));
     MLCC_TRY(c.mass.reserve(n * sizeof(double)));
@@ -468,6 +470,12 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
         return fail(MLCC_ERR_INVALID, "watchdog_ms=%d outside [0, 600000]", p.watchdog_ms);
     if (c.rect && p.precision != MLCC_FP64)
         return fail(MLCC_ERR_INVALID, "a rectangular field is solved in MLCC_FP64 only");
+    if (p.star_sums != MLCC_STARS_DIRECT && p.star_sums != MLCC_STARS_FMM)
+        return fail(MLCC_ERR_INVALID, "unknown star_sums %d", p.star_sums);
+    if (p.star_sums == MLCC_STARS_FMM && c.batched)
+        return fail(MLCC_ERR_INVALID, "MLCC_STARS_FMM takes one field per call");
+    if (p.fmm_order != 0 && (p.fmm_order < 8 || p.fmm_order > 63))
+        return fail(MLCC_ERR_INVALID, "fmm_order must be 0 or 8..63 (got %d)", p.fmm_order);
     MLCC_TRY(check_device_ptr(&c, roots_re, "roots_re"));
     MLCC_TRY(check_device_ptr(&c, roots_im, "roots_im"));
     if ((caustics_re == nullptr) != (caustics_im == nullptr))

@@ -192,6 +192,10 @@ struct Ctx {
     DevBuf err;       // int32 error flag
     DevBuf edt_col;   // int32 column distances
     DevBuf dmask;     // uint8 caustic-pixel mask (moving-source distances)
+    // fast multipole star sums: the stars sorted by grid cell and each cell's
+    // expansions (built by the root finder when asked for)
+    std::vector<double4> hstars;   // host copy of the stars (x, y, m, 0)
+    DevBuf fmm_cs, fmm_st, fmm_cf, fmm_cg, fmm_q, fmm_m;
 
     void *pinned = nullptr; // host-pinned readback area
     size_t pinned_bytes = 0;

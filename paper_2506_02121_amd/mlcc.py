@@ -47,7 +47,8 @@ class CCParams(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("tol_step", ctypes.c_double),
                 ("tol_inv_mu", ctypes.c_double), ("timing", ctypes.c_int32),
                 ("predictor", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("watchdog_ms", ctypes.c_int32)]
+                ("watchdog_ms", ctypes.c_int32), ("star_sums", ctypes.c_int32),
+                ("fmm_order", ctypes.c_int32)]
 
 
 class CCStats(ctypes.Structure):
@@ -264,7 +265,8 @@ class Context:
                              chain_next: bool = True, caustics: bool = False, out=None,
                              caustics_out=None, raise_on_error: bool = True,
                              precision: str = "fp64", predictor: int = 2,
-                             schedule: str = "persistent", watchdog_ms: int = 0):
+                             schedule: str = "persistent", watchdog_ms: int = 0,
+                             star_sums: str = "direct", fmm_order: int = 0):
         """Returns (roots_re, roots_im, chain_next, stats, status), or with
         caustics=True (roots_re, roots_im, caus_re, caus_im, chain_next, stats,
         status).  One field: arrays are (m_steps + 1, n_r) float64 device
@@ -281,6 +283,8 @@ class Context:
         p.predictor = int(predictor)
         p.schedule = {"rounds": 0, "persistent": 1}[schedule]
         p.watchdog_ms = int(watchdog_ms)
+        p.star_sums = {"direct": 0, "fmm": 1}[star_sums]
+        p.fmm_order = int(fmm_order)
         n_r = self.num_roots()
         shape = (m_steps + 1, n_r) if self.star_offsets is None else ((m_steps + 1) * n_r,)
         if out is None:
