@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--compare", dest="compare", action="store_true", default=True,
                     help="also run the other precision (mixed vs FP64) on the same field")
     ap.add_argument("--no-compare", dest="compare", action="store_false")
+    ap.add_argument("--star-sums", dest="star_sums", default="direct", choices=["direct", "fmm"],
+                    help="star sums of the FP64 sweeps and the polish: direct, or fast multipole "
+                         "(one field per call)")
     ap.add_argument("--directional", type=int, default=0, metavar="K",
                     help="after the timed steps, moving-source distance maps of the last step's "
                          "N_cc map for K directions over [0, 180) degrees, with their histograms "
@@ -158,7 +161,7 @@ def main():
         _, _, _, _, cn, st, _ = ctx.find_critical_curves(
             m_steps, n_subchains=args.subchains, timing=True, caustics=True,
             out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=prec,
-            predictor=args.predictor, schedule=args.schedule)
+            predictor=args.predictor, schedule=args.schedule, star_sums=args.star_sums)
         ev[1].record()
         ctx.caustic_crossings(w_re, w_im, cn, grid, out=ncc)
         ev[2].record()
@@ -241,7 +244,8 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "n_stars": n, "roots_per_row": n_r, "phase_steps": m_steps,
                    "grid": [grid.nx, grid.ny], "precision": precision,
-                   "predictor": args.predictor, "schedule": args.schedule, "seed": args.seed},
+                   "predictor": args.predictor, "schedule": args.schedule,
+                   "star_sums": args.star_sums, "seed": args.seed},
         "roofline": {
             "bound": "alu",
             "kernel": dominant["kernel"],
@@ -268,6 +272,11 @@ def main():
                   "max_row_sweeps": s0["max_row_sweeps"], "match_maxdist": s0["match_maxdist"],
                   "ncc_max": int(ncc_h.max()), "ncc_min": int(ncc_h.min())},
     }
+    if args.star_sums == "fmm":
+        # the algorithmic count assumes every star term summed directly
+        out["roofline"].update({"achieved": None, "frac": None, "traffic": None,
+                                "note": "fast-multipole star sums: the direct-sum FLOP count "
+                                        "does not apply; see ms_per_step and value"})
     if args.directional > 0:
         out["directional"] = directional_stage(ctx, grid, ncc, args.directional)
     if args.compare and f.sheet is None:   # a rectangular field is solved in FP64 only
