@@ -273,10 +273,14 @@ def main():
                   "ncc_max": int(ncc_h.max()), "ncc_min": int(ncc_h.min())},
     }
     if args.star_sums == "fmm":
-        # the algorithmic count assumes every star term summed directly
-        out["roofline"].update({"achieved": None, "frac": None, "traffic": None,
-                                "note": "fast-multipole star sums: the direct-sum FLOP count "
-                                        "does not apply; see ms_per_step and value"})
+        # the library counts the multipole form's own work: near star terms
+        # plus one series evaluation per update; the traffic counters were
+        # taken with direct sums
+        out["roofline"].update({"traffic": None,
+                                "note": "fast-multipole star sums: FLOP = 29 per near star term "
+                                        "+ (26 p + 20) per series evaluation + root terms"})
+        out["stats"].update({"fmm_near_terms_per_step": s0["fmm_near_terms"],
+                             "fmm_far_evals_per_step": s0["fmm_far_evals"]})
     if args.directional > 0:
         out["directional"] = directional_stage(ctx, grid, ncc, args.directional)
     if args.compare and f.sheet is None:   # a rectangular field is solved in FP64 only

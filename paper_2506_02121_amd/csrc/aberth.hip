@@ -401,11 +401,12 @@ __device__ __forceinline__ void horner0(const double2 *__restrict__ a, int p, do
 }
 
 // Far-field sums at z: f, f', f'' of the weighted expansion, g of the unit
-// one, and the bound on sum_far w |u|^4.  Sets `cell` to the cell index, or
-// -1 outside the grid (then every star is far).
+// one (when want_g; the polish does not use it), and the bound on
+// sum_far w |u|^4.  Sets `cell` to the cell index, or -1 outside the grid
+// (then every star is far).
 __device__ __forceinline__ void fmm_far(const FmmArgs &M, double zr, double zi, int &cell,
                                         double2 &f, double2 &f1, double2 &f2, double2 &g,
-                                        double &q)
+                                        double &q, bool want_g)
 {
     const double fx = floor((zr - M.x0) / M.w), fy = floor((zi - M.y0) / M.w);
     if (fx >= 0.0 && fy >= 0.0 && fx < (double)M.G && fy < (double)M.G) {
@@ -416,8 +417,10 @@ __device__ __forceinline__ void fmm_far(const FmmArgs &M, double zr, double zi, 
         horner2(a, M.p, tr, ti, f.x, f.y, f1.x, f1.y, f2.x, f2.y);
         if (M.equal) {
             g = f;
-        } else {
+        } else if (want_g) {
             horner0(M.cg + (int64_t)cell * (M.p + 1), M.p, tr, ti, g.x, g.y);
+        } else {
+            g = make_double2(0.0, 0.0);
         }
         q = M.qfar[cell];
         return;
@@ -518,16 +521,36 @@ fmm_p2l(int32_t G, int32_t p, double x0, double y0, double w, int32_t equal,
     if (k == 0) qfar[cell] = q;
 }
 
-// Calls body(star) for the stars of the 3 x 3 cells around `cell`.
+// Calls body(star) for the stars of the 3 x 3 cells around `cell`; returns
+// their number.
 template <class Body>
-__device__ __forceinline__ void fmm_near(const FmmArgs &M, int cell, Body &&body)
+__device__ __forceinline__ int fmm_near(const FmmArgs &M, int cell, Body &&body)
 {
-    if (cell < 0) return;
+    if (cell < 0) return 0;
     const int ix = cell % M.G, iy = cell / M.G;
+    int n = 0;
     for (int y = max(iy - 1, 0); y <= min(iy + 1, M.G - 1); ++y) {
         const int q0 = y * M.G + max(ix - 1, 0), q1 = y * M.G + min(ix + 1, M.G - 1);
         // the cells of one grid row are adjacent in the sorted order
-        for (int i = M.cell_start[q0]; i < M.cell_start[q1 + 1]; ++i) body(M.fstars[i]);
+        const int i0 = M.cell_start[q0], i1 = M.cell_start[q1 + 1];
+        n += i1 - i0;
+        for (int i = i0; i < i1; ++i) body(M.fstars[i]);
+    }
+    return n;
+}
+
+// Adds a wave's near-field star terms and far-field evaluations (lanes that
+// updated a root) to the totals behind the algorithmic FLOP count.
+__device__ __forceinline__ void fmm_count(unsigned long long *near, unsigned long long *far,
+                                          bool act, int n_near)
+{
+    int v = act ? n_near : 0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int n_act = __popcll(__ballot(act));
+    if ((threadIdx.x & 63) == 0 && n_act) {
+        atomicAdd(near, (unsigned long long)v);
+        atomicAdd(far, (unsigned long long)n_act);
     }
 }
 
@@ -768,11 +791,12 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
             int cell;
             double2 f, f1, f2, g;
             double q;
-            fmm_far(A.fmm, zr, zi, cell, f, f1, f2, g, q);
-            fmm_near(A.fmm, cell, [&](const double4 &s4) {
+            fmm_far(A.fmm, zr, zi, cell, f, f1, f2, g, q, true);
+            const int n_near = fmm_near(A.fmm, cell, [&](const double4 &s4) {
                 if constexpr (EQUAL) add_star<EQUAL>(S, zr, zi, make_double2(s4.x, s4.y));
                 else add_star<EQUAL>(S, zr, zi, s4);
             });
+            fmm_count(&A.ctl->fmm_near, &A.ctl->fmm_far, act, n_near);
             // far terms in the accumulators' conventions (s2i holds -Im/2)
             S.s1r += g.x; S.s1i += g.y;
             if (!EQUAL) { S.s0r += f.x; S.s0i += f.y; }
@@ -1128,11 +1152,12 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
             int cell;
             double2 f, f1, f2, g;
             double q;
-            fmm_far(A.fmm, zr, zi, cell, f, f1, f2, g, q);
-            fmm_near(A.fmm, cell, [&](const double4 &s4) {
+            fmm_far(A.fmm, zr, zi, cell, f, f1, f2, g, q, false);
+            const int n_near = fmm_near(A.fmm, cell, [&](const double4 &s4) {
                 if constexpr (EQUAL) add_star_polish<EQUAL>(S, zr, zi, make_double2(s4.x, s4.y));
                 else add_star_polish<EQUAL>(S, zr, zi, s4);
             });
+            fmm_count(&A.ctl->fmm_near_polish, &A.ctl->fmm_far_polish, act, n_near);
             S.s0r += f.x; S.s0i += f.y;
             S.s2r -= f1.x; S.s2i += 0.5 * f1.y;
             S.s3r += 0.5 * f2.x; S.s3i += 0.5 * f2.y;
@@ -2545,7 +2570,26 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         // update (star terms only); the device counts updates and
         // updates x N, which gives the sums over mixed field sizes
         // star terms in FP64; root terms in FP64 except in fast-root passes
-        stats->algorithmic_flop = 29.0 * (double)h.star_updates +
+        // With fast-multipole star sums (one field), an update that took
+        // them has its near stars' terms at 29 FLOP each and one evaluation
+        // of the cell's series of order p in place of the other N - near
+        // terms: Horner's rule for f, f' and f'' together takes 26 FLOP per
+        // order (the unit-weight series of unequal masses 8 more in the
+        // sweeps), plus ~20 for the cell and the sums.  The outside-grid
+        // expansion, rarely taken, is counted the same.
+        double star64 = (double)h.star_updates, starpol = (double)h.star_updates_polish;
+        double far64 = 0.0, farpol = 0.0;
+        if (fmm.on) {
+            const double nf = (double)c->n;
+            const double pf = (double)fmm.p;
+            far64 = (double)h.fmm_far * (26.0 * pf + 20.0 + (fmm.equal ? 0.0 : 8.0 * pf));
+            farpol = (double)h.fmm_far_polish * (26.0 * pf + 20.0);
+            star64 += (double)h.fmm_near - nf * (double)h.fmm_far;
+            starpol += (double)h.fmm_near_polish - nf * (double)h.fmm_far_polish;
+            stats->fmm_near_terms = (int64_t)(h.fmm_near + h.fmm_near_polish);
+            stats->fmm_far_evals = (int64_t)(h.fmm_far + h.fmm_far_polish);
+        }
+        stats->algorithmic_flop = 29.0 * star64 + far64 +
                                   20.0 * (double)(h.star_updates - h.star_updates_fast) -
                                   10.0 * (double)(h.updates - h.updates_fast);
         stats->algorithmic_flop_sweep_roots =
@@ -2557,7 +2601,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         }
         stats->algorithmic_flop_f32 =
             49.0 * (double)h.star_updates_f32 - 10.0 * (double)h.updates_f32;
-        stats->algorithmic_flop_polish = 29.0 * (double)h.star_updates_polish;
+        stats->algorithmic_flop_polish = 29.0 * starpol + farpol;
     }
     return result;
 }

@@ -145,6 +145,10 @@ struct Control {
     unsigned long long star_updates_polish;
     unsigned long long updates_fast;      // FP64 Aberth updates of warm FP64-mode rows, whose
     unsigned long long star_updates_fast; // root-root terms run in FP32 (and their star counts)
+    // fast-multipole star sums: near-field star terms and far-field series
+    // evaluations of the updates that took them (FP64 sweeps; polish)
+    unsigned long long fmm_near, fmm_far;
+    unsigned long long fmm_near_polish, fmm_far_polish;
 };
 
 struct Ctx {

@@ -117,12 +117,21 @@ def test_fmm_close_to_direct(ctx):
     say("fmm vs direct")
     f = fields.random_field(55, 500, kappa_star=0.4, kappa_s=0.0, gamma=0.4, masses="salpeter")
     load(ctx, f)
-    out = {}
+    out, sts = {}, {}
     for ss in ("direct", "fmm"):
         rr, ri, cr, ci, cn, st, code = ctx.find_critical_curves(200, n_subchains=5, caustics=True,
                                                                 star_sums=ss)
         torch.cuda.synchronize()
         out[ss] = (host_c(rr, ri), host_c(cr, ci))
+        sts[ss] = st
+    # the work counts behind the algorithmic FLOP: no series without them;
+    # with them every dense update evaluates one, next to a few near stars
+    assert sts["direct"]["fmm_far_evals"] == 0 and sts["direct"]["fmm_near_terms"] == 0
+    far, near = sts["fmm"]["fmm_far_evals"], sts["fmm"]["fmm_near_terms"]
+    assert 0 < far <= sts["fmm"]["root_updates"]
+    assert 0 < near < 0.5 * f.n * far
+    assert sts["fmm"]["algorithmic_flop"] < sts["direct"]["algorithmic_flop"]
+    print(f"[fmm counts] {far} series evaluations, {near / far:.1f} near stars each", flush=True)
     perm, _ = parity.pair(out["direct"][0][0], out["fmm"][0][0])
     dr = float(np.max(np.abs(out["fmm"][0][:, perm] - out["direct"][0])))
     dw = float(np.max(np.abs(out["fmm"][1][:, perm] - out["direct"][1])))

@@ -1,6 +1,7 @@
 """Parity at the full workload sizes, in the launch configuration the
 benchmark times (library-chosen subchains, fused caustics, per-launch event
-timing).  The oracle cannot redo whole runs of this size, so it checks
+timing), with direct and with fast-multipole star sums (Sec. 4.1).  The
+oracle, which always sums every star directly, cannot redo whole runs of this size, so it checks
 sampled rows (cold-started on their own), a window of subchain 0 grown
 centre-out as the GPU grows it (the same columns once the two centre
 rows are paired), and properties that
@@ -95,19 +96,23 @@ def subchain0_window(st, m_steps, half):
 
 
 FULL = [
-    # workload, sampled rows, half-width of the subchain-0 window, sampled pixels
-    ("n1k", 6, 40, 24),
-    ("n10k", 2, 4, 8),
-    ("n10k_mixed", 2, 4, 0),
+    # workload, sampled rows, half-width of the subchain-0 window, sampled pixels, star sums
+    ("n1k", 6, 40, 24, "direct"),
+    ("n10k", 2, 4, 8, "direct"),
+    ("n10k_mixed", 2, 4, 0, "direct"),
+    ("n10k", 2, 4, 8, "fmm"),
+    ("n10k_mixed", 2, 4, 0, "fmm"),
 ]
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("case", FULL, ids=[c[0] for c in FULL])
+@pytest.mark.parametrize("case", FULL, ids=[c[0] + ("_fmm" if c[4] == "fmm" else "")
+                                            for c in FULL])
 def test_full_size_single_field(mlcc, case):
-    name, n_rows, half, n_pix = case
+    wl_name, n_rows, half, n_pix, star_sums = case
+    name = wl_name + ("_fmm" if star_sums == "fmm" else "")
     say("full size", name)
-    wl = fields.workload(name)
+    wl = fields.workload(wl_name)
     f, m_steps = wl.field, wl.m_steps
     n_r = 2 * f.n
     ctx = mlcc.Context(0)
@@ -116,7 +121,7 @@ def test_full_size_single_field(mlcc, case):
         ctx.set_lenses(torch.as_tensor(f.x, device=dev), torch.as_tensor(f.y, device=dev),
                        torch.as_tensor(f.m, device=dev), f.kappa_s, f.gamma)
         rr, ri, cr, ci, cn, st, code = ctx.find_critical_curves(
-            m_steps, timing=True, caustics=True, precision=wl.precision)
+            m_steps, timing=True, caustics=True, precision=wl.precision, star_sums=star_sums)
         torch.cuda.synchronize()
         print("[stats]", {k: st[k] for k in ("n_subchains", "sweeps", "root_updates",
                                              "root_updates_f32", "rows_fallback",
@@ -148,7 +153,7 @@ def test_full_size_single_field(mlcc, case):
         # the GPU's; from there the warm-started rows must follow the same
         # columns
         lo, c, hi = subchain0_window(st, m_steps, half)
-        if name == "n1k":
+        if wl_name == "n1k":
             # grow the oracle's window on through the first boundary row, where
             # the GPU's columns continue only through the relabelling
             hi = m_steps // st["n_subchains"] + half
