@@ -241,12 +241,14 @@ typedef struct {
     double algorithmic_flop_sweep_roots; /* FP64 sweeps, FP32 part: 10 (2N - 1) per update of
                                 a warm MLCC_FP64 row (its root-root terms run in FP32) */
     int64_t fmm_near_terms;  /* MLCC_STARS_FMM: star terms summed directly in the updates that
-                                took the multipole sums (the 3 x 3 near cells), FP64 sweeps and
-                                polish; 0 otherwise */
+                                took the multipole sums (the 3 x 3 near cells), all pass kinds;
+                                0 otherwise */
     int64_t fmm_far_evals;   /* MLCC_STARS_FMM: those updates (one evaluation of a cell's series
                                 each); the algorithmic FLOP fields above count such an update as
                                 29 per near star term plus 26 p + 20 for the series of order p
-                                (8 p more in sweeps of unequal masses) */
+                                (8 p more in sweeps of unequal masses).  FP32 sweeps take these
+                                sums in FP64: their star part counts in algorithmic_flop, their
+                                root terms stay in algorithmic_flop_f32 */
 } mlcc_cc_stats;
 
 /*

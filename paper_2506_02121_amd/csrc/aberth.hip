@@ -343,6 +343,9 @@ __device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0
 // Blocks with at most this many unconverged roots take the cooperative path.
 constexpr int SPARSE_MAX = 16;
 
+// Newton steps a root may take within one polish pass with multipole sums.
+constexpr int FMM_POLISH_STEPS = 3;
+
 // ---------------------------------------------------------------------------
 // Fast multipole star sums (Sec. 4.1: near stars directly, far stars through
 // a local Taylor series)
@@ -358,45 +361,75 @@ constexpr int SPARSE_MAX = 16;
 // (w_i = m_i, or 1 when all masses are equal and the kernels apply the mass
 // once), whose derivatives give the other sums: sum w/(z - z_i)^2 = -f',
 // sum w/(z - z_i)^3 = f''/2.  The ratio |z - c| / |z_i - c| <= 0.47 bounds the
-// truncation after order p by ~0.47^(p+1) of each term.  Points outside the
+// truncation after order p by ~0.47^(p+1) of each term.  The coefficients
+// are stored scaled, b_k = a_k w^k = -(1/w) sum w_i v_i^(k+1) with
+// v_i = w / (z_i - c), |v_i| <= 2/3, and the series is evaluated in
+// tau = (z - c) / w, |tau| <= 0.71, so no power over- or underflows whatever
+// the field's scale; f' and f'' take 1/w and 1/w^2.  Points outside the
 // grid (|z - c0| >= 2R) use one expansion about c0 of all stars,
 // f = sum_k M_k / (z - c0)^(k+1), M_k = sum w_i (z_i - c0)^k.  The polish's
 // bound sum w |u|^4 takes, for the far stars, the per-cell constant
 // sum_far w_i / dist(z_i, cell)^4 (or W / (|z - c0| - R)^4 outside).
 struct FmmArgs {
     int32_t on, G, p, equal;
-    double x0, y0, w;          // grid origin (lower-left corner) and cell width
+    int32_t stride;            // coefficients per cell: p + 1 rounded up to a multiple of 8
+    double x0, y0, w, inv_w;   // grid origin (lower-left corner), cell width, 1 / w
     double cx, cy, R, wsum;    // c0, R, sum of the weights
     const int32_t *cell_start; // [G*G + 1]: stars of cell q are fstars[cell_start[q] ..)
     const double4 *fstars;     // stars sorted by cell: (x, y, m, 0)
-    const double2 *cf, *cg;    // [G*G][p + 1]: a_k of f and of g
+    const double2 *cf, *cg;    // [G*G][stride]: b_k of f and of g (zero for k > p)
     const double *qfar;        // [G*G]
     const double2 *mf, *mg;    // [p + 1]: M_k about c0, weighted and unit
 };
 
-// Horner's rule for sum_k a_k t^k and its first two derivatives.
-__device__ __forceinline__ void horner2(const double2 *__restrict__ a, int p, double tr, double ti,
-                                        double &fr, double &fi, double &dr, double &di,
+// Horner's rule for sum_k a_k t^k and its first two derivatives, over a
+// coefficient row padded with zeros to a multiple of 8 (leading zeros leave
+// the result unchanged).  Eight coefficients are loaded at a time, so the
+// loads of a chunk are in flight together: the rows live in L2 or beyond,
+// and one load per step would wait out that latency p times.
+__device__ __forceinline__ void horner2(const double2 *__restrict__ a, int stride, double tr,
+                                        double ti, double &fr, double &fi, double &dr, double &di,
                                         double &er, double &ei)
 {
-    fr = a[p].x; fi = a[p].y;
-    dr = di = er = ei = 0.0;
-    for (int k = p - 1; k >= 0; --k) {
-        // e = e t + 2 d, d = d t + f, f = f t + a_k (e = f'', d = f')
-        const double ner = er * tr - ei * ti + 2.0 * dr, nei = er * ti + ei * tr + 2.0 * di;
-        const double ndr = dr * tr - di * ti + fr, ndi = dr * ti + di * tr + fi;
-        const double nfr = fr * tr - fi * ti + a[k].x, nfi = fr * ti + fi * tr + a[k].y;
-        er = ner; ei = nei; dr = ndr; di = ndi; fr = nfr; fi = nfi;
+    fr = fi = dr = di = er = ei = 0.0;
+    for (int c = stride - 8; c >= 0; c -= 8) {
+        const double4 *a4 = reinterpret_cast<const double4 *>(a + c);
+        double2 q[8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double4 v = a4[j];
+            q[2 * j] = make_double2(v.x, v.y);
+            q[2 * j + 1] = make_double2(v.z, v.w);
+        }
+#pragma unroll
+        for (int j = 7; j >= 0; --j) {
+            // e = e t + 2 d, d = d t + f, f = f t + a_k (e = f'', d = f')
+            const double ner = er * tr - ei * ti + 2.0 * dr, nei = er * ti + ei * tr + 2.0 * di;
+            const double ndr = dr * tr - di * ti + fr, ndi = dr * ti + di * tr + fi;
+            const double nfr = fr * tr - fi * ti + q[j].x, nfi = fr * ti + fi * tr + q[j].y;
+            er = ner; ei = nei; dr = ndr; di = ndi; fr = nfr; fi = nfi;
+        }
     }
 }
 
-__device__ __forceinline__ void horner0(const double2 *__restrict__ a, int p, double tr, double ti,
-                                        double &fr, double &fi)
+__device__ __forceinline__ void horner0(const double2 *__restrict__ a, int stride, double tr,
+                                        double ti, double &fr, double &fi)
 {
-    fr = a[p].x; fi = a[p].y;
-    for (int k = p - 1; k >= 0; --k) {
-        const double nfr = fr * tr - fi * ti + a[k].x, nfi = fr * ti + fi * tr + a[k].y;
-        fr = nfr; fi = nfi;
+    fr = fi = 0.0;
+    for (int c = stride - 8; c >= 0; c -= 8) {
+        const double4 *a4 = reinterpret_cast<const double4 *>(a + c);
+        double2 q[8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double4 v = a4[j];
+            q[2 * j] = make_double2(v.x, v.y);
+            q[2 * j + 1] = make_double2(v.z, v.w);
+        }
+#pragma unroll
+        for (int j = 7; j >= 0; --j) {
+            const double nfr = fr * tr - fi * ti + q[j].x, nfi = fr * ti + fi * tr + q[j].y;
+            fr = nfr; fi = nfi;
+        }
     }
 }
 
@@ -412,13 +445,17 @@ __device__ __forceinline__ void fmm_far(const FmmArgs &M, double zr, double zi, 
     if (fx >= 0.0 && fy >= 0.0 && fx < (double)M.G && fy < (double)M.G) {
         const int ix = (int)fx, iy = (int)fy;
         cell = iy * M.G + ix;
-        const double tr = zr - (M.x0 + (ix + 0.5) * M.w), ti = zi - (M.y0 + (iy + 0.5) * M.w);
-        const double2 *a = M.cf + (int64_t)cell * (M.p + 1);
-        horner2(a, M.p, tr, ti, f.x, f.y, f1.x, f1.y, f2.x, f2.y);
+        const double tr = (zr - (M.x0 + (ix + 0.5) * M.w)) * M.inv_w;
+        const double ti = (zi - (M.y0 + (iy + 0.5) * M.w)) * M.inv_w;
+        const double2 *a = M.cf + (int64_t)cell * M.stride;
+        horner2(a, M.stride, tr, ti, f.x, f.y, f1.x, f1.y, f2.x, f2.y);
+        const double iw2 = M.inv_w * M.inv_w;
+        f1.x *= M.inv_w; f1.y *= M.inv_w;
+        f2.x *= iw2; f2.y *= iw2;
         if (M.equal) {
             g = f;
         } else if (want_g) {
-            horner0(M.cg + (int64_t)cell * (M.p + 1), M.p, tr, ti, g.x, g.y);
+            horner0(M.cg + (int64_t)cell * M.stride, M.stride, tr, ti, g.x, g.y);
         } else {
             g = make_double2(0.0, 0.0);
         }
@@ -458,67 +495,74 @@ __device__ __forceinline__ void fmm_far(const FmmArgs &M, double zr, double zi, 
     q = M.wsum / (dd * dd * dd * dd);
 }
 
-// Local expansions of every cell from its far stars: one work group per
-// cell, lane k accumulating a_k = -sum w_i v_i^(k+1), v_i = 1 / (z_i - c),
-// for both weightings, v^(k+1) by binary powering; lane 0 also the bound
+// Local expansions of every cell from its far stars, one work group of 64
+// lanes per cell.  The stars go by in blocks of 64: lane k takes star k of
+// the block, forms v = w / (z_k - c) (0 for a star of the 3 x 3 near cells,
+// whose cell index rides in the record's fourth component) and writes its
+// powers v^1 .. v^stride to LDS; then lane j adds up power j + 1 over the
+// block's stars, weighted (f) and unweighted (g).  Successive products cost
+// one complex multiply per power, against ~7 for raising each lane's star
+// to its own power.  Lane k also adds its star's term of the bound
 // sum_far w_i / dist(z_i, cell)^4.
 __global__ void __launch_bounds__(64)
-fmm_p2l(int32_t G, int32_t p, double x0, double y0, double w, int32_t equal,
-        const int32_t *__restrict__ cell_start, const double4 *__restrict__ fstars,
-        double2 *__restrict__ cf, double2 *__restrict__ cg, double *__restrict__ qfar)
+fmm_p2l(int32_t G, int32_t p, int32_t stride, double x0, double y0, double w, int32_t equal,
+        int32_t n, const double4 *__restrict__ fstars, double2 *__restrict__ cf,
+        double2 *__restrict__ cg, double *__restrict__ qfar)
 {
+    __shared__ double2 pw[64 * 65];   // pw[j * 65 + k] = v_k^(j+1); the pad spreads the banks
+    __shared__ double wk[64];
     const int cell = blockIdx.x;
     const int ix = cell % G, iy = cell / G;
     const double cx = x0 + (ix + 0.5) * w, cy = y0 + (iy + 0.5) * w;
-    const int k = threadIdx.x;
-    const int e = k + 1;
+    const int lane = threadIdx.x;
     double fr = 0.0, fi = 0.0, gr = 0.0, gi = 0.0, q = 0.0;
-    for (int y = 0; y < G; ++y) {
-        // the row's cells outside [ix-1, ix+1] (all of them when |y - iy| > 1)
-        const bool near_row = y >= iy - 1 && y <= iy + 1;
-        for (int part = 0; part < 2; ++part) {
-            int qa, qb;   // cell range [qa, qb) of the row
-            if (!near_row) {
-                if (part) break;
-                qa = y * G; qb = y * G + G;
-            } else if (part == 0) {
-                qa = y * G; qb = y * G + max(ix - 1, 0);
-            } else {
-                qa = y * G + min(ix + 2, G); qb = y * G + G;
-            }
-            for (int i = cell_start[qa]; i < cell_start[qb]; ++i) {
-                const double4 st = fstars[i];
+    for (int i0 = 0; i0 < n; i0 += 64) {
+        const int i = i0 + lane;
+        double vr = 0.0, vi = 0.0, wi = 0.0;
+        if (i < n) {
+            const double4 st = fstars[i];
+            const int sc = (int)st.w;
+            const int sx = sc % G, sy = sc / G;
+            if (abs(sx - ix) > 1 || abs(sy - iy) > 1) {
                 const double dx = st.x - cx, dy = st.y - cy;
                 const double r2 = dx * dx + dy * dy;
-                const double vr = dx / r2, vi = -dy / r2;
-                // v^e by binary powering (e <= 64)
-                double pr = 1.0, pi = 0.0, br = vr, bi = vi;
-                for (int b = 0; b < 7; ++b) {
-                    if ((e >> b) & 1) {
-                        const double t = pr * br - pi * bi;
-                        pi = pr * bi + pi * br;
-                        pr = t;
-                    }
-                    const double t = br * br - bi * bi;
-                    bi = 2.0 * br * bi;
-                    br = t;
-                }
-                const double wi = equal ? 1.0 : st.z;
-                fr -= wi * pr; fi -= wi * pi;
-                gr -= pr; gi -= pi;
-                if (k == 0) {
-                    const double ex = fmax(fabs(dx) - 0.5 * w, 0.0), ey = fmax(fabs(dy) - 0.5 * w, 0.0);
-                    const double d2 = ex * ex + ey * ey;
-                    q += wi / (d2 * d2);
-                }
+                vr = w * dx / r2;
+                vi = -w * dy / r2;
+                wi = equal ? 1.0 : st.z;
+                const double ex = fmax(fabs(dx) - 0.5 * w, 0.0), ey = fmax(fabs(dy) - 0.5 * w, 0.0);
+                const double d2 = ex * ex + ey * ey;
+                q += wi / (d2 * d2);
             }
         }
+        double pr = vr, pi = vi;
+        for (int j = 0; j < stride; ++j) {
+            pw[j * 65 + lane] = make_double2(pr, pi);
+            const double t = pr * vr - pi * vi;
+            pi = pr * vi + pi * vr;
+            pr = t;
+        }
+        wk[lane] = wi;
+        __syncthreads();
+        if (lane < stride) {
+#pragma unroll 8
+            for (int k = 0; k < 64; ++k) {
+                const double2 v = pw[lane * 65 + k];
+                const double wt = wk[k];
+                fr = fma(-wt, v.x, fr);
+                fi = fma(-wt, v.y, fi);
+                gr -= v.x;
+                gi -= v.y;
+            }
+        }
+        __syncthreads();
     }
-    if (k <= p) {
-        cf[(int64_t)cell * (p + 1) + k] = make_double2(fr, fi);
-        cg[(int64_t)cell * (p + 1) + k] = make_double2(gr, gi);
+    wave_sum(q);
+    if (lane < stride) {
+        const double s = lane <= p ? 1.0 / w : 0.0;
+        cf[(int64_t)cell * stride + lane] = make_double2(fr * s, fi * s);
+        cg[(int64_t)cell * stride + lane] = make_double2(gr * s, gi * s);
     }
-    if (k == 0) qfar[cell] = q;
+    if (lane == 0) qfar[cell] = q;
 }
 
 // Calls body(star) for the stars of the 3 x 3 cells around `cell`; returns
@@ -534,6 +578,7 @@ __device__ __forceinline__ int fmm_near(const FmmArgs &M, int cell, Body &&body)
         // the cells of one grid row are adjacent in the sorted order
         const int i0 = M.cell_start[q0], i1 = M.cell_start[q1 + 1];
         n += i1 - i0;
+#pragma unroll 4
         for (int i = i0; i < i1; ++i) body(M.fstars[i]);
     }
     return n;
@@ -902,10 +947,26 @@ __device__ __forceinline__ void sweep_f32_pass(const RoundArgs<typename StarRec<
         zi = z.y;
         if (B.pred) predict(A, B, k, zr, zi);
     }
-    // star sums: FP32 within a tile, FP64 across tiles
+    // star sums: FP32 within a tile, FP64 across tiles (with multipole
+    // sums: the near stars' terms and the cell's series, in FP64)
     double S1r = 0, S1i = 0, S2r = 0, S2i = 0, S3r = 0, S3i = 0;
     float p1r = 0, p1i = 0, p2r = 0, p2i = 0, p3r = 0, p3i = 0;
-    stream_tiles_ex(
+    if (A.fmm.on) {
+        Sums S;
+        zero(S);
+        int cell;
+        double2 f, f1, f2, g;
+        double q;
+        fmm_far(A.fmm, zr, zi, cell, f, f1, f2, g, q, true);
+        const int n_near = fmm_near(A.fmm, cell, [&](const double4 &s4) {
+            if constexpr (EQUAL) add_star<EQUAL>(S, zr, zi, make_double2(s4.x, s4.y));
+            else add_star<EQUAL>(S, zr, zi, s4);
+        });
+        fmm_count(&A.ctl->fmm_near_f32, &A.ctl->fmm_far_f32, valid, n_near);
+        S1r = S.s1r + g.x; S1i = S.s1i + g.y;
+        S2r = S.s2r - f1.x; S2i = S.s2i + 0.5 * f1.y;
+        S3r = S.s3r + 0.5 * f2.x; S3i = S.s3i + 0.5 * f2.y;
+    } else stream_tiles_ex(
         stars, n_stars, reinterpret_cast<T *>(tiles), Same{},
         [&](int, const T &s) {
             const float dx = (float)(zr - s.x), dy = (float)(zi - s.y);
@@ -1118,7 +1179,11 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
     const double2 e = B.e;
     double fr_ = zr, fi_ = zi;   // value this root ends the pass with
     int n_after = 0;
-    if (n_act > 0 && n_act <= SPARSE_MAX) {
+    int n_steps = -1;   // Newton steps this lane took (-1: one per active root)
+    // (with multipole sums a root's star terms are a few near stars and one
+    // series, as cheap per lane as a wave's share of a direct sum, so the
+    // wave never takes its few roots one at a time)
+    if (n_act > 0 && n_act <= SPARSE_MAX && !A.fmm.on) {
         unsigned long long mm = amask;
         while (mm) {
             const int l = __ffsll((long long)mm) - 1;
@@ -1146,27 +1211,53 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
             n_after += u.flag ? 0 : 1;
         }
     } else if (n_act > 0) {
-        PSums S;
-        zero(S);
+        Update u{};
         if (A.fmm.on) {
-            int cell;
-            double2 f, f1, f2, g;
-            double q;
-            fmm_far(A.fmm, zr, zi, cell, f, f1, f2, g, q, false);
-            const int n_near = fmm_near(A.fmm, cell, [&](const double4 &s4) {
-                if constexpr (EQUAL) add_star_polish<EQUAL>(S, zr, zi, make_double2(s4.x, s4.y));
-                else add_star_polish<EQUAL>(S, zr, zi, s4);
-            });
-            fmm_count(&A.ctl->fmm_near_polish, &A.ctl->fmm_far_polish, act, n_near);
-            S.s0r += f.x; S.s0i += f.y;
-            S.s2r -= f1.x; S.s2i += 0.5 * f1.y;
-            S.s3r += 0.5 * f2.x; S.s3i += 0.5 * f2.y;
-            S.q += q;
+            // A Newton step needs only its own root's sums, and with
+            // multipole sums those cost a few near stars and one series: a
+            // root the acceptance test turns down takes its next step in the
+            // same pass (up to FMM_POLISH_STEPS), instead of waiting a pass.
+            double xr = zr, xi = zi;
+            bool open = act;
+            n_steps = 0;
+            for (int it = 0; it < FMM_POLISH_STEPS; ++it) {
+                PSums S;
+                zero(S);
+                int cell;
+                double2 f, f1, f2, g;
+                double q;
+                fmm_far(A.fmm, xr, xi, cell, f, f1, f2, g, q, false);
+                const int n_near = fmm_near(A.fmm, cell, [&](const double4 &s4) {
+                    if constexpr (EQUAL)
+                        add_star_polish<EQUAL>(S, xr, xi, make_double2(s4.x, s4.y));
+                    else add_star_polish<EQUAL>(S, xr, xi, s4);
+                });
+                fmm_count(&A.ctl->fmm_near_polish, &A.ctl->fmm_far_polish, open, n_near);
+                S.s0r += f.x; S.s0i += f.y;
+                S.s2r -= f1.x; S.s2i += 0.5 * f1.y;
+                S.s3r += 0.5 * f2.x; S.s3i += 0.5 * f2.y;
+                S.q += q;
+                const Update v = polish_finish<EQUAL>(S, xr, xi, m0, e, gamma, a, a1, tol_step2,
+                                                      tol_mu, k);
+                if (open) {
+                    u = v;
+                    n_steps += 1;
+                    if (v.flag) {
+                        open = false;
+                    } else {
+                        xr = v.zr;
+                        xi = v.zi;
+                    }
+                }
+                if (!__ballot(open)) break;
+            }
         } else {
+            PSums S;
+            zero(S);
             stream_tiles(stars, n_stars, reinterpret_cast<T *>(tiles),
                          [&](int, const T &s) { add_star_polish<EQUAL>(S, zr, zi, s); });
+            u = polish_finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k);
         }
-        const Update u = polish_finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k);
         if (act) {
             nxt[base_f + k] = make_double2(u.zr, u.zi);
             fr_ = u.zr;
@@ -1194,8 +1285,15 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
         A.vieta[2 * B.vslot] = make_double4(s1r, s1i, s2r, s2i);
         A.vieta[2 * B.vslot + 1] = make_double4(t_e, t_e2, t_a, t_a2);
         if (n_after) atomicAdd(&A.counts[B.f], n_after);
-        if (n_act) atomicAdd(&A.passupd[B.f], n_act);
     }
+    // updates of the pass: one per active root, or its Newton steps
+    int n_upd = n_act;
+    if (n_steps >= 0) {
+        n_upd = n_steps;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) n_upd += __shfl_xor(n_upd, off, 64);
+    }
+    if (lane == 0 && n_upd) atomicAdd(&A.passupd[B.f], n_upd);
 }
 
 template <bool EQUAL>
@@ -1777,21 +1875,29 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
 // round: ~0.8 of the longest wave pass, plus ~40 us of launches and control.
 // The number of rounds is ~2.1 per row of a front's m / 2S rows, plus the
 // cold start.
+// With multipole star sums (one field) a wave's star part is a few near
+// stars and one series of order ~48: ~3,400 instructions, but bound by the
+// latency of its chain of dependent loads (cell, coefficients chunk by
+// chunk, near-cell ranges): measured on n10k at 4 waves per SIMD, a polish
+// pass occupies ~94k SIMD cycles whatever N, and the star part of a sweep
+// is priced the same; the root terms keep their cost.
 struct TuneModel {
     double cold_sweeps = 27.0, rounds_per_row = 2.1, tail = 0.8, round_us = 40.0;
     double clock_hz = 2.4e9, simds = 1024.0;
+    double fmm_star_cycles = 94000.0;
 };
 
-static double pass_cycles(int kind, double n)
+static double pass_cycles(int kind, double n, bool fmm)
 {
+    const TuneModel tm;
     const double n_r = 2.0 * n;
-    if (kind == PH_F64) return 114.0 * n + 47.0 * n_r;
-    if (kind == PH_F32) return 56.0 * n + 22.0 * n_r;
-    return 120.0 * n;
+    if (kind == PH_F64) return (fmm ? tm.fmm_star_cycles : 114.0 * n) + 47.0 * n_r;
+    if (kind == PH_F32) return (fmm ? tm.fmm_star_cycles : 56.0 * n) + 22.0 * n_r;
+    return fmm ? tm.fmm_star_cycles : 120.0 * n;
 }
 
 static double predicted_seconds(const std::vector<RealHost> &reals, int64_t m, int64_t s, bool mixed,
-                         int predictor)
+                         int predictor, bool fmm)
 {
     const TuneModel tm;
     double work = 0.0, blocks_all = 0.0, longest = 0.0;
@@ -1799,16 +1905,17 @@ static double predicted_seconds(const std::vector<RealHost> &reals, int64_t m, i
         const double n = (double)r.n, blocks = std::ceil(2.0 * n / 64.0);
         double row, cold;
         if (!mixed) {
-            row = (predictor > 0 ? 1.03 : 2.0) * pass_cycles(PH_F64, n);
-            cold = tm.cold_sweeps * pass_cycles(PH_F64, n);
+            row = (predictor > 0 ? 1.03 : 2.0) * pass_cycles(PH_F64, n, fmm);
+            cold = tm.cold_sweeps * pass_cycles(PH_F64, n, fmm);
         } else {
-            row = 1.02 * pass_cycles(PH_POLISH, n) +
-                  (predictor > 0 ? 0.0 : pass_cycles(PH_F32, n));
-            cold = tm.cold_sweeps * pass_cycles(PH_F32, n) + pass_cycles(PH_POLISH, n);
+            row = 1.02 * pass_cycles(PH_POLISH, n, fmm) +
+                  (predictor > 0 ? 0.0 : pass_cycles(PH_F32, n, fmm));
+            cold = tm.cold_sweeps * pass_cycles(PH_F32, n, fmm) + pass_cycles(PH_POLISH, n, fmm);
         }
         work += blocks * (row * (double)(m + s) + cold * (double)s);
         blocks_all += blocks;
-        longest = std::max(longest, mixed ? pass_cycles(PH_POLISH, n) : pass_cycles(PH_F64, n));
+        longest = std::max(longest, mixed ? pass_cycles(PH_POLISH, n, fmm)
+                                          : pass_cycles(PH_F64, n, fmm));
     }
     // about half of the 2S fronts are in a full pass at any time
     const double waves = (double)s * blocks_all;
@@ -1823,7 +1930,7 @@ static double predicted_seconds(const std::vector<RealHost> &reals, int64_t m, i
 // predicted time among those that leave every subchain at least 16 rows and
 // keep the front table within MAX_FRONTS.
 static int autotune_subchains(const std::vector<RealHost> &reals, int64_t m, bool mixed,
-                              int predictor)
+                              int predictor, bool fmm)
 {
     const int64_t half = m / 2;
     const int64_t s_max = std::max<int64_t>(
@@ -1832,7 +1939,7 @@ static int autotune_subchains(const std::vector<RealHost> &reals, int64_t m, boo
     int best_s = 1;
     for (int64_t s = 1; s <= std::min<int64_t>(half, std::min<int64_t>(s_max, 4096)); ++s) {
         if (half % s) continue;
-        const double t = predicted_seconds(reals, m, s, mixed, predictor);
+        const double t = predicted_seconds(reals, m, s, mixed, predictor, fmm);
         if (t < best * 0.999) {
             best = t;
             best_s = (int)s;
@@ -1878,10 +1985,15 @@ static mlcc_status build_fmm(Ctx *c, int order, FmmArgs &M)
         start[cell_of[i] + 1] += 1;
     }
     for (int q = 0; q < G * G; ++q) start[q + 1] += start[q];
+    // sorted by cell; the fourth component carries the cell index
     std::vector<double4> sorted(n);
     {
         std::vector<int32_t> fill(start.begin(), start.end() - 1);
-        for (int64_t i = 0; i < n; ++i) sorted[fill[cell_of[i]]++] = st[i];
+        for (int64_t i = 0; i < n; ++i) {
+            double4 a = st[i];
+            a.w = (double)cell_of[i];
+            sorted[fill[cell_of[i]]++] = a;
+        }
     }
     // expansions about the centre: M_k = sum w_i (z_i - c0)^k, and unit weights
     std::vector<double2> mm(2 * (pp + 1), make_double2(0.0, 0.0));
@@ -1897,20 +2009,26 @@ static mlcc_status build_fmm(Ctx *c, int order, FmmArgs &M)
         }
     }
     const size_t ncell = (size_t)G * G;
+    const int stride = (pp + 8) & ~7;
     MLCC_TRY(c->fmm_cs.reserve(start.size() * sizeof(int32_t)));
     MLCC_TRY(c->fmm_st.reserve(std::max<int64_t>(n, 1) * sizeof(double4)));
-    MLCC_TRY(c->fmm_cf.reserve(ncell * (pp + 1) * sizeof(double2)));
-    MLCC_TRY(c->fmm_cg.reserve(ncell * (pp + 1) * sizeof(double2)));
+    MLCC_TRY(c->fmm_cf.reserve(ncell * stride * sizeof(double2)));
+    MLCC_TRY(c->fmm_cg.reserve(ncell * stride * sizeof(double2)));
     MLCC_TRY(c->fmm_q.reserve(ncell * sizeof(double)));
     MLCC_TRY(c->fmm_m.reserve(mm.size() * sizeof(double2)));
     MLCC_HIP(hipMemcpyAsync(c->fmm_cs.p, start.data(), start.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice, c->stream));
     MLCC_HIP(hipMemcpyAsync(c->fmm_st.p, sorted.data(), n * sizeof(double4), hipMemcpyHostToDevice,
                             c->stream));
+    std::vector<double2> sorted2(n);
+    for (int64_t i = 0; i < n; ++i) sorted2[i] = make_double2(sorted[i].x, sorted[i].y);
+    MLCC_TRY(c->fmm_st2.reserve(std::max<int64_t>(n, 1) * sizeof(double2)));
+    MLCC_HIP(hipMemcpyAsync(c->fmm_st2.p, sorted2.data(), n * sizeof(double2),
+                            hipMemcpyHostToDevice, c->stream));
     MLCC_HIP(hipMemcpyAsync(c->fmm_m.p, mm.data(), mm.size() * sizeof(double2),
                             hipMemcpyHostToDevice, c->stream));
-    hipLaunchKernelGGL(fmm_p2l, dim3((unsigned)ncell), dim3(64), 0, c->stream, G, pp, x0, y0, w,
-                       (int32_t)equal, c->fmm_cs.as<int32_t>(), c->fmm_st.as<double4>(),
+    hipLaunchKernelGGL(fmm_p2l, dim3((unsigned)ncell), dim3(64), 0, c->stream, G, pp, stride, x0,
+                       y0, w, (int32_t)equal, (int32_t)n, c->fmm_st.as<double4>(),
                        c->fmm_cf.as<double2>(), c->fmm_cg.as<double2>(), c->fmm_q.as<double>());
     MLCC_HIP(hipGetLastError());
     // host vectors must outlive the copies
@@ -1919,7 +2037,8 @@ static mlcc_status build_fmm(Ctx *c, int order, FmmArgs &M)
     M.G = G;
     M.p = pp;
     M.equal = equal;
-    M.x0 = x0; M.y0 = y0; M.w = w;
+    M.stride = stride;
+    M.x0 = x0; M.y0 = y0; M.w = w; M.inv_w = 1.0 / w;
     M.cx = cx; M.cy = cy; M.R = R; M.wsum = wsum;
     M.cell_start = c->fmm_cs.as<int32_t>();
     M.fstars = c->fmm_st.as<double4>();
@@ -1941,7 +2060,9 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     // one field with equal masses: (x, y) records, the mass applied once
     const bool equal = !c->batched && c->equal_mass;
     int S = p->n_subchains;
-    if (S <= 0) S = autotune_subchains(c->reals, m, mixed, p->predictor);
+    if (S <= 0)
+        S = autotune_subchains(c->reals, m, mixed, p->predictor,
+                               p->star_sums == MLCC_STARS_FMM);
     if ((m / 2) % S) return fail(MLCC_ERR_INVALID, "n_subchains=%d must divide m/2", S);
     const int64_t L = m / S;
     const int max_cold = p->max_iter_cold > 0 ? p->max_iter_cold : 500;
@@ -2080,7 +2201,16 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     MLCC_TRY(c->reals_d.reserve((size_t)n_real * sizeof(Real)));
     MLCC_TRY(c->sheet.reserve(std::max<size_t>(1, sheet_host.size()) * sizeof(double)));
     FmmArgs fmm{};
-    if (p->star_sums == MLCC_STARS_FMM) MLCC_TRY(build_fmm(c, p->fmm_order, fmm));
+    // With multipole sums the kernels take the stars in cell order, so that
+    // the seeds z_i +- 1 of a work group's roots, and the roots grown from
+    // them, share a few cells (and those cells' series) instead of 64.
+    const double2 *stars2 = c->stars.as<double2>();
+    const double4 *stars4 = c->stars4.as<double4>();
+    if (p->star_sums == MLCC_STARS_FMM) {
+        MLCC_TRY(build_fmm(c, p->fmm_order, fmm));
+        stars2 = c->fmm_st2.as<double2>();
+        stars4 = c->fmm_st.as<double4>();
+    }
     MLCC_TRY(c->bmap.reserve((size_t)ngrid * sizeof(int2)));
     MLCC_TRY(c->workflags.reserve(2 * MAX_BATCH * sizeof(int32_t)));
     MLCC_TRY(ensure_pinned(c, 2 * (sizeof(Control) + MAX_BATCH * sizeof(int32_t))));
@@ -2111,11 +2241,11 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     MLCC_HIP(hipMemsetAsync(c->passupd.p, 0, F * sizeof(int32_t), c->stream));
     if (equal)
         hipLaunchKernelGGL(seed_centres<double2>, dim3((unsigned)ngrid), dim3(64), 0, c->stream,
-                           c->stars.as<double2>(), c->reals_d.as<Real>(), c->fronts.as<Front>(),
+                           stars2, c->reals_d.as<Real>(), c->fronts.as<Front>(),
                            c->bmap.as<int2>(), c->sheet.as<double>(), c->iter[0].as<double2>());
     else
         hipLaunchKernelGGL(seed_centres<double4>, dim3((unsigned)ngrid), dim3(64), 0, c->stream,
-                           c->stars4.as<double4>(), c->reals_d.as<Real>(), c->fronts.as<Front>(),
+                           stars4, c->reals_d.as<Real>(), c->fronts.as<Front>(),
                            c->bmap.as<int2>(), c->sheet.as<double>(), c->iter[0].as<double2>());
     MLCC_HIP(hipGetLastError());
     // Host copies must finish before the vectors above go out of scope.
@@ -2160,12 +2290,12 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     const dim3 grid((unsigned)ngrid);
     auto launch_kind = [&](int kind, const double2 *cur, double2 *nxt) {
         if (equal) {
-            fill(A2, c->stars.as<double2>(), cur, nxt);
+            fill(A2, stars2, cur, nxt);
             if (kind == 0) hipLaunchKernelGGL(aberth_sweep_f64<true>, grid, dim3(64), 0, rs, A2);
             if (kind == 1) hipLaunchKernelGGL(aberth_sweep_f32<true>, grid, dim3(64), 0, rs, A2);
             if (kind == 2) hipLaunchKernelGGL(newton_polish_f64<true>, grid, dim3(64), 0, rs, A2);
         } else {
-            fill(A4, c->stars4.as<double4>(), cur, nxt);
+            fill(A4, stars4, cur, nxt);
             if (kind == 0) hipLaunchKernelGGL(aberth_sweep_f64<false>, grid, dim3(64), 0, rs, A4);
             if (kind == 1) hipLaunchKernelGGL(aberth_sweep_f32<false>, grid, dim3(64), 0, rs, A4);
             if (kind == 2) hipLaunchKernelGGL(newton_polish_f64<false>, grid, dim3(64), 0, rs, A4);
@@ -2357,7 +2487,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         }
         const double2 *cur0 = c->iter[0].as<double2>();
         if (equal) {
-            fill(A2, c->stars.as<double2>(), cur0, c->iter[1].as<double2>());
+            fill(A2, stars2, cur0, c->iter[1].as<double2>());
             A2.persistent = 1;
             A2.iter0 = c->iter[0].as<double2>();
             A2.iter1 = c->iter[1].as<double2>();
@@ -2365,7 +2495,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
                                c->fronts.as<Front>(), dq, dtasks, dseq,
                                (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm, stall);
         } else {
-            fill(A4, c->stars4.as<double4>(), cur0, c->iter[1].as<double2>());
+            fill(A4, stars4, cur0, c->iter[1].as<double2>());
             A4.persistent = 1;
             A4.iter0 = c->iter[0].as<double2>();
             A4.iter1 = c->iter[1].as<double2>();
@@ -2577,17 +2707,23 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         // order (the unit-weight series of unequal masses 8 more in the
         // sweeps), plus ~20 for the cell and the sums.  The outside-grid
         // expansion, rarely taken, is counted the same.
+        // The FP32 sweeps take such sums in FP64: their star terms move from
+        // the FP32 count to the FP64 one.
         double star64 = (double)h.star_updates, starpol = (double)h.star_updates_polish;
-        double far64 = 0.0, farpol = 0.0;
+        double far64 = 0.0, farpol = 0.0, star32_off = 0.0;
         if (fmm.on) {
             const double nf = (double)c->n;
             const double pf = (double)fmm.p;
-            far64 = (double)h.fmm_far * (26.0 * pf + 20.0 + (fmm.equal ? 0.0 : 8.0 * pf));
+            const double unit_g = fmm.equal ? 0.0 : 8.0 * pf;
+            far64 = (double)h.fmm_far * (26.0 * pf + 20.0 + unit_g) +
+                    (double)h.fmm_far_f32 * (26.0 * pf + 20.0 + unit_g) +
+                    29.0 * (double)h.fmm_near_f32;
             farpol = (double)h.fmm_far_polish * (26.0 * pf + 20.0);
             star64 += (double)h.fmm_near - nf * (double)h.fmm_far;
             starpol += (double)h.fmm_near_polish - nf * (double)h.fmm_far_polish;
-            stats->fmm_near_terms = (int64_t)(h.fmm_near + h.fmm_near_polish);
-            stats->fmm_far_evals = (int64_t)(h.fmm_far + h.fmm_far_polish);
+            star32_off = 29.0 * nf * (double)h.fmm_far_f32;
+            stats->fmm_near_terms = (int64_t)(h.fmm_near + h.fmm_near_polish + h.fmm_near_f32);
+            stats->fmm_far_evals = (int64_t)(h.fmm_far + h.fmm_far_polish + h.fmm_far_f32);
         }
         stats->algorithmic_flop = 29.0 * star64 + far64 +
                                   20.0 * (double)(h.star_updates - h.star_updates_fast) -
@@ -2600,7 +2736,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
             stats->algorithmic_flop_sweep_roots += ex * (double)h.updates_fast;
         }
         stats->algorithmic_flop_f32 =
-            49.0 * (double)h.star_updates_f32 - 10.0 * (double)h.updates_f32;
+            49.0 * (double)h.star_updates_f32 - 10.0 * (double)h.updates_f32 - star32_off;
         stats->algorithmic_flop_polish = 29.0 * starpol + farpol;
     }
     return result;

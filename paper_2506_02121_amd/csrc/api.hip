@@ -183,7 +183,8 @@ void mlcc_destroy(mlcc_ctx *ctx)
                       &c.flagrow, &c.fronts, &c.counts, &c.control, &c.etab, &c.bnd, &c.perm,
                       &c.match_aux, &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.vsum,
                       &c.pq, &c.passupd, &c.reals_d, &c.bmap, &c.diff, &c.err, &c.edt_col,
-                      &c.dmask, &c.fmm_cs, &c.fmm_st, &c.fmm_cf, &c.fmm_cg, &c.fmm_q, &c.fmm_m};
+                      &c.dmask, &c.fmm_cs, &c.fmm_st, &c.fmm_st2, &c.fmm_cf, &c.fmm_cg,
+                      &c.fmm_q, &c.fmm_m};
     for (DevBuf *b : bufs) b->release();
     if (c.own_stream) (void)hipStreamDestroy(c.own_stream);
     if (c.pinned) (void)hipHostFree(c.pinned);
