@@ -743,7 +743,7 @@ __device__ __forceinline__ bool fast_roots_pass(const Front &fr)
 
 // One FP64 Aberth pass of a block (the block context is set by enter()).
 // `tiles` holds two tiles of up to 32-byte records.
-template <bool EQUAL>
+template <bool EQUAL, bool FMM>
 __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<EQUAL>::T> &A,
                                                const BlockCtx<typename StarRec<EQUAL>::T> &B,
                                                double4 *tiles)
@@ -832,7 +832,7 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
     } else {
         Sums S;
         zero(S);
-        if (A.fmm.on) {
+        if constexpr (FMM) {
             int cell;
             double2 f, f1, f2, g;
             double q;
@@ -902,14 +902,14 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
     }
 }
 
-template <bool EQUAL>
+template <bool EQUAL, bool FMM>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MLCC_SWEEP_WAVES, 8)))
 aberth_sweep_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
 {
     __shared__ double4 tiles[128];
     BlockCtx<typename StarRec<EQUAL>::T> B;
     if (!enter(A, PH_F64, B)) return;
-    sweep_f64_pass<EQUAL>(A, B, tiles);
+    sweep_f64_pass<EQUAL, FMM>(A, B, tiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -928,7 +928,7 @@ constexpr double TOL_F32 = 1e-6;
 // terms from swamping the accumulation.  The other roots enter in FP32
 // coordinates (they only steer the step).  The step itself and the new
 // iterate are FP64.
-template <bool EQUAL>
+template <bool EQUAL, bool FMM>
 __device__ __forceinline__ void sweep_f32_pass(const RoundArgs<typename StarRec<EQUAL>::T> &A,
                                                const BlockCtx<typename StarRec<EQUAL>::T> &B,
                                                double4 *tiles)
@@ -951,7 +951,7 @@ __device__ __forceinline__ void sweep_f32_pass(const RoundArgs<typename StarRec<
     // sums: the near stars' terms and the cell's series, in FP64)
     double S1r = 0, S1i = 0, S2r = 0, S2i = 0, S3r = 0, S3i = 0;
     float p1r = 0, p1i = 0, p2r = 0, p2i = 0, p3r = 0, p3i = 0;
-    if (A.fmm.on) {
+    if constexpr (FMM) {
         Sums S;
         zero(S);
         int cell;
@@ -966,34 +966,36 @@ __device__ __forceinline__ void sweep_f32_pass(const RoundArgs<typename StarRec<
         S1r = S.s1r + g.x; S1i = S.s1i + g.y;
         S2r = S.s2r - f1.x; S2i = S.s2i + 0.5 * f1.y;
         S3r = S.s3r + 0.5 * f2.x; S3i = S.s3i + 0.5 * f2.y;
-    } else stream_tiles_ex(
-        stars, n_stars, reinterpret_cast<T *>(tiles), Same{},
-        [&](int, const T &s) {
-            const float dx = (float)(zr - s.x), dy = (float)(zi - s.y);
-            const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, dy * dy));
-            // as in add_star: p2i accumulates sum m ux uy (Im u^2 = -2 ux uy)
-            const float ux = dx * inv, uy = dy * inv;
-            const float a = ux * ux, b = uy * uy;
-            p1r += ux;
-            p1i -= uy;
-            if (EQUAL) {
-                p2r += a - b;
-                p2i = fmaf(ux, uy, p2i);
-                p3r = fmaf(ux, fmaf(-3.0f, b, a), p3r);
-                p3i = fmaf(uy, fmaf(-3.0f, a, b), p3i);
-            } else {
-                const float mi = (float)StarRec<EQUAL>::mass(s);
-                const float mux = mi * ux, muy = mi * uy;
-                p2r = fmaf(mi, a - b, p2r);
-                p2i = fmaf(mux, uy, p2i);
-                p3r = fmaf(mux, fmaf(-3.0f, b, a), p3r);
-                p3i = fmaf(muy, fmaf(-3.0f, a, b), p3i);
-            }
-        },
-        [&]() {
-            S1r += p1r; S1i += p1i; S2r += p2r; S2i += p2i; S3r += p3r; S3i += p3i;
-            p1r = p1i = p2r = p2i = p3r = p3i = 0.f;
-        });
+    } else {
+        stream_tiles_ex(
+            stars, n_stars, reinterpret_cast<T *>(tiles), Same{},
+            [&](int, const T &s) {
+                const float dx = (float)(zr - s.x), dy = (float)(zi - s.y);
+                const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, dy * dy));
+                // as in add_star: p2i accumulates sum m ux uy (Im u^2 = -2 ux uy)
+                const float ux = dx * inv, uy = dy * inv;
+                const float a = ux * ux, b = uy * uy;
+                p1r += ux;
+                p1i -= uy;
+                if (EQUAL) {
+                    p2r += a - b;
+                    p2i = fmaf(ux, uy, p2i);
+                    p3r = fmaf(ux, fmaf(-3.0f, b, a), p3r);
+                    p3i = fmaf(uy, fmaf(-3.0f, a, b), p3i);
+                } else {
+                    const float mi = (float)StarRec<EQUAL>::mass(s);
+                    const float mux = mi * ux, muy = mi * uy;
+                    p2r = fmaf(mi, a - b, p2r);
+                    p2i = fmaf(mux, uy, p2i);
+                    p3r = fmaf(mux, fmaf(-3.0f, b, a), p3r);
+                    p3i = fmaf(muy, fmaf(-3.0f, a, b), p3i);
+                }
+            },
+            [&]() {
+                S1r += p1r; S1i += p1i; S2r += p2r; S2i += p2i; S3r += p3r; S3i += p3i;
+                p1r = p1i = p2r = p2i = p3r = p3i = 0.f;
+            });
+    }
     // root-root sum in FP32 coordinates
     const float zr32 = (float)zr, zi32 = (float)zi;
     double Rr = 0, Ri = 0;
@@ -1047,14 +1049,14 @@ __device__ __forceinline__ void sweep_f32_pass(const RoundArgs<typename StarRec<
     }
 }
 
-template <bool EQUAL>
+template <bool EQUAL, bool FMM>
 __global__ void __launch_bounds__(64)
 aberth_sweep_f32(RoundArgs<typename StarRec<EQUAL>::T> A)
 {
     __shared__ double4 tiles[128];
     BlockCtx<typename StarRec<EQUAL>::T> B;
     if (!enter(A, PH_F32, B)) return;
-    sweep_f32_pass<EQUAL>(A, B, tiles);
+    sweep_f32_pass<EQUAL, FMM>(A, B, tiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -1148,7 +1150,7 @@ __device__ __forceinline__ Update polish_finish(PSums S, double zr, double zi, d
     return u;
 }
 
-template <bool EQUAL>
+template <bool EQUAL, bool FMM>
 __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQUAL>::T> &A,
                                             const BlockCtx<typename StarRec<EQUAL>::T> &B,
                                             double4 *tiles)
@@ -1183,7 +1185,7 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
     // (with multipole sums a root's star terms are a few near stars and one
     // series, as cheap per lane as a wave's share of a direct sum, so the
     // wave never takes its few roots one at a time)
-    if (n_act > 0 && n_act <= SPARSE_MAX && !A.fmm.on) {
+    if (n_act > 0 && n_act <= SPARSE_MAX && !FMM) {
         unsigned long long mm = amask;
         while (mm) {
             const int l = __ffsll((long long)mm) - 1;
@@ -1212,7 +1214,7 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
         }
     } else if (n_act > 0) {
         Update u{};
-        if (A.fmm.on) {
+        if constexpr (FMM) {
             // A Newton step needs only its own root's sums, and with
             // multipole sums those cost a few near stars and one series: a
             // root the acceptance test turns down takes its next step in the
@@ -1296,14 +1298,14 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
     if (lane == 0 && n_upd) atomicAdd(&A.passupd[B.f], n_upd);
 }
 
-template <bool EQUAL>
+template <bool EQUAL, bool FMM>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MLCC_POLISH_WAVES, 8)))
 newton_polish_f64(RoundArgs<typename StarRec<EQUAL>::T> A)
 {
     __shared__ double4 tiles[128];
     BlockCtx<typename StarRec<EQUAL>::T> B;
     if (!enter(A, PH_POLISH, B)) return;
-    polish_pass<EQUAL>(A, B, tiles);
+    polish_pass<EQUAL, FMM>(A, B, tiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -1708,7 +1710,7 @@ __device__ __forceinline__ void push_front(PQueue *q, int2 *tasks, unsigned long
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <bool EQUAL>
+template <bool EQUAL, bool FMM>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MLCC_SWEEP_WAVES, 8)))
 aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ fronts_w,
                   PQueue *__restrict__ q, int2 *__restrict__ tasks,
@@ -1758,11 +1760,11 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
         if (enter_fq(A, -1, tf, tq, B)) {
             const int ph = A.fronts[tf].phase;
             if (ph == PH_F64)
-                sweep_f64_pass<EQUAL>(A, B, tiles);
+                sweep_f64_pass<EQUAL, FMM>(A, B, tiles);
             else if (ph == PH_F32)
-                sweep_f32_pass<EQUAL>(A, B, tiles);
+                sweep_f32_pass<EQUAL, FMM>(A, B, tiles);
             else
-                polish_pass<EQUAL>(A, B, tiles);
+                polish_pass<EQUAL, FMM>(A, B, tiles);
         }
         // the last block of the front's pass advances the front; every
         // block publishes its writes before counting itself done
@@ -2289,16 +2291,22 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     };
     const dim3 grid((unsigned)ngrid);
     auto launch_kind = [&](int kind, const double2 *cur, double2 *nxt) {
+        // each kernel comes with and without multipole sums, so that the
+        // direct kernels carry none of the multipole code's registers
+        auto go = [&](auto &A, auto eq, auto fm) {
+            constexpr bool E = decltype(eq)::value, M = decltype(fm)::value;
+            if (kind == 0) hipLaunchKernelGGL((aberth_sweep_f64<E, M>), grid, dim3(64), 0, rs, A);
+            if (kind == 1) hipLaunchKernelGGL((aberth_sweep_f32<E, M>), grid, dim3(64), 0, rs, A);
+            if (kind == 2) hipLaunchKernelGGL((newton_polish_f64<E, M>), grid, dim3(64), 0, rs, A);
+        };
+        using T_ = std::true_type;
+        using F_ = std::false_type;
         if (equal) {
             fill(A2, stars2, cur, nxt);
-            if (kind == 0) hipLaunchKernelGGL(aberth_sweep_f64<true>, grid, dim3(64), 0, rs, A2);
-            if (kind == 1) hipLaunchKernelGGL(aberth_sweep_f32<true>, grid, dim3(64), 0, rs, A2);
-            if (kind == 2) hipLaunchKernelGGL(newton_polish_f64<true>, grid, dim3(64), 0, rs, A2);
+            if (fmm.on) go(A2, T_{}, T_{}); else go(A2, T_{}, F_{});
         } else {
             fill(A4, stars4, cur, nxt);
-            if (kind == 0) hipLaunchKernelGGL(aberth_sweep_f64<false>, grid, dim3(64), 0, rs, A4);
-            if (kind == 1) hipLaunchKernelGGL(aberth_sweep_f32<false>, grid, dim3(64), 0, rs, A4);
-            if (kind == 2) hipLaunchKernelGGL(newton_polish_f64<false>, grid, dim3(64), 0, rs, A4);
+            if (fmm.on) go(A4, F_{}, T_{}); else go(A4, F_{}, F_{});
         }
     };
 
@@ -2469,8 +2477,11 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         int cus = 0, per_cu = 0, clock_khz = 0;
         MLCC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
         MLCC_HIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, c->device));
-        const void *kfn = equal ? reinterpret_cast<const void *>(&aberth_persistent<true>)
-                                : reinterpret_cast<const void *>(&aberth_persistent<false>);
+        const void *kfn =
+            equal ? (fmm.on ? reinterpret_cast<const void *>(&aberth_persistent<true, true>)
+                            : reinterpret_cast<const void *>(&aberth_persistent<true, false>))
+                  : (fmm.on ? reinterpret_cast<const void *>(&aberth_persistent<false, true>)
+                            : reinterpret_cast<const void *>(&aberth_persistent<false, false>));
         MLCC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 64, 0));
         if (cus < 1 || per_cu < 1 || clock_khz < 1)
             return fail(MLCC_ERR_HIP, "cannot size the persistent launch");
@@ -2491,17 +2502,31 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
             A2.persistent = 1;
             A2.iter0 = c->iter[0].as<double2>();
             A2.iter1 = c->iter[1].as<double2>();
-            hipLaunchKernelGGL(aberth_persistent<true>, dim3(workers), dim3(64), 0, rs, A2,
-                               c->fronts.as<Front>(), dq, dtasks, dseq,
-                               (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm, stall);
+            if (fmm.on)
+                hipLaunchKernelGGL((aberth_persistent<true, true>), dim3(workers), dim3(64), 0, rs,
+                                   A2, c->fronts.as<Front>(), dq, dtasks, dseq,
+                                   (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
+                                   stall);
+            else
+                hipLaunchKernelGGL((aberth_persistent<true, false>), dim3(workers), dim3(64), 0, rs,
+                                   A2, c->fronts.as<Front>(), dq, dtasks, dseq,
+                                   (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
+                                   stall);
         } else {
             fill(A4, stars4, cur0, c->iter[1].as<double2>());
             A4.persistent = 1;
             A4.iter0 = c->iter[0].as<double2>();
             A4.iter1 = c->iter[1].as<double2>();
-            hipLaunchKernelGGL(aberth_persistent<false>, dim3(workers), dim3(64), 0, rs, A4,
-                               c->fronts.as<Front>(), dq, dtasks, dseq,
-                               (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm, stall);
+            if (fmm.on)
+                hipLaunchKernelGGL((aberth_persistent<false, true>), dim3(workers), dim3(64), 0, rs,
+                                   A4, c->fronts.as<Front>(), dq, dtasks, dseq,
+                                   (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
+                                   stall);
+            else
+                hipLaunchKernelGGL((aberth_persistent<false, false>), dim3(workers), dim3(64), 0,
+                                   rs, A4, c->fronts.as<Front>(), dq, dtasks, dseq,
+                                   (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
+                                   stall);
         }
         MLCC_HIP(hipGetLastError());
         if (p->timing) MLCC_HIP(hipEventRecord(e1, rs));
