@@ -76,6 +76,10 @@ def parse():
     ap.add_argument("--star-sums", dest="star_sums", default="direct", choices=["direct", "fmm"],
                     help="star sums of the FP64 sweeps and the polish: direct, or fast multipole "
                          "(one field per call)")
+    ap.add_argument("--multipole", dest="multipole", action="store_true", default=True,
+                    help="after the timed run, the same field with fast-multipole star sums (FP64 "
+                         "and mixed), reported beside it")
+    ap.add_argument("--no-multipole", dest="multipole", action="store_false")
     ap.add_argument("--directional", type=int, default=0, metavar="K",
                     help="after the timed steps, moving-source distance maps of the last step's "
                          "N_cc map for K directions over [0, 180) degrees, with their histograms "
@@ -283,19 +287,25 @@ def main():
                              "fmm_far_evals_per_step": s0["fmm_far_evals"]})
     if args.directional > 0:
         out["directional"] = directional_stage(ctx, grid, ncc, args.directional)
-    if args.compare and f.sheet is None:   # a rectangular field is solved in FP64 only
-        # the other precision on the same field: throughput, and how far its
-        # roots lie from this run's on sampled rows (same sets, any order)
-        from scipy.spatial import cKDTree
-        other = "mixed" if precision == "fp64" else "fp64"
-        sample = np.linspace(0, m_steps, 17).astype(np.int64)
-        ref = [(roots_re[j].cpu().numpy(), roots_im[j].cpu().numpy()) for j in sample]
-        el2, st2 = run(other, 0, args.steps)
+    # sampled rows of the timed run: the other runs below report how far their
+    # roots lie from these (same sets, any order)
+    from scipy.spatial import cKDTree
+    sample = np.linspace(0, m_steps, 17).astype(np.int64)
+    ref = [(roots_re[j].cpu().numpy(), roots_im[j].cpu().numpy()) for j in sample]
+
+    def distance_to_ref():
         dmax = 0.0
         for j, (a_re, a_im) in zip(sample, ref):
             b = np.stack([roots_re[j].cpu().numpy(), roots_im[j].cpu().numpy()], 1)
             d, _ = cKDTree(b).query(np.stack([a_re, a_im], 1))
             dmax = max(dmax, float(d.max()))
+        return dmax
+
+    if args.compare and f.sheet is None:   # a rectangular field is solved in FP64 only
+        # the other precision on the same field: throughput and distance
+        other = "mixed" if precision == "fp64" else "fp64"
+        el2, st2 = run(other, 0, args.steps)
+        dmax = distance_to_ref()
         k2 = root_kernels(st2, other)
         out["compare"] = {
             "precision": other, "value": roots_per_step / (el2 / args.steps),
@@ -306,6 +316,28 @@ def main():
             "stats": {k: st2[-1][k] for k in ("sweeps", "root_updates", "root_updates_f32",
                                               "polish_updates", "rows_fallback")},
         }
+    if args.multipole and args.star_sums == "direct":
+        # the same field with fast-multipole star sums (Sec. 4.1), in each
+        # precision the field takes: throughput, its launch's roofline on the
+        # method's own FLOP count, and the distance to the timed run's roots
+        out["multipole"] = {}
+        for prec_m in (["fp64"] if f.sheet is not None else ["fp64", "mixed"]):
+            saved = args.star_sums
+            args.star_sums = "fmm"
+            el3, st3 = run(prec_m, 1, args.steps)
+            args.star_sums = saved
+            k3 = root_kernels(st3, prec_m)
+            out["multipole"][prec_m] = {
+                "value": roots_per_step / (el3 / args.steps), "ms_per_step": 1e3 * el3 / args.steps,
+                "steps": args.steps, "warmup": 1,
+                "speedup_over_timed_run": elapsed / el3,
+                "max_root_distance_to_main_run": distance_to_ref(), "sampled_rows": len(sample),
+                "kernels": k3,
+                "stats": {k: st3[-1][k] for k in ("n_subchains", "sweeps", "root_updates",
+                                                  "root_updates_f32", "polish_updates",
+                                                  "fmm_near_terms", "fmm_far_evals")},
+            }
+            log(f"multipole {prec_m}: {1e3 * el3 / args.steps:.1f} ms per step")
     ctx.close()
     del roots_re, roots_im, w_re, w_im
     torch.cuda.empty_cache()

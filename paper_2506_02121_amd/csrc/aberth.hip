@@ -339,6 +339,13 @@ __device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0
 #ifndef MLCC_POLISH_WAVES
 #define MLCC_POLISH_WAVES 4
 #endif
+// The persistent kernel with multipole sums spends most of its time waiting
+// on dependent loads; trading registers for resident waves did not pay on
+// n10k mixed (4 waves 331 ms per step, 5: 362, 6: 386, 8: 423: the spills
+// cost more than the extra waves hide), so it keeps the sweep's count.
+#ifndef MLCC_FMM_WAVES
+#define MLCC_FMM_WAVES MLCC_SWEEP_WAVES
+#endif
 
 // Blocks with at most this many unconverged roots take the cooperative path.
 constexpr int SPARSE_MAX = 16;
@@ -1711,7 +1718,8 @@ __device__ __forceinline__ void push_front(PQueue *q, int2 *tasks, unsigned long
 }
 
 template <bool EQUAL, bool FMM>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MLCC_SWEEP_WAVES, 8)))
+__global__ void __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(FMM ? MLCC_FMM_WAVES : MLCC_SWEEP_WAVES, 8)))
 aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ fronts_w,
                   PQueue *__restrict__ q, int2 *__restrict__ tasks,
                   unsigned long long *__restrict__ seq, unsigned long long mask,
