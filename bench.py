@@ -490,12 +490,12 @@ def bench_batched(args, wl, precision):
     ctx = mlcc.Context(0)
     torch.cuda.synchronize()
 
-    def step(prec=precision):
+    def step(prec=precision, star_sums=args.star_sums):
         ctx.set_lenses_batched(off, x, y, mm, ks, gs)
         _, _, _, _, cn, st, _ = ctx.find_critical_curves(
             m_steps, n_subchains=args.subchains, timing=True, caustics=True,
             out=(roots_re, roots_im), caustics_out=(w_re, w_im), precision=prec,
-            predictor=args.predictor, schedule=args.schedule)
+            predictor=args.predictor, schedule=args.schedule, star_sums=star_sums)
         return st
 
     for i in range(args.warmup):
@@ -527,7 +527,7 @@ def bench_batched(args, wl, precision):
         "config": {"workload": f"batched: {WORKLOAD_TEXT['batched']}", "fields": len(fs),
                    "total_stars": n_tot, "roots_per_row": 2 * n_tot, "phase_steps": m_steps,
                    "precision": precision, "predictor": args.predictor,
-                   "schedule": args.schedule, "seed": args.seed},
+                   "schedule": args.schedule, "star_sums": args.star_sums, "seed": args.seed},
         "roofline": {"bound": "alu", "kernel": dominant["kernel"],
                      "achieved": dominant["achieved"], "peak": dominant["peak"],
                      "unit": "TFLOP/s", "frac": dominant["frac"], "traffic": None,
@@ -600,6 +600,31 @@ def bench_batched(args, wl, precision):
             "kernels": root_kernels(st2, other),
         }
         log(f"{other}: {1e3 * el2 / args.steps:.0f} ms per step, max root distance {dmax:.2e}")
+    if args.multipole and args.star_sums == "direct":
+        # the same fields with fast-multipole star sums (a grid per field), in
+        # the timed run's precision
+        step(precision, "fmm")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st3 = [step(precision, "fmm") for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        el3 = time.perf_counter() - t0
+        dmax = max(float(cKDTree(b).query(a)[0].max()) for a, b in zip(ref, sample()))
+        out["multipole"] = {
+            precision: {
+                "value": roots_per_step / (el3 / args.steps), "ms_per_step": 1e3 * el3 / args.steps,
+                "steps": args.steps, "warmup": 1,
+                "speedup_over_timed_run": elapsed / el3,
+                "max_root_distance_to_main_run": dmax,
+                "sampled": f"{len(picks)} fields x {len(rows)} rows",
+                "kernels": root_kernels(st3, precision),
+                "stats": {k: st3[-1][k] for k in ("n_subchains", "sweeps", "root_updates",
+                                                  "root_updates_f32", "polish_updates",
+                                                  "fmm_near_terms", "fmm_far_evals")},
+            }
+        }
+        log(f"multipole {precision}: {1e3 * el3 / args.steps:.0f} ms per step, "
+            f"max root distance {dmax:.2e}")
     print(json.dumps(out), flush=True)
 
 

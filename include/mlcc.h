@@ -78,7 +78,9 @@ typedef enum {
     MLCC_STARS_FMM = 1            /* Sec. 4.1: stars binned on a grid; the 3 x 3 cells around a
                                      root summed directly, all others through the cell's local
                                      Taylor expansion (order fmm_order), which is built once per
-                                     call from the far stars; one field per call */
+                                     call from the far stars; in a batched call every field has
+                                     its own grid.  The kernels then take each field's stars in
+                                     cell order, so the seeds z_i +- 1 are numbered in that order */
 } mlcc_star_sums;
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream` (a
@@ -199,8 +201,8 @@ typedef struct {
     int32_t watchdog_ms;   /* MLCC_SCHEDULE_PERSISTENT: the launch gives up, and the call
                               returns MLCC_ERR_HIP, once no pass has finished anywhere for this
                               many milliseconds (0 = 5000; at most 600000) */
-    int32_t star_sums;     /* mlcc_star_sums: how the Aberth sweeps and the polish sum over the
-                              stars (the FP32 sweeps and the few-root passes always directly) */
+    int32_t star_sums;     /* mlcc_star_sums: how the sweeps and the polish sum over the stars
+                              (the FP64 sweep's few-root cooperative passes always directly) */
     int32_t fmm_order;     /* MLCC_STARS_FMM: expansion order p, 8..63 (0 = 48); a far star's
                               terms are truncated after ~0.47^(p+1) of their size */
 } mlcc_cc_params;

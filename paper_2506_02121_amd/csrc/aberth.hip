@@ -593,8 +593,10 @@ __device__ __forceinline__ int fmm_near(const FmmArgs &M, int cell, Body &&body)
 
 // Adds a wave's near-field star terms and far-field evaluations (lanes that
 // updated a root) to the totals behind the algorithmic FLOP count.
+// far[0]: evaluations, far[1]: evaluations times the field's star count
+// (the direct terms they replace).
 __device__ __forceinline__ void fmm_count(unsigned long long *near, unsigned long long *far,
-                                          bool act, int n_near)
+                                          bool act, int n_near, int n_stars)
 {
     int v = act ? n_near : 0;
 #pragma unroll
@@ -602,7 +604,8 @@ __device__ __forceinline__ void fmm_count(unsigned long long *near, unsigned lon
     const int n_act = __popcll(__ballot(act));
     if ((threadIdx.x & 63) == 0 && n_act) {
         atomicAdd(near, (unsigned long long)v);
-        atomicAdd(far, (unsigned long long)n_act);
+        atomicAdd(&far[0], (unsigned long long)n_act);
+        atomicAdd(&far[1], (unsigned long long)n_act * (unsigned long long)n_stars);
     }
 }
 
@@ -630,12 +633,12 @@ template <class T> struct RoundArgs {
     int32_t persistent; // the persistent scheduler: iterates by per-front parity
     double2 *iter0, *iter1;
     const double *sheet; // rectangular fields' sheet records (Real::sheet_off)
-    FmmArgs fmm;         // fast multipole star sums (fmm.on = 0: direct sums)
+    const FmmArgs *fmm;  // fast multipole star sums: one record per field (kernels built with them)
 };
 
 // What one block knows about its front and star field.
 template <class T> struct BlockCtx {
-    int f, q, k0, k, lane, n_r, n_stars, row, stamp, dir, pred;
+    int f, q, r, k0, k, lane, n_r, n_stars, row, stamp, dir, pred;
     int n_poly, n_extra;   // rectangular field: sheet terms and extra roots (else 0)
     const double *sheet;   // its record: d_2k, then d_2k / (2k + 1), then extra seeds
     int vslot;   // this block's slot in the per-block row sums (front order)
@@ -657,6 +660,7 @@ __device__ __forceinline__ bool enter_fq(const RoundArgs<T> &A, int phase, int f
     const Front *F = A.fronts + B.f;
     if (F->state != FRONT_ACTIVE || (phase >= 0 && F->phase != phase)) return false;
     const Real *R = A.reals + F->real;
+    B.r = F->real;
     B.row = F->row;
     B.stamp = F->stamp;
     B.vslot = F->blk0 + B.q;
@@ -843,12 +847,12 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
             int cell;
             double2 f, f1, f2, g;
             double q;
-            fmm_far(A.fmm, zr, zi, cell, f, f1, f2, g, q, true);
-            const int n_near = fmm_near(A.fmm, cell, [&](const double4 &s4) {
+            fmm_far(A.fmm[B.r], zr, zi, cell, f, f1, f2, g, q, true);
+            const int n_near = fmm_near(A.fmm[B.r], cell, [&](const double4 &s4) {
                 if constexpr (EQUAL) add_star<EQUAL>(S, zr, zi, make_double2(s4.x, s4.y));
                 else add_star<EQUAL>(S, zr, zi, s4);
             });
-            fmm_count(&A.ctl->fmm_near, &A.ctl->fmm_far, act, n_near);
+            fmm_count(&A.ctl->fmm_near, A.ctl->fmm_far, act, n_near, n_stars);
             // far terms in the accumulators' conventions (s2i holds -Im/2)
             S.s1r += g.x; S.s1i += g.y;
             if (!EQUAL) { S.s0r += f.x; S.s0i += f.y; }
@@ -964,12 +968,12 @@ __device__ __forceinline__ void sweep_f32_pass(const RoundArgs<typename StarRec<
         int cell;
         double2 f, f1, f2, g;
         double q;
-        fmm_far(A.fmm, zr, zi, cell, f, f1, f2, g, q, true);
-        const int n_near = fmm_near(A.fmm, cell, [&](const double4 &s4) {
+        fmm_far(A.fmm[B.r], zr, zi, cell, f, f1, f2, g, q, true);
+        const int n_near = fmm_near(A.fmm[B.r], cell, [&](const double4 &s4) {
             if constexpr (EQUAL) add_star<EQUAL>(S, zr, zi, make_double2(s4.x, s4.y));
             else add_star<EQUAL>(S, zr, zi, s4);
         });
-        fmm_count(&A.ctl->fmm_near_f32, &A.ctl->fmm_far_f32, valid, n_near);
+        fmm_count(&A.ctl->fmm_near_f32, A.ctl->fmm_far_f32, valid, n_near, n_stars);
         S1r = S.s1r + g.x; S1i = S.s1i + g.y;
         S2r = S.s2r - f1.x; S2i = S.s2i + 0.5 * f1.y;
         S3r = S.s3r + 0.5 * f2.x; S3i = S.s3i + 0.5 * f2.y;
@@ -1235,13 +1239,14 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
                 int cell;
                 double2 f, f1, f2, g;
                 double q;
-                fmm_far(A.fmm, xr, xi, cell, f, f1, f2, g, q, false);
-                const int n_near = fmm_near(A.fmm, cell, [&](const double4 &s4) {
+                fmm_far(A.fmm[B.r], xr, xi, cell, f, f1, f2, g, q, false);
+                const int n_near = fmm_near(A.fmm[B.r], cell, [&](const double4 &s4) {
                     if constexpr (EQUAL)
                         add_star_polish<EQUAL>(S, xr, xi, make_double2(s4.x, s4.y));
                     else add_star_polish<EQUAL>(S, xr, xi, s4);
                 });
-                fmm_count(&A.ctl->fmm_near_polish, &A.ctl->fmm_far_polish, open, n_near);
+                fmm_count(&A.ctl->fmm_near_polish, A.ctl->fmm_far_polish, open, n_near,
+                          n_stars);
                 S.s0r += f.x; S.s0i += f.y;
                 S.s2r -= f1.x; S.s2i += 0.5 * f1.y;
                 S.s3r += 0.5 * f2.x; S.s3i += 0.5 * f2.y;
@@ -1962,101 +1967,131 @@ static int autotune_subchains(const std::vector<RealHost> &reals, int64_t m, boo
 // Host driver
 // ---------------------------------------------------------------------------
 
-// Builds the fast-multipole grid of the (single) field: stars binned and
-// sorted by cell, the expansions about the field centre on the host, the
-// cells' local expansions on the device.
-static mlcc_status build_fmm(Ctx *c, int order, FmmArgs &M)
+// Builds the fast-multipole grids of every field of the call: each field's
+// stars binned and sorted by cell (the kernels then take the stars in that
+// order), its expansions about the field centre on the host, its cells'
+// local expansions on the device; one FmmArgs record per field, with
+// pointers into the concatenated arrays.
+static mlcc_status build_fmm(Ctx *c, int order, bool equal, std::vector<FmmArgs> &recs)
 {
     const std::vector<double4> &st = c->hstars;
-    const int64_t n = (int64_t)st.size();
-    const bool equal = c->equal_mass;
-    double xmin = st[0].x, xmax = st[0].x, ymin = st[0].y, ymax = st[0].y;
-    for (const double4 &a : st) {
-        xmin = std::min(xmin, a.x); xmax = std::max(xmax, a.x);
-        ymin = std::min(ymin, a.y); ymax = std::max(ymax, a.y);
-    }
-    const double cx = 0.5 * (xmin + xmax), cy = 0.5 * (ymin + ymax);
-    double R = 0.0, wsum = 0.0;
-    for (const double4 &a : st) {
-        R = std::max(R, std::hypot(a.x - cx, a.y - cy));
-        wsum += equal ? 1.0 : a.z;
-    }
-    if (!(R > 0.0)) R = 1.0;
-    R *= 1.0 + 1e-12;   // every star strictly inside the radius
-    const int G = (int)std::min<double>(256.0, std::max(4.0, std::round(std::sqrt(1.7 * (double)n))));
     const int pp = order > 0 ? order : 48;
-    const double w = 4.0 * R / G, x0 = cx - 2.0 * R, y0 = cy - 2.0 * R;
-    // counting sort by cell
-    std::vector<int32_t> cell_of(n), start((size_t)G * G + 1, 0);
-    for (int64_t i = 0; i < n; ++i) {
-        const int ix = std::min(G - 1, std::max(0, (int)std::floor((st[i].x - x0) / w)));
-        const int iy = std::min(G - 1, std::max(0, (int)std::floor((st[i].y - y0) / w)));
-        cell_of[i] = iy * G + ix;
-        start[cell_of[i] + 1] += 1;
-    }
-    for (int q = 0; q < G * G; ++q) start[q + 1] += start[q];
-    // sorted by cell; the fourth component carries the cell index
-    std::vector<double4> sorted(n);
-    {
+    const int stride = (pp + 8) & ~7;
+    const int n_real = (int)c->reals.size();
+    struct Grid { int G; double x0, y0, w, cx, cy, R, wsum; int64_t cs_off, cell_off; };
+    std::vector<Grid> grids(n_real);
+    int64_t n_cs = 0, n_cells = 0;
+    const int64_t n_all = (int64_t)st.size();
+    std::vector<double4> sorted(n_all);
+    std::vector<int32_t> starts;
+    std::vector<double2> mm((size_t)n_real * 2 * (pp + 1), make_double2(0.0, 0.0));
+    for (int r = 0; r < n_real; ++r) {
+        const int64_t o = c->reals[r].star_off, n = c->reals[r].n;
+        double xmin = st[o].x, xmax = st[o].x, ymin = st[o].y, ymax = st[o].y;
+        for (int64_t i = o; i < o + n; ++i) {
+            xmin = std::min(xmin, st[i].x); xmax = std::max(xmax, st[i].x);
+            ymin = std::min(ymin, st[i].y); ymax = std::max(ymax, st[i].y);
+        }
+        Grid &g = grids[r];
+        g.cx = 0.5 * (xmin + xmax);
+        g.cy = 0.5 * (ymin + ymax);
+        g.R = 0.0;
+        g.wsum = 0.0;
+        for (int64_t i = o; i < o + n; ++i) {
+            g.R = std::max(g.R, std::hypot(st[i].x - g.cx, st[i].y - g.cy));
+            g.wsum += equal ? 1.0 : st[i].z;
+        }
+        if (!(g.R > 0.0)) g.R = 1.0;
+        g.R *= 1.0 + 1e-12;   // every star strictly inside the radius
+        g.G = (int)std::min<double>(256.0, std::max(4.0, std::round(std::sqrt(1.7 * (double)n))));
+        g.w = 4.0 * g.R / g.G;
+        g.x0 = g.cx - 2.0 * g.R;
+        g.y0 = g.cy - 2.0 * g.R;
+        g.cs_off = n_cs;
+        g.cell_off = n_cells;
+        const int G = g.G;
+        n_cs += (int64_t)G * G + 1;
+        n_cells += (int64_t)G * G;
+        // counting sort by cell; indices local to the field
+        std::vector<int32_t> cell_of(n), start((size_t)G * G + 1, 0);
+        for (int64_t i = 0; i < n; ++i) {
+            const double4 &a = st[o + i];
+            const int ix = std::min(G - 1, std::max(0, (int)std::floor((a.x - g.x0) / g.w)));
+            const int iy = std::min(G - 1, std::max(0, (int)std::floor((a.y - g.y0) / g.w)));
+            cell_of[i] = iy * G + ix;
+            start[cell_of[i] + 1] += 1;
+        }
+        for (int q = 0; q < G * G; ++q) start[q + 1] += start[q];
+        // sorted by cell; the fourth component carries the cell index
         std::vector<int32_t> fill(start.begin(), start.end() - 1);
         for (int64_t i = 0; i < n; ++i) {
-            double4 a = st[i];
+            double4 a = st[o + i];
             a.w = (double)cell_of[i];
-            sorted[fill[cell_of[i]]++] = a;
+            sorted[o + fill[cell_of[i]]++] = a;
+        }
+        starts.insert(starts.end(), start.begin(), start.end());
+        // expansions about the centre: M_k = sum w_i (z_i - c0)^k, and unit weights
+        double2 *mf = mm.data() + (size_t)r * 2 * (pp + 1), *mg = mf + (pp + 1);
+        for (int64_t i = o; i < o + n; ++i) {
+            const double dx = st[i].x - g.cx, dy = st[i].y - g.cy, wi = equal ? 1.0 : st[i].z;
+            double pr = 1.0, pi = 0.0;
+            for (int k = 0; k <= pp; ++k) {
+                mf[k].x += wi * pr; mf[k].y += wi * pi;
+                mg[k].x += pr; mg[k].y += pi;
+                const double t = pr * dx - pi * dy;
+                pi = pr * dy + pi * dx;
+                pr = t;
+            }
         }
     }
-    // expansions about the centre: M_k = sum w_i (z_i - c0)^k, and unit weights
-    std::vector<double2> mm(2 * (pp + 1), make_double2(0.0, 0.0));
-    for (const double4 &a : st) {
-        const double dx = a.x - cx, dy = a.y - cy, wi = equal ? 1.0 : a.z;
-        double pr = 1.0, pi = 0.0;
-        for (int k = 0; k <= pp; ++k) {
-            mm[k].x += wi * pr; mm[k].y += wi * pi;
-            mm[pp + 1 + k].x += pr; mm[pp + 1 + k].y += pi;
-            const double t = pr * dx - pi * dy;
-            pi = pr * dy + pi * dx;
-            pr = t;
-        }
-    }
-    const size_t ncell = (size_t)G * G;
-    const int stride = (pp + 8) & ~7;
-    MLCC_TRY(c->fmm_cs.reserve(start.size() * sizeof(int32_t)));
-    MLCC_TRY(c->fmm_st.reserve(std::max<int64_t>(n, 1) * sizeof(double4)));
-    MLCC_TRY(c->fmm_cf.reserve(ncell * stride * sizeof(double2)));
-    MLCC_TRY(c->fmm_cg.reserve(ncell * stride * sizeof(double2)));
-    MLCC_TRY(c->fmm_q.reserve(ncell * sizeof(double)));
+    MLCC_TRY(c->fmm_cs.reserve(starts.size() * sizeof(int32_t)));
+    MLCC_TRY(c->fmm_st.reserve(std::max<int64_t>(n_all, 1) * sizeof(double4)));
+    MLCC_TRY(c->fmm_st2.reserve(std::max<int64_t>(n_all, 1) * sizeof(double2)));
+    MLCC_TRY(c->fmm_cf.reserve((size_t)n_cells * stride * sizeof(double2)));
+    MLCC_TRY(c->fmm_cg.reserve((size_t)n_cells * stride * sizeof(double2)));
+    MLCC_TRY(c->fmm_q.reserve((size_t)n_cells * sizeof(double)));
     MLCC_TRY(c->fmm_m.reserve(mm.size() * sizeof(double2)));
-    MLCC_HIP(hipMemcpyAsync(c->fmm_cs.p, start.data(), start.size() * sizeof(int32_t),
+    MLCC_TRY(c->fmm_args.reserve((size_t)n_real * sizeof(FmmArgs)));
+    std::vector<double2> sorted2(n_all);
+    for (int64_t i = 0; i < n_all; ++i) sorted2[i] = make_double2(sorted[i].x, sorted[i].y);
+    MLCC_HIP(hipMemcpyAsync(c->fmm_cs.p, starts.data(), starts.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice, c->stream));
-    MLCC_HIP(hipMemcpyAsync(c->fmm_st.p, sorted.data(), n * sizeof(double4), hipMemcpyHostToDevice,
-                            c->stream));
-    std::vector<double2> sorted2(n);
-    for (int64_t i = 0; i < n; ++i) sorted2[i] = make_double2(sorted[i].x, sorted[i].y);
-    MLCC_TRY(c->fmm_st2.reserve(std::max<int64_t>(n, 1) * sizeof(double2)));
-    MLCC_HIP(hipMemcpyAsync(c->fmm_st2.p, sorted2.data(), n * sizeof(double2),
+    MLCC_HIP(hipMemcpyAsync(c->fmm_st.p, sorted.data(), n_all * sizeof(double4),
+                            hipMemcpyHostToDevice, c->stream));
+    MLCC_HIP(hipMemcpyAsync(c->fmm_st2.p, sorted2.data(), n_all * sizeof(double2),
                             hipMemcpyHostToDevice, c->stream));
     MLCC_HIP(hipMemcpyAsync(c->fmm_m.p, mm.data(), mm.size() * sizeof(double2),
                             hipMemcpyHostToDevice, c->stream));
-    hipLaunchKernelGGL(fmm_p2l, dim3((unsigned)ncell), dim3(64), 0, c->stream, G, pp, stride, x0,
-                       y0, w, (int32_t)equal, (int32_t)n, c->fmm_st.as<double4>(),
-                       c->fmm_cf.as<double2>(), c->fmm_cg.as<double2>(), c->fmm_q.as<double>());
+    recs.assign(n_real, FmmArgs{});
+    for (int r = 0; r < n_real; ++r) {
+        const Grid &g = grids[r];
+        const int64_t o = c->reals[r].star_off;
+        FmmArgs &M = recs[r];
+        M.on = 1;
+        M.G = g.G;
+        M.p = pp;
+        M.equal = equal;
+        M.stride = stride;
+        M.x0 = g.x0; M.y0 = g.y0; M.w = g.w; M.inv_w = 1.0 / g.w;
+        M.cx = g.cx; M.cy = g.cy; M.R = g.R; M.wsum = g.wsum;
+        M.cell_start = c->fmm_cs.as<int32_t>() + g.cs_off;
+        M.fstars = c->fmm_st.as<double4>() + o;
+        M.cf = c->fmm_cf.as<double2>() + g.cell_off * stride;
+        M.cg = c->fmm_cg.as<double2>() + g.cell_off * stride;
+        M.qfar = c->fmm_q.as<double>() + g.cell_off;
+        M.mf = c->fmm_m.as<double2>() + (size_t)r * 2 * (pp + 1);
+        M.mg = M.mf + (pp + 1);
+        const unsigned ncell = (unsigned)((int64_t)g.G * g.G);
+        hipLaunchKernelGGL(fmm_p2l, dim3(ncell), dim3(64), 0, c->stream, g.G, pp, stride, g.x0,
+                           g.y0, g.w, (int32_t)equal, (int32_t)c->reals[r].n, M.fstars,
+                           const_cast<double2 *>(M.cf), const_cast<double2 *>(M.cg),
+                           const_cast<double *>(M.qfar));
+    }
     MLCC_HIP(hipGetLastError());
+    MLCC_HIP(hipMemcpyAsync(c->fmm_args.p, recs.data(), recs.size() * sizeof(FmmArgs),
+                            hipMemcpyHostToDevice, c->stream));
     // host vectors must outlive the copies
     MLCC_HIP(hipStreamSynchronize(c->stream));
-    M.on = 1;
-    M.G = G;
-    M.p = pp;
-    M.equal = equal;
-    M.stride = stride;
-    M.x0 = x0; M.y0 = y0; M.w = w; M.inv_w = 1.0 / w;
-    M.cx = cx; M.cy = cy; M.R = R; M.wsum = wsum;
-    M.cell_start = c->fmm_cs.as<int32_t>();
-    M.fstars = c->fmm_st.as<double4>();
-    M.cf = c->fmm_cf.as<double2>();
-    M.cg = c->fmm_cg.as<double2>();
-    M.qfar = c->fmm_q.as<double>();
-    M.mf = c->fmm_m.as<double2>();
-    M.mg = c->fmm_m.as<double2>() + (pp + 1);
     return MLCC_OK;
 }
 
@@ -2210,17 +2245,19 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     if (mixed) MLCC_TRY(c->errbuf.reserve((size_t)it_total * sizeof(double)));
     MLCC_TRY(c->reals_d.reserve((size_t)n_real * sizeof(Real)));
     MLCC_TRY(c->sheet.reserve(std::max<size_t>(1, sheet_host.size()) * sizeof(double)));
-    FmmArgs fmm{};
-    // With multipole sums the kernels take the stars in cell order, so that
-    // the seeds z_i +- 1 of a work group's roots, and the roots grown from
-    // them, share a few cells (and those cells' series) instead of 64.
+    // With multipole sums the kernels take each field's stars in cell order,
+    // so that the seeds z_i +- 1 of a work group's roots, and the roots grown
+    // from them, share a few cells (and those cells' series) instead of 64.
+    std::vector<FmmArgs> fmm_recs;
+    const bool fmm_on = p->star_sums == MLCC_STARS_FMM;
     const double2 *stars2 = c->stars.as<double2>();
     const double4 *stars4 = c->stars4.as<double4>();
-    if (p->star_sums == MLCC_STARS_FMM) {
-        MLCC_TRY(build_fmm(c, p->fmm_order, fmm));
+    if (fmm_on) {
+        MLCC_TRY(build_fmm(c, p->fmm_order, equal, fmm_recs));
         stars2 = c->fmm_st2.as<double2>();
         stars4 = c->fmm_st.as<double4>();
     }
+    const FmmArgs *fmm_dev = fmm_on ? c->fmm_args.as<FmmArgs>() : nullptr;
     MLCC_TRY(c->bmap.reserve((size_t)ngrid * sizeof(int2)));
     MLCC_TRY(c->workflags.reserve(2 * MAX_BATCH * sizeof(int32_t)));
     MLCC_TRY(ensure_pinned(c, 2 * (sizeof(Control) + MAX_BATCH * sizeof(int32_t))));
@@ -2295,7 +2332,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         A.predictor = p->predictor;
         A.errbuf = mixed ? c->errbuf.as<double>() : nullptr;
         A.sheet = c->sheet.as<double>();
-        A.fmm = fmm;
+        A.fmm = fmm_dev;
     };
     const dim3 grid((unsigned)ngrid);
     auto launch_kind = [&](int kind, const double2 *cur, double2 *nxt) {
@@ -2311,10 +2348,10 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         using F_ = std::false_type;
         if (equal) {
             fill(A2, stars2, cur, nxt);
-            if (fmm.on) go(A2, T_{}, T_{}); else go(A2, T_{}, F_{});
+            if (fmm_on) go(A2, T_{}, T_{}); else go(A2, T_{}, F_{});
         } else {
             fill(A4, stars4, cur, nxt);
-            if (fmm.on) go(A4, F_{}, T_{}); else go(A4, F_{}, F_{});
+            if (fmm_on) go(A4, F_{}, T_{}); else go(A4, F_{}, F_{});
         }
     };
 
@@ -2486,9 +2523,9 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         MLCC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
         MLCC_HIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, c->device));
         const void *kfn =
-            equal ? (fmm.on ? reinterpret_cast<const void *>(&aberth_persistent<true, true>)
+            equal ? (fmm_on ? reinterpret_cast<const void *>(&aberth_persistent<true, true>)
                             : reinterpret_cast<const void *>(&aberth_persistent<true, false>))
-                  : (fmm.on ? reinterpret_cast<const void *>(&aberth_persistent<false, true>)
+                  : (fmm_on ? reinterpret_cast<const void *>(&aberth_persistent<false, true>)
                             : reinterpret_cast<const void *>(&aberth_persistent<false, false>));
         MLCC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 64, 0));
         if (cus < 1 || per_cu < 1 || clock_khz < 1)
@@ -2510,7 +2547,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
             A2.persistent = 1;
             A2.iter0 = c->iter[0].as<double2>();
             A2.iter1 = c->iter[1].as<double2>();
-            if (fmm.on)
+            if (fmm_on)
                 hipLaunchKernelGGL((aberth_persistent<true, true>), dim3(workers), dim3(64), 0, rs,
                                    A2, c->fronts.as<Front>(), dq, dtasks, dseq,
                                    (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
@@ -2525,7 +2562,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
             A4.persistent = 1;
             A4.iter0 = c->iter[0].as<double2>();
             A4.iter1 = c->iter[1].as<double2>();
-            if (fmm.on)
+            if (fmm_on)
                 hipLaunchKernelGGL((aberth_persistent<false, true>), dim3(workers), dim3(64), 0, rs,
                                    A4, c->fronts.as<Front>(), dq, dtasks, dseq,
                                    (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
@@ -2744,19 +2781,19 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         // the FP32 count to the FP64 one.
         double star64 = (double)h.star_updates, starpol = (double)h.star_updates_polish;
         double far64 = 0.0, farpol = 0.0, star32_off = 0.0;
-        if (fmm.on) {
-            const double nf = (double)c->n;
-            const double pf = (double)fmm.p;
-            const double unit_g = fmm.equal ? 0.0 : 8.0 * pf;
-            far64 = (double)h.fmm_far * (26.0 * pf + 20.0 + unit_g) +
-                    (double)h.fmm_far_f32 * (26.0 * pf + 20.0 + unit_g) +
+        if (fmm_on) {
+            const double pf = (double)fmm_recs[0].p;
+            const double unit_g = equal ? 0.0 : 8.0 * pf;
+            far64 = (double)h.fmm_far[0] * (26.0 * pf + 20.0 + unit_g) +
+                    (double)h.fmm_far_f32[0] * (26.0 * pf + 20.0 + unit_g) +
                     29.0 * (double)h.fmm_near_f32;
-            farpol = (double)h.fmm_far_polish * (26.0 * pf + 20.0);
-            star64 += (double)h.fmm_near - nf * (double)h.fmm_far;
-            starpol += (double)h.fmm_near_polish - nf * (double)h.fmm_far_polish;
-            star32_off = 29.0 * nf * (double)h.fmm_far_f32;
+            farpol = (double)h.fmm_far_polish[0] * (26.0 * pf + 20.0);
+            star64 += (double)h.fmm_near - (double)h.fmm_far[1];
+            starpol += (double)h.fmm_near_polish - (double)h.fmm_far_polish[1];
+            star32_off = 29.0 * (double)h.fmm_far_f32[1];
             stats->fmm_near_terms = (int64_t)(h.fmm_near + h.fmm_near_polish + h.fmm_near_f32);
-            stats->fmm_far_evals = (int64_t)(h.fmm_far + h.fmm_far_polish + h.fmm_far_f32);
+            stats->fmm_far_evals =
+                (int64_t)(h.fmm_far[0] + h.fmm_far_polish[0] + h.fmm_far_f32[0]);
         }
         stats->algorithmic_flop = 29.0 * star64 + far64 +
                                   20.0 * (double)(h.star_updates - h.star_updates_fast) -

@@ -184,7 +184,7 @@ void mlcc_destroy(mlcc_ctx *ctx)
                       &c.match_aux, &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.vsum,
                       &c.pq, &c.passupd, &c.reals_d, &c.bmap, &c.diff, &c.err, &c.edt_col,
                       &c.dmask, &c.fmm_cs, &c.fmm_st, &c.fmm_st2, &c.fmm_cf, &c.fmm_cg,
-                      &c.fmm_q, &c.fmm_m};
+                      &c.fmm_q, &c.fmm_m, &c.fmm_args};
     for (DevBuf *b : bufs) b->release();
     if (c.own_stream) (void)hipStreamDestroy(c.own_stream);
     if (c.pinned) (void)hipHostFree(c.pinned);
@@ -473,8 +473,6 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
         return fail(MLCC_ERR_INVALID, "a rectangular field is solved in MLCC_FP64 only");
     if (p.star_sums != MLCC_STARS_DIRECT && p.star_sums != MLCC_STARS_FMM)
         return fail(MLCC_ERR_INVALID, "unknown star_sums %d", p.star_sums);
-    if (p.star_sums == MLCC_STARS_FMM && c.batched)
-        return fail(MLCC_ERR_INVALID, "MLCC_STARS_FMM takes one field per call");
     if (p.fmm_order != 0 && (p.fmm_order < 8 || p.fmm_order > 63))
         return fail(MLCC_ERR_INVALID, "fmm_order must be 0 or 8..63 (got %d)", p.fmm_order);
     MLCC_TRY(check_device_ptr(&c, roots_re, "roots_re"));

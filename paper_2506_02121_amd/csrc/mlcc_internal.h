@@ -145,12 +145,12 @@ struct Control {
     unsigned long long star_updates_polish;
     unsigned long long updates_fast;      // FP64 Aberth updates of warm FP64-mode rows, whose
     unsigned long long star_updates_fast; // root-root terms run in FP32 (and their star counts)
-    // fast-multipole star sums: near-field star terms and far-field series
-    // evaluations of the updates that took them (FP64 sweeps; polish; FP32
-    // sweeps)
-    unsigned long long fmm_near, fmm_far;
-    unsigned long long fmm_near_polish, fmm_far_polish;
-    unsigned long long fmm_near_f32, fmm_far_f32;
+    // fast-multipole star sums: near-field star terms, far-field series
+    // evaluations ([0]) and those evaluations times their field's star count
+    // ([1]) of the updates that took them (FP64 sweeps; polish; FP32 sweeps)
+    unsigned long long fmm_near, fmm_far[2];
+    unsigned long long fmm_near_polish, fmm_far_polish[2];
+    unsigned long long fmm_near_f32, fmm_far_f32[2];
 };
 
 struct Ctx {
@@ -201,7 +201,7 @@ struct Ctx {
     // fast multipole star sums: the stars sorted by grid cell and each cell's
     // expansions (built by the root finder when asked for)
     std::vector<double4> hstars;   // host copy of the stars (x, y, m, 0)
-    DevBuf fmm_cs, fmm_st, fmm_st2, fmm_cf, fmm_cg, fmm_q, fmm_m;
+    DevBuf fmm_cs, fmm_st, fmm_st2, fmm_cf, fmm_cg, fmm_q, fmm_m, fmm_args;
 
     void *pinned = nullptr; // host-pinned readback area
     size_t pinned_bytes = 0;

@@ -3,7 +3,8 @@ which sums every star directly: root sets within the conditioning-aware
 bound, chains column for column once the first cold start's labelling is
 matched, caustics within their bound, in FP64 and mixed precision, for equal
 and unequal masses, a rectangular field, and a pair of stars whose outer critical
-curve lies entirely outside the grid (the expansion about the field centre)."""
+curve lies entirely outside the grid (the expansion about the field centre),
+and batched calls of fields of uneven N, each with its own grid."""
 import numpy as np
 import pytest
 
@@ -166,10 +167,54 @@ def test_fmm_arguments(ctx, mlcc):
             ctx.find_critical_curves(20, star_sums="fmm", fmm_order=order)
     rr, ri, cn, st, code = ctx.find_critical_curves(20, star_sums="fmm", fmm_order=20)
     assert code == 0
-    fs = [fields.random_field(57 + i, 10) for i in range(2)]
-    off = [0, 10, 20]
-    ctx.set_lenses_batched(off, dev(np.concatenate([g.x for g in fs])),
-                           dev(np.concatenate([g.y for g in fs])),
-                           dev(np.concatenate([g.m for g in fs])), [0.0, 0.0], [0.3, 0.3])
-    with pytest.raises(mlcc.MlccError):
-        ctx.find_critical_curves(20, star_sums="fmm")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fmm_batched_matches_oracle(ctx, precision):
+    """Fields of uneven N in one batched call, each with its own grid: every
+    field's root sets against the oracle's (direct sums), closure, caustics,
+    and the same call with direct sums."""
+    say("fmm batched", precision)
+    sizes = [12, 30, 45, 80]
+    fs = [fields.random_field(60 + i, n, kappa_star=0.3 + 0.1 * i, gamma=0.2 + 0.08 * i,
+                              masses="salpeter") for i, n in enumerate(sizes)]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    m_steps = 120
+    out = {}
+    for ss in ("direct", "fmm"):
+        ctx.set_lenses_batched(off, dev(np.concatenate([g.x for g in fs])),
+                               dev(np.concatenate([g.y for g in fs])),
+                               dev(np.concatenate([g.m for g in fs])),
+                               [g.kappa_s for g in fs], [g.gamma for g in fs])
+        rr, ri, cr, ci, cn, st, code = ctx.find_critical_curves(m_steps, caustics=True,
+                                                                precision=precision,
+                                                                star_sums=ss)
+        torch.cuda.synchronize()
+        assert code == 0
+        out[ss] = (host_c(rr, ri), host_c(cr, ci), cn.cpu().numpy(), st)
+    blocks = ctx.field_blocks(m_steps)
+    R_all, W_all, cn_all, st = out["fmm"]
+    assert st["fmm_far_evals"] > 0
+    for f, (o, co, n_r) in zip(fs, blocks):
+        R = R_all[o:o + (m_steps + 1) * n_r].reshape(m_steps + 1, n_r)
+        W = W_all[o:o + (m_steps + 1) * n_r].reshape(m_steps + 1, n_r)
+        c_f = cn_all[co:co + n_r]
+        assert sorted(c_f.tolist()) == list(range(n_r))
+        assert np.max(np.abs(R[-1] - R[0][c_f])) < 1e-8
+        R_ref, _, _ = oracle.critical_curves(f, m_steps, n_sub=1)
+        Fp = np.stack([oracle.eval_F(f, oracle.phase(j, m_steps), R_ref[j])[1]
+                       for j in range(m_steps + 1)])
+        bound = parity.root_bound(f, Fp)
+        worst, ratio = parity.compare_row_sets(R, R_ref, bound)
+        assert ratio <= 1.0, (f.n, worst, ratio)
+        W_ref = oracle.lens_map(f, R_ref)
+        for j in range(m_steps + 1):
+            idx, _ = parity.pair(R_ref[j], R[j])
+            bw = 2 * abs(1 - f.kappa_s) * bound[j] + 1e-11 * (1 + np.abs(W_ref[j]))
+            assert np.all(np.abs(W[j][idx] - W_ref[j]) <= bw), (f.n, j)
+        # against the direct-sum call: the same root sets
+        Rd = out["direct"][0][o:o + (m_steps + 1) * n_r].reshape(m_steps + 1, n_r)
+        dd = max(float(parity.pair(Rd[j], R[j])[1].max()) for j in range(0, m_steps + 1, 10))
+        print(f"[fmm batched {precision} N={f.n}] roots {worst:.3e} (ratio {ratio:.3f}), "
+              f"direct vs multipole {dd:.3e}", flush=True)
+        assert dd < 1e-10
