@@ -328,8 +328,14 @@ def main():
         for prec_m in (["fp64"] if f.sheet is not None else ["fp64", "mixed"]):
             saved = args.star_sums
             args.star_sums = "fmm"
-            el3, st3 = run(prec_m, 1, args.steps)
-            args.star_sums = saved
+            try:
+                el3, st3 = run(prec_m, 1, args.steps)
+            except mlcc.MlccError as e:   # reported, not fatal to the timed run's line
+                out["multipole"][prec_m] = {"error": str(e)}
+                log(f"multipole {prec_m}: {e}")
+                continue
+            finally:
+                args.star_sums = saved
             k3 = root_kernels(st3, prec_m)
             out["multipole"][prec_m] = {
                 "value": roots_per_step / (el3 / args.steps), "ms_per_step": 1e3 * el3 / args.steps,
@@ -610,12 +616,18 @@ def bench_batched(args, wl, precision):
     if args.multipole and args.star_sums == "direct":
         # the same fields with fast-multipole star sums (a grid per field), in
         # the timed run's precision
-        step(precision, "fmm")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st3 = [step(precision, "fmm") for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        el3 = time.perf_counter() - t0
+        try:
+            step(precision, "fmm")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st3 = [step(precision, "fmm") for _ in range(args.steps)]
+            torch.cuda.synchronize()
+            el3 = time.perf_counter() - t0
+        except mlcc.MlccError as e:   # reported, not fatal to the timed run's line
+            out["multipole"] = {precision: {"error": str(e)}}
+            log(f"multipole {precision}: {e}")
+            print(json.dumps(out), flush=True)
+            return
         dmax = max(float(cKDTree(b).query(a)[0].max()) for a, b in zip(ref, sample()))
         out["multipole"] = {
             precision: {

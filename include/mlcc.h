@@ -251,6 +251,9 @@ typedef struct {
                                 (8 p more in sweeps of unequal masses).  FP32 sweeps take these
                                 sums in FP64: their star part counts in algorithmic_flop, their
                                 root terms stay in algorithmic_flop_f32 */
+    int64_t cold_restarts;   /* FP64 cold starts still unsettled after 100 sweeps and begun again
+                                from the second set of start values (z_i +- i; a rectangular
+                                sheet's extra roots turned by half their spacing) */
 } mlcc_cc_stats;
 
 /*

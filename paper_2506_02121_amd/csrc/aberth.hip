@@ -350,6 +350,10 @@ __device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0
 // Blocks with at most this many unconverged roots take the cooperative path.
 constexpr int SPARSE_MAX = 16;
 
+// An FP64 cold start still unsettled after this many sweeps (cold starts
+// take 11-30) starts again from the second set of start values.
+constexpr int STALL_START = 100;
+
 // Newton steps a root may take within one polish pass with multipole sums.
 constexpr int FMM_POLISH_STEPS = 3;
 
@@ -762,15 +766,24 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
     using T = typename StarRec<EQUAL>::T;
     if (A.fronts[B.f].reseed) {
         // restart the row from its start values: the seeds z_i +- 1 for a
-        // cold start, the previous row of the subchain otherwise
+        // cold start, the previous row of the subchain otherwise.  The second
+        // set for a stalled cold start: z_i +- i, and the extra roots of a
+        // rectangular sheet turned by half their spacing.
+        const bool second = A.fronts[B.f].seedvar > 0;
         if (B.valid) {
             double2 z;
             if (B.dir == 0 && B.k >= 2 * B.n_stars) {   // a rectangular sheet's extra root
                 const int x = B.k - 2 * B.n_stars;
                 z = make_double2(B.sheet[2 * B.n_poly + 2 * x], B.sheet[2 * B.n_poly + 2 * x + 1]);
+                if (second) {
+                    double sn, cs;
+                    sincos(M_PI / (double)B.n_extra, &sn, &cs);
+                    z = make_double2(z.x * cs - z.y * sn, z.x * sn + z.y * cs);
+                }
             } else if (B.dir == 0) {
                 const T st = B.stars[B.k >> 1];
-                z = make_double2(st.x + ((B.k & 1) ? -1.0 : 1.0), st.y);
+                const double o = (B.k & 1) ? -1.0 : 1.0;
+                z = second ? make_double2(st.x, st.y + o) : make_double2(st.x + o, st.y);
             } else {
                 const int64_t o = B.out_off + (int64_t)(B.row - B.dir) * B.n_r + B.k;
                 z = make_double2(A.out_re[o], A.out_im[o]);
@@ -1518,7 +1531,15 @@ __device__ __attribute__((noinline)) int advance_front(Front &fr, int f, int32_t
         partner = row_converged(fr, f, fronts, st, f0, predictor);
     } else {
         fr.sweeps += 1;
-        if (fr.sweeps >= (fr.dir == 0 ? max_cold : max_warm)) {
+        if (fr.dir == 0 && fr.phase == PH_F64 && fr.seedvar == 0 && fr.sweeps >= STALL_START &&
+            fr.sweeps < max_cold) {
+            // a stalled cold start: once, all over again from other seeds
+            fr.seedvar = 1;
+            fr.reseed = 1;
+            fr.stamp += 1;
+            fr.sweeps = 0;
+            atomicAdd((unsigned long long *)&ctl->cold_restarts, 1ull);
+        } else if (fr.sweeps >= (fr.dir == 0 ? max_cold : max_warm)) {
             fr.state = FRONT_FAILED;
             if (st) st[f - f0] = FRONT_FAILED;
             atomicAdd(&ctl->failed_rows, 1);
@@ -2744,6 +2765,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         stats->polish_updates = (int64_t)h.polish_updates;
         stats->unconverged = h.unconverged;
         stats->rows_capped = h.failed_rows;
+        stats->cold_restarts = h.cold_restarts;
         stats->rows_fallback = h.rows_fallback;
         stats->n_subchains = S;
         int32_t mw = 0, mc = 0;

@@ -75,6 +75,7 @@ struct Front {
     int32_t reseed;   // 1: the next FP64 pass restarts the row from its start values
     int32_t par;      // persistent scheduler: which iterate buffer holds the current values
     int32_t npass;    // passes run by this front (all rows)
+    int32_t seedvar;  // cold start: 0 = the seeds z_i +- 1; 1 = the second set (after a stall)
     int64_t it_off;   // first element of its roots in the iterate and flag arrays
 };
 
@@ -140,6 +141,7 @@ struct Control {
     unsigned long long polish_updates;
     int64_t rows_fallback;            // rows that fell back to FP64 sweeps
     int64_t live_sweeps;              // rounds that found an active front
+    int64_t cold_restarts;            // FP64 cold starts begun again from the second seeds
     unsigned long long star_updates;  // sum over FP64 updates of the field's star count
     unsigned long long star_updates_f32;
     unsigned long long star_updates_polish;

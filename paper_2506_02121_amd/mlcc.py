@@ -66,7 +66,8 @@ class CCStats(ctypes.Structure):
                 ("algorithmic_flop_polish", ctypes.c_double),
                 ("persistent_ms", ctypes.c_double), ("persistent_launches", ctypes.c_int64),
                 ("algorithmic_flop_sweep_roots", ctypes.c_double),
-                ("fmm_near_terms", ctypes.c_int64), ("fmm_far_evals", ctypes.c_int64)]
+                ("fmm_near_terms", ctypes.c_int64), ("fmm_far_evals", ctypes.c_int64),
+                ("cold_restarts", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -168,3 +168,33 @@ def test_rect_arguments(ctx, mlcc):
     g = fields.random_field(2, 10)
     ctx.set_lenses(dev(g.x), dev(g.y), dev(g.m), g.kappa_s, g.gamma)
     assert ctx.num_roots() == 20
+
+
+def test_rect_stalled_cold_start_recovers(ctx):
+    """The rectangular workload's field with 250 subchains: the cold start at
+    row 13160 left one iterate parked far from every root for the whole
+    sweep cap, before a cold start unsettled after 100 sweeps began again
+    from the second set of start values.  Rows of that subchain, and rows
+    elsewhere, against cold-started oracle rows."""
+    say("rect stalled cold start")
+    wl = fields.workload("rect")
+    f, m_steps = wl.field, wl.m_steps
+    set_rect(ctx, f)
+    rr, ri, cn, st, code = ctx.find_critical_curves(m_steps, n_subchains=250,
+                                                    raise_on_error=False)
+    torch.cuda.synchronize()
+    print("[stats]", {k: st[k] for k in ("n_subchains", "sweeps", "cold_sweeps",
+                                         "unconverged", "cold_restarts")}, flush=True)
+    assert code == 0 and st["unconverged"] == 0 and st["cold_restarts"] >= 1
+    R = host_c(rr, ri)
+    cnh = cn.cpu().numpy()
+    assert np.max(np.abs(R[-1] - R[0][cnh])) < 1e-8
+    worst = 0.0
+    for j in (13121, 13140, 13160, 13180, 13199, 0, 10000):
+        phi = oracle.phase(j, m_steps)
+        z_ref, _, _, _ = oracle.aberth_row(f, phi)
+        Fp = oracle.eval_F(f, phi, z_ref)[1]
+        idx, d = parity.pair(z_ref, R[j])
+        assert np.all(d <= parity.root_bound(f, Fp)), j
+        worst = max(worst, float(d.max()))
+    print(f"[rect stall] sampled rows within {worst:.3e} of the oracle", flush=True)
