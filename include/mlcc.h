@@ -204,7 +204,9 @@ typedef struct {
     int32_t star_sums;     /* mlcc_star_sums: how the sweeps and the polish sum over the stars
                               (the FP64 sweep's few-root cooperative passes always directly) */
     int32_t fmm_order;     /* MLCC_STARS_FMM: expansion order p, 8..63 (0 = 48); a far star's
-                              terms are truncated after ~0.47^(p+1) of their size */
+                              terms are truncated after ~0.47^(p+1) of their size.  Below
+                              p ~ 28 the jumps of F between neighbouring cells exceed what the
+                              1e-9 cutoffs resolve, and roots near cell borders may not settle */
 } mlcc_cc_params;
 
 /* The paper's cutoffs (Sec. 3.2 footnote: 1e-9 and |mu| > 1e9),

@@ -218,3 +218,29 @@ def test_fmm_batched_matches_oracle(ctx, precision):
         print(f"[fmm batched {precision} N={f.n}] roots {worst:.3e} (ratio {ratio:.3f}), "
               f"direct vs multipole {dd:.3e}", flush=True)
         assert dd < 1e-10
+
+
+def test_fmm_truncation_shrinks_with_order(ctx):
+    """The series' truncation after order p leaves ~0.47^(p+1) of each far
+    term: the roots' distance to the direct-sum roots falls with p, to
+    rounding level at the default order.  (Much lower orders leave jumps in F
+    between neighbouring cells larger than the cutoffs resolve.)"""
+    say("fmm order sweep")
+    f = fields.random_field(58, 300, kappa_star=0.5, gamma=0.3, masses="salpeter")
+    load(ctx, f)
+    rr, ri, cn, st, code = ctx.find_critical_curves(60, n_subchains=2, star_sums="direct")
+    torch.cuda.synchronize()
+    R_d = host_c(rr, ri)
+    dist = {}
+    for p in (28, 36, 48):
+        rr, ri, cn, st, code = ctx.find_critical_curves(60, n_subchains=2, star_sums="fmm",
+                                                        fmm_order=p)
+        torch.cuda.synchronize()
+        assert code == 0
+        R = host_c(rr, ri)
+        dist[p] = max(float(parity.pair(R_d[j], R[j])[1].max()) for j in range(61))
+    print("[fmm order] distance to direct sums by order:",
+          {p: f"{d:.2e}" for p, d in dist.items()}, flush=True)
+    assert dist[28] > 10 * dist[48] and dist[28] >= dist[36]
+    assert dist[48] < 1e-12
+    assert dist[28] < 1e-7
