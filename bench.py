@@ -540,7 +540,9 @@ def bench_batched(args, wl, precision):
                    "schedule": args.schedule, "star_sums": args.star_sums, "seed": args.seed},
         "roofline": {"bound": "alu", "kernel": dominant["kernel"],
                      "achieved": dominant["achieved"], "peak": dominant["peak"],
-                     "unit": "TFLOP/s", "frac": dominant["frac"], "traffic": None,
+                     "unit": "TFLOP/s", "frac": dominant["frac"],
+                     "traffic": (measured_traffic(dominant["kernel"], "batched")
+                                 if args.star_sums == "direct" else None),
                      "avg_launch_ms": dominant["avg_launch_ms"],
                      "launches": dominant["launches"],
                      "frac_of_fp64_peak": (dominant["achieved"] / FP64_VECTOR_PEAK_TFLOPS
