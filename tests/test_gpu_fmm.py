@@ -244,3 +244,22 @@ def test_fmm_truncation_shrinks_with_order(ctx):
     assert dist[28] > 10 * dist[48] and dist[28] >= dist[36]
     assert dist[48] < 1e-12
     assert dist[28] < 1e-7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fmm_schedules_agree_bitwise(ctx, precision):
+    """The round schedule (one launch per pass kind and round) and the
+    persistent one run the same multipole passes on the same data."""
+    say("fmm schedules", precision)
+    f = fields.random_field(59, 200, kappa_star=0.45, gamma=0.3, masses="salpeter")
+    load(ctx, f)
+    out = []
+    for sched in ("rounds", "persistent"):
+        rr, ri, cr, ci, cn, st, code = ctx.find_critical_curves(120, n_subchains=3, caustics=True,
+                                                                precision=precision,
+                                                                star_sums="fmm", schedule=sched)
+        torch.cuda.synchronize()
+        assert code == 0
+        out.append([t.cpu().numpy() for t in (rr, ri, cr, ci, cn)])
+    for a, b in zip(*out):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
