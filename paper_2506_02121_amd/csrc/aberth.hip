@@ -105,6 +105,35 @@ __device__ __forceinline__ void stream_tiles(const T *__restrict__ p, int n, T *
     stream_tiles_ex(p, n, lds, Same{}, body, NoEnd{});
 }
 
+// The same stream, records taken two at a time: two(a, b) for consecutive
+// records, one(a) for the last of an odd count.  The terms meet the sums in
+// the same order as with stream_tiles.
+template <class T, class One, class Two>
+__device__ __forceinline__ void stream_tiles_pairs(const T *__restrict__ p, int n, T *lds, One &&one,
+                                                   Two &&two)
+{
+    if (n <= 0) return;
+    const int lane = threadIdx.x;
+    const int ntiles = (n + 63) >> 6;
+    T reg = p[min(lane, n - 1)];
+    for (int t = 0; t < ntiles; ++t) {
+        T *buf = lds + ((t & 1) << 6);
+        buf[lane] = reg;
+        __syncthreads();
+        if (t + 1 < ntiles) reg = p[min(((t + 1) << 6) + lane, n - 1)];
+        const int cnt = min(64, n - (t << 6));
+        if (cnt == 64) {
+#pragma unroll 4
+            for (int k = 0; k < 64; k += 2) two(buf[k], buf[k + 1]);
+        } else {
+            int k = 0;
+            for (; k + 1 < cnt; k += 2) two(buf[k], buf[k + 1]);
+            if (k < cnt) one(buf[k]);
+        }
+    }
+    __syncthreads();
+}
+
 // Star records: (x, y) when all masses are equal (the common mass is applied
 // once at the end), (x, y, m, 0) otherwise.
 template <bool EQUAL> struct StarRec;
@@ -145,12 +174,45 @@ __device__ __forceinline__ void zero(Sums &S)
     S.s1r = S.s1i = S.s0r = S.s0i = S.s2r = S.s2i = S.s3r = S.s3i = S.Rr = S.Ri = 0.0;
 }
 
+// Two reciprocals for the price of one: 1/a = b/(ab), 1/b = a/(ab), with the
+// refined reciprocal of the product (the same ~2^-47 relative error).  The
+// quarter-rate v_rcp_f64 and its Newton step are ~24% of a star term's issue
+// cycles.  A zero distance makes both terms non-finite, as it makes its own
+// term non-finite alone, and the iterate is nudged either way.
+__device__ __forceinline__ void rcp_pair(double a, double b, double &ia, double &ib)
+{
+    const double ip = rcp_refined<RCP_STAR>(a * b);
+    ia = b * ip;
+    ib = a * ip;
+}
+
+template <bool EQUAL, class T>
+__device__ __forceinline__ void add_star_inv(Sums &S, double dx, double dy, double inv,
+                                             const T &s);
+
 template <bool EQUAL, class T>
 __device__ __forceinline__ void add_star(Sums &S, double zr, double zi, const T &s)
 {
     const double dx = zr - s.x;
     const double dy = zi - s.y;
-    const double inv = rcp_refined<RCP_STAR>(fma(dx, dx, dy * dy));
+    add_star_inv<EQUAL>(S, dx, dy, rcp_refined<RCP_STAR>(fma(dx, dx, dy * dy)), s);
+}
+
+template <bool EQUAL, class T>
+__device__ __forceinline__ void add_star_pair(Sums &S, double zr, double zi, const T &s,
+                                              const T &t)
+{
+    const double dx = zr - s.x, dy = zi - s.y, ex = zr - t.x, ey = zi - t.y;
+    double is, it;
+    rcp_pair(fma(dx, dx, dy * dy), fma(ex, ex, ey * ey), is, it);
+    add_star_inv<EQUAL>(S, dx, dy, is, s);
+    add_star_inv<EQUAL>(S, ex, ey, it, t);
+}
+
+template <bool EQUAL, class T>
+__device__ __forceinline__ void add_star_inv(Sums &S, double dx, double dy, double inv,
+                                             const T &s)
+{
     // u = conj(d) / |d|^2 = ux - i uy, with a = ux^2, b = uy^2:
     //   u^2 = (a - b) - 2 i ux uy,   u^3 = ux (a - 3b) + i uy (b - 3a)
     const double ux = dx * inv;
@@ -872,8 +934,11 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
             S.s2r -= f1.x; S.s2i += 0.5 * f1.y;
             S.s3r += 0.5 * f2.x; S.s3i += 0.5 * f2.y;
         } else {
-            stream_tiles(stars, n_stars, reinterpret_cast<T *>(tiles),
-                         [&](int, const T &s) { add_star<EQUAL>(S, zr, zi, s); });
+            stream_tiles_pairs(stars, n_stars, reinterpret_cast<T *>(tiles),
+                               [&](const T &s) { add_star<EQUAL>(S, zr, zi, s); },
+                               [&](const T &s, const T &t) {
+                                   add_star_pair<EQUAL>(S, zr, zi, s, t);
+                               });
         }
         if (!fast_roots_pass(A.fronts[B.f])) {
             double2 *rtiles = reinterpret_cast<double2 *>(tiles);
@@ -1100,11 +1165,32 @@ __device__ __forceinline__ void zero(PSums &S)
 }
 
 template <bool EQUAL, class T>
+__device__ __forceinline__ void add_star_polish_inv(PSums &S, double dx, double dy, double inv,
+                                                    const T &s);
+
+template <bool EQUAL, class T>
 __device__ __forceinline__ void add_star_polish(PSums &S, double zr, double zi, const T &s)
 {
     const double dx = zr - s.x;
     const double dy = zi - s.y;
-    const double inv = rcp_refined<RCP_STAR>(fma(dx, dx, dy * dy));
+    add_star_polish_inv<EQUAL>(S, dx, dy, rcp_refined<RCP_STAR>(fma(dx, dx, dy * dy)), s);
+}
+
+template <bool EQUAL, class T>
+__device__ __forceinline__ void add_star_polish_pair(PSums &S, double zr, double zi, const T &s,
+                                                     const T &t)
+{
+    const double dx = zr - s.x, dy = zi - s.y, ex = zr - t.x, ey = zi - t.y;
+    double is, it;
+    rcp_pair(fma(dx, dx, dy * dy), fma(ex, ex, ey * ey), is, it);
+    add_star_polish_inv<EQUAL>(S, dx, dy, is, s);
+    add_star_polish_inv<EQUAL>(S, ex, ey, it, t);
+}
+
+template <bool EQUAL, class T>
+__device__ __forceinline__ void add_star_polish_inv(PSums &S, double dx, double dy, double inv,
+                                                    const T &s)
+{
     // u = ux - i uy, a = ux^2, b = uy^2:  u^2 = (a - b) - 2i ux uy,
     // u^3 = ux (a - 3b) + i uy (b - 3a),  |u|^4 = inv^2
     // (s2i accumulates sum m ux uy; polish_finish turns it into Im s2 = -2 that)
@@ -1281,8 +1367,11 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
         } else {
             PSums S;
             zero(S);
-            stream_tiles(stars, n_stars, reinterpret_cast<T *>(tiles),
-                         [&](int, const T &s) { add_star_polish<EQUAL>(S, zr, zi, s); });
+            stream_tiles_pairs(stars, n_stars, reinterpret_cast<T *>(tiles),
+                               [&](const T &s) { add_star_polish<EQUAL>(S, zr, zi, s); },
+                               [&](const T &s, const T &t) {
+                                   add_star_polish_pair<EQUAL>(S, zr, zi, s, t);
+                               });
             u = polish_finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k);
         }
         if (act) {
