@@ -44,11 +44,14 @@ typedef enum {
 } mlcc_status;
 
 typedef enum {
-    MLCC_FP64 = 0, /* every sum and step in IEEE double precision; the root-root
-                      reciprocal inside the Aberth correction uses the hardware
-                      estimate (relative error ~2^-24), which cannot move a root
-                      at convergence */
-    MLCC_MIXED = 1 /* Aberth sweeps in FP32 (FP64 star distances, FP32 sums per tile of
+    MLCC_FP64 = 0, /* the double-precision iteration of Sec. 3.2 and Sec. 4.4: every
+                      star term, root-root term, sum, step and cutoff in IEEE double
+                      precision.  Each reciprocal 1/|d|^2 is the hardware estimate
+                      refined by one Newton step (relative error below 2^-47, against
+                      2^-53 for a correctly rounded division); consecutive star terms,
+                      and consecutive root-root terms, are taken in pairs that share
+                      one refined reciprocal of the product of their two |d|^2 */
+    MLCC_MIXED = 1,/* Aberth sweeps in FP32 (FP64 star distances, FP32 sums per tile of
                       64 stars carried in FP64), every root finished by FP64 Newton
                       polish passes that accept a root on the same cutoffs as the
                       Aberth sweeps (on the Newton step), and the two row identities
@@ -59,6 +62,15 @@ typedef enum {
                       gets one FP32 sweep and the polish again, then restarts from
                       its start values with FP64 Aberth sweeps.  Results meet the
                       same cutoffs as MLCC_FP64. */
+    MLCC_FP64_R32 = 2 /* not the paper's precision: MLCC_FP64, except that in warm rows
+                      the root-root sum R = sum_{r != k} 1/(z_k - z_r) of the Aberth
+                      correction is formed in FP32 (each coordinate split into an FP32
+                      pair hi + lo, the distance as (hi_k - hi_r) + (lo_k - lo_r), an
+                      FP32 reciprocal, FP32 sums per tile of 64 roots carried in FP64):
+                      relative error ~2^-24 per term.  R enters the step only through
+                      F (2 S1 - R), which vanishes at a zero of F, so the roots it
+                      accepts meet the same FP64 cutoffs; star sums, F, F', the step
+                      and the lens map stay FP64, and cold starts are MLCC_FP64's */
 } mlcc_precision;
 
 typedef enum {
@@ -137,8 +149,9 @@ mlcc_status mlcc_set_lenses(mlcc_ctx *ctx, int64_t n, const double *x, const dou
  * Rejected (MLCC_ERR_INVALID): the mlcc_set_lenses conditions (except the
  * |gamma| rule, which applies to gamma - d0 and only for t = 1), even or
  * out-of-range t, and (t - 1) Arg(c) within 10% of pi of a multiple of pi
- * (the leading coefficient nearly vanishes; App. B).  Only MLCC_FP64 solves
- * it.  Copies the inputs; synchronous.
+ * (the leading coefficient nearly vanishes; App. B).  Only the two FP64
+ * precisions (MLCC_FP64, MLCC_FP64_R32) solve it.  Copies the inputs;
+ * synchronous.
  */
 mlcc_status mlcc_set_lenses_rect(mlcc_ctx *ctx, int64_t n, const double *x, const double *y,
                                  const double *m, double kappa_s, double gamma, double kappa_star,
@@ -235,15 +248,16 @@ typedef struct {
     int64_t sweep_launches, sweep_f32_launches, polish_launches;   /* launches that did work */
     double algorithmic_flop; /* FP64 sweeps, FP64 part: root_updates * 29 N (star terms) plus
                                 10 (2N - 1) per update whose root-root terms run in FP64
-                                (cold starts, the mixed form's restarts); FMA = 2,
-                                add/mul/reciprocal = 1 */
+                                (every update of MLCC_FP64; cold starts and the mixed form's
+                                restarts otherwise); FMA = 2, add/mul/reciprocal = 1 */
     double algorithmic_flop_f32;    /* FP32 sweeps: root_updates_f32 * (29 N + 10 (2N - 1)) */
     double algorithmic_flop_polish; /* polish: polish_updates * 29 N (star terms only) */
     double persistent_ms;    /* MLCC_SCHEDULE_PERSISTENT: GPU time of the one launch that runs
                                 every pass (timing != 0); the per-kind times above stay 0 */
     int64_t persistent_launches;    /* 1 with MLCC_SCHEDULE_PERSISTENT, else 0 */
     double algorithmic_flop_sweep_roots; /* FP64 sweeps, FP32 part: 10 (2N - 1) per update of
-                                a warm MLCC_FP64 row (its root-root terms run in FP32) */
+                                a warm MLCC_FP64_R32 row (its root-root terms run in FP32);
+                                0 for MLCC_FP64 */
     int64_t fmm_near_terms;  /* MLCC_STARS_FMM: star terms summed directly in the updates that
                                 took the multipole sums (the 3 x 3 near cells), all pass kinds;
                                 0 otherwise */

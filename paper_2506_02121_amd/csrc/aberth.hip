@@ -48,15 +48,13 @@ __device__ __forceinline__ double rcp_refined(double x)
     return y;
 }
 
-// The hardware estimate v_rcp_f64 has relative error ~2^-24.4.  Star terms
-// take one refinement step (relative error ~2^-47): F then carries errors of
-// a few 1e-15 of its terms, far below what moves a root by the 1e-9 cutoff.
-// The root-root sum R only enters the step as F * (2 S1 - R);
-// that factor vanishes at a zero of F, so an error in R cannot move a
-// converged root, it only perturbs the path at second order in the error
-// of the iterate.  R therefore uses the unrefined estimate.
+// The hardware estimate v_rcp_f64 has relative error ~2^-24.4; one
+// refinement step takes it below 2^-47, a few units in the last place of a
+// double.  Star terms and root-root terms both take that step, so every sum
+// of an FP64 Aberth sweep is formed at double precision (the paper's program
+// is double precision throughout, Sec. 4.4).
 constexpr int RCP_STAR = 1;
-constexpr int RCP_ROOT = 0;
+constexpr int RCP_ROOT = 1;
 
 // Streams the records p[0..n) through body(i, rec) for a one-wave work
 // group.  Tiles of 64 records (one per lane) are fetched with coalesced
@@ -237,6 +235,7 @@ __device__ __forceinline__ void add_star_inv(Sums &S, double dx, double dy, doub
     }
 }
 
+// Root-root term of the Aberth correction, 1/(z - z_r) = conj(d) / |d|^2.
 __device__ __forceinline__ void add_root(Sums &S, double zr, double zi, const double2 &o)
 {
     const double dx = zr - o.x, dy = zi - o.y;
@@ -245,13 +244,28 @@ __device__ __forceinline__ void add_root(Sums &S, double zr, double zi, const do
     S.Ri = fma(-dy, inv, S.Ri);
 }
 
-// The same root-root term with FP32 arithmetic, for the dense sweep.  Each
+// Two root-root terms sharing one refined reciprocal (rcp_pair), in the
+// order add_root would take them.  Two iterates at one point make both
+// terms non-finite, as one term alone would be, and the iterate is nudged.
+__device__ __forceinline__ void add_root_pair(Sums &S, double zr, double zi, const double2 &o,
+                                              const double2 &p)
+{
+    const double dx = zr - o.x, dy = zi - o.y, ex = zr - p.x, ey = zi - p.y;
+    double io, ip;
+    rcp_pair(fma(dx, dx, dy * dy), fma(ex, ex, ey * ey), io, ip);
+    S.Rr = fma(dx, io, S.Rr);
+    S.Ri = fma(-dy, io, S.Ri);
+    S.Rr = fma(ex, ip, S.Rr);
+    S.Ri = fma(-ey, ip, S.Ri);
+}
+
+// The root-root term with FP32 arithmetic (MLCC_FP64_R32, warm rows).  Each
 // coordinate enters as an FP32 pair hi + lo (hi = the FP64 value rounded to
 // FP32, lo = the rounded remainder), and the difference is formed as
 // (hi_k - hi_r) + (lo_k - lo_r): the first difference is exact for nearby
 // roots, so the distance carries FP32 relative accuracy (~2^-24) at any
-// separation, as does the FP32 reciprocal.  That matches the ~2^-24 of the
-// unrefined FP64 reciprocal above; the term runs at the FP32 issue rate.
+// separation, as does the FP32 reciprocal; the term runs at the FP32 issue
+// rate.
 struct SplitRoot {
     __device__ __forceinline__ float4 operator()(const double2 &o) const
     {
@@ -810,12 +824,12 @@ __device__ __forceinline__ void put(const RoundArgs<T> &A, const BlockCtx<T> &B,
 }
 
 // Which FP64 Aberth passes take the root-root sum in FP32 (add_root_hl):
-// warm rows of the FP64 form.  Cold starts, where the repulsion between the
-// iterates steers global convergence from the seeds, and the mixed form's
-// FP64 restarts of difficult rows keep it in FP64 (add_root).
-__device__ __forceinline__ bool fast_roots_pass(const Front &fr)
+// warm rows of a field solved in MLCC_FP64_R32.  Cold starts, where the
+// repulsion between the iterates steers global convergence from the seeds,
+// MLCC_FP64 and the mixed form's FP64 restarts keep it in FP64.
+__device__ __forceinline__ bool fast_roots_pass(const Front &fr, const Real &r)
 {
-    return fr.dir != 0 && fr.mode == PH_F64;
+    return r.root32 && fr.dir != 0 && fr.mode == PH_F64;
 }
 
 // One FP64 Aberth pass of a block (the block context is set by enter()).
@@ -940,11 +954,14 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
                                    add_star_pair<EQUAL>(S, zr, zi, s, t);
                                });
         }
-        if (!fast_roots_pass(A.fronts[B.f])) {
+        if (!fast_roots_pass(A.fronts[B.f], A.reals[B.r])) {
+            // the other roots in FP64, two at a time outside the own block;
+            // within it one at a time, skipping the root itself
             double2 *rtiles = reinterpret_cast<double2 *>(tiles);
-            auto other = [&](int, const double2 &o) { add_root(S, zr, zi, o); };
+            auto one = [&](const double2 &o) { add_root(S, zr, zi, o); };
+            auto two = [&](const double2 &o, const double2 &p) { add_root_pair(S, zr, zi, o, p); };
             const int own_hi = min(k0 + 64, n_r);
-            stream_tiles(zsrc, k0, rtiles, other);
+            stream_tiles_pairs(zsrc, k0, rtiles, one, two);
             stream_tiles(zsrc + k0, own_hi - k0, rtiles, [&](int j, const double2 &o) {
                 Sums T2 = S;
                 add_root(T2, zr, zi, o);
@@ -952,7 +969,7 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
                 S.Rr = self ? S.Rr : T2.Rr;
                 S.Ri = self ? S.Ri : T2.Ri;
             });
-            stream_tiles(zsrc + own_hi, n_r - own_hi, rtiles, other);
+            stream_tiles_pairs(zsrc + own_hi, n_r - own_hi, rtiles, one, two);
             const Update u = finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k,
                                            B.sheet, B.n_poly);
             if (act) store(k, u);
@@ -1702,7 +1719,7 @@ aberth_control(Front *__restrict__ fronts, int32_t *__restrict__ counts, int32_t
             const unsigned long long us = u * (unsigned)reals[fr.real].n_stars;
             my_upd[fr.phase] += u;
             my_star[fr.phase] += us;
-            if (fr.phase == PH_F64 && fast_roots_pass(fr)) {
+            if (fr.phase == PH_F64 && fast_roots_pass(fr, reals[fr.real])) {
                 my_upd[3] += u;
                 my_star[3] += us;
             }
@@ -1925,7 +1942,7 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
             if (fr.phase == PH_F64) {
                 atomicAdd(&A.ctl->updates, u);
                 atomicAdd(&A.ctl->star_updates, us);
-                if (fast_roots_pass(fr)) {
+                if (fast_roots_pass(fr, *R)) {
                     atomicAdd(&A.ctl->updates_fast, u);
                     atomicAdd(&A.ctl->star_updates_fast, us);
                 }
@@ -2274,6 +2291,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         const double u_ro = 1.1102230246251565e-16;
         R.tol1 = 8.0 * u_ro * h.sum_abs_z;
         R.tol2 = 16.0 * u_ro * h.sum_abs_z2;
+        R.root32 = p->precision == MLCC_FP64_R32 ? 1 : 0;
         const int bpf = (int)ceil_div(n_r, 64);
         for (int s = 0; s < S; ++s) {
             const int32_t lo = (int32_t)(s * L), hi = (int32_t)(lo + L), cen = (int32_t)(lo + L / 2);

@@ -182,7 +182,7 @@ void mlcc_destroy(mlcc_ctx *ctx)
     DevBuf *bufs[] = {&c.stars, &c.mass, &c.stars4, &c.sheet_d, &c.sheet, &c.iter[0], &c.iter[1],
                       &c.flagrow, &c.fronts, &c.counts, &c.control, &c.etab, &c.bnd, &c.perm,
                       &c.match_aux, &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.vsum,
-                      &c.pq, &c.passupd, &c.reals_d, &c.bmap, &c.diff, &c.err, &c.edt_col,
+                      &c.pq, &c.passupd, &c.reals_d, &c.bmap, &c.diff, &c.edt_col,
                       &c.dmask, &c.fmm_cs, &c.fmm_st, &c.fmm_st2, &c.fmm_cf, &c.fmm_cg,
                       &c.fmm_q, &c.fmm_m, &c.fmm_args};
     for (DevBuf *b : bufs) b->release();
@@ -461,7 +461,7 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
         return fail(MLCC_ERR_INVALID, "tol_inv_mu must be >= 0 and finite");
     if (p.max_iter_cold < 0 || p.max_iter_warm < 0)
         return fail(MLCC_ERR_INVALID, "iteration caps must be >= 0");
-    if (p.precision != MLCC_FP64 && p.precision != MLCC_MIXED)
+    if (p.precision != MLCC_FP64 && p.precision != MLCC_MIXED && p.precision != MLCC_FP64_R32)
         return fail(MLCC_ERR_INVALID, "unknown precision %d", p.precision);
     if (p.predictor < 0 || p.predictor > 2)
         return fail(MLCC_ERR_INVALID, "predictor must be 0, 1 or 2 (got %d)", p.predictor);
@@ -469,8 +469,8 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
         return fail(MLCC_ERR_INVALID, "unknown schedule %d", p.schedule);
     if (p.watchdog_ms < 0 || p.watchdog_ms > 600000)
         return fail(MLCC_ERR_INVALID, "watchdog_ms=%d outside [0, 600000]", p.watchdog_ms);
-    if (c.rect && p.precision != MLCC_FP64)
-        return fail(MLCC_ERR_INVALID, "a rectangular field is solved in MLCC_FP64 only");
+    if (c.rect && p.precision == MLCC_MIXED)
+        return fail(MLCC_ERR_INVALID, "a rectangular field is solved in the FP64 precisions only");
     if (p.star_sums != MLCC_STARS_DIRECT && p.star_sums != MLCC_STARS_FMM)
         return fail(MLCC_ERR_INVALID, "unknown star_sums %d", p.star_sums);
     if (p.fmm_order != 0 && (p.fmm_order < 8 || p.fmm_order > 63))

@@ -10,6 +10,8 @@
 // Exactness: vertices go on a lattice of 2^24 points per pixel; pixel centres
 // are lattice points; the crossing test is a 128-bit integer comparison, and
 // the first column is a floating-point estimate corrected by that exact test.
+#include <algorithm>
+
 #include "mlcc_internal.h"
 
 namespace mlcc {
@@ -35,30 +37,17 @@ __device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b)
     return q;
 }
 
-__global__ void __launch_bounds__(256)
-crossing_edges(int64_t rows, int64_t n_r, const double *__restrict__ wr,
-               const double *__restrict__ wi, const int32_t *__restrict__ chain_next,
-               double x0, double y0, double hx, double hy, int32_t nx, int32_t ny,
-               int32_t *__restrict__ diff, int32_t *__restrict__ err)
+// Edges of one chain (column k) over CROSS_ROWS consecutive rows per lane:
+// each vertex is loaded and put on the lattice once and serves as the end of
+// one edge and the start of the next; lanes of a work group take adjacent
+// columns, so every row's loads are coalesced.
+constexpr int CROSS_ROWS = 16;
+
+// Adds the edge (a -> b)'s crossings to the difference map.
+__device__ __forceinline__ void edge_crossings(int64_t ax, int64_t ay, int64_t bx, int64_t by,
+                                               int32_t nx, int32_t ny,
+                                               int32_t *__restrict__ diff)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= rows * n_r) return;
-    const int64_t j = e / n_r, k = e - j * n_r;
-    int64_t j2 = j + 1, k2 = k;
-    if (j2 == rows) {
-        j2 = 0;
-        k2 = chain_next ? chain_next[k] : k;
-        if (k2 < 0 || k2 >= n_r) {
-            atomicOr(err, 2);
-            return;
-        }
-    }
-    int64_t ax, ay, bx, by;
-    if (!to_lattice(wr[e], x0, hx, &ax) || !to_lattice(wi[e], y0, hy, &ay) ||
-        !to_lattice(wr[j2 * n_r + k2], x0, hx, &bx) || !to_lattice(wi[j2 * n_r + k2], y0, hy, &by)) {
-        atomicOr(err, 1);
-        return;
-    }
     if (ay == by) return;
     int s = 1;
     if (ay > by) {   // order the ends by height; a downward edge counts -1
@@ -90,6 +79,52 @@ crossing_edges(int64_t rows, int64_t n_r, const double *__restrict__ wr,
         while (c < nx && !right(c)) ++c;
         if (c < nx) atomicAdd(&diff[r * nx + c], s);
     }
+}
+
+// One lane per (column, chunk of CROSS_ROWS rows); work group b covers
+// columns 256 (b mod cb) .. + 255 of chunk b / cb (cb = column blocks).
+__global__ void __launch_bounds__(256)
+crossing_edges(int64_t rows, int64_t n_r, int64_t cb, const double *__restrict__ wr,
+               const double *__restrict__ wi, const int32_t *__restrict__ chain_next,
+               double x0, double y0, double hx, double hy, int32_t nx, int32_t ny,
+               int32_t *__restrict__ diff, int32_t *__restrict__ err)
+{
+    const int64_t k = (blockIdx.x % cb) * 256 + threadIdx.x;
+    if (k >= n_r) return;
+    const int64_t j0 = (blockIdx.x / cb) * CROSS_ROWS;
+    const int64_t j1 = min(j0 + CROSS_ROWS, rows);
+    int64_t ax, ay;
+    if (!to_lattice(wr[j0 * n_r + k], x0, hx, &ax) || !to_lattice(wi[j0 * n_r + k], y0, hy, &ay)) {
+        atomicOr(err, 1);
+        return;
+    }
+    for (int64_t j = j0; j < j1; ++j) {
+        int64_t j2 = j + 1, k2 = k;
+        if (j2 == rows) {   // the closing edge: row 0 of the chain that continues this one
+            j2 = 0;
+            k2 = chain_next ? chain_next[k] : k;
+            if (k2 < 0 || k2 >= n_r) {
+                atomicOr(err, 2);
+                return;
+            }
+        }
+        int64_t bx, by;
+        if (!to_lattice(wr[j2 * n_r + k2], x0, hx, &bx) ||
+            !to_lattice(wi[j2 * n_r + k2], y0, hy, &by)) {
+            atomicOr(err, 1);
+            return;
+        }
+        edge_crossings(ax, ay, bx, by, nx, ny, diff);
+        ax = bx;
+        ay = by;
+    }
+}
+
+// Clears n int32 (the difference map and the error word before a call).
+__global__ void __launch_bounds__(256) zero_i32(int32_t *__restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = 0;
 }
 
 // Inclusive prefix sum along each row: one 256-lane work-group per row,
@@ -130,21 +165,22 @@ mlcc_status run_caustic_crossings(Ctx *c, int64_t rows, int64_t n_r, const doubl
     const int64_t nx = g->nx, ny = g->ny;
     const double x0 = g->center_re - g->half_width, y0 = g->center_im - g->half_height;
     const double hx = (2.0 * g->half_width) / (double)nx, hy = (2.0 * g->half_height) / (double)ny;
-    MLCC_TRY(c->diff.reserve((size_t)nx * ny * sizeof(int32_t)));
-    MLCC_TRY(c->err.reserve(sizeof(int32_t)));
-    MLCC_HIP(hipMemsetAsync(c->diff.p, 0, (size_t)nx * ny * sizeof(int32_t), c->stream));
-    MLCC_HIP(hipMemsetAsync(c->err.p, 0, sizeof(int32_t), c->stream));
-    const int64_t ne = rows * n_r;
-    const int64_t blocks = ceil_div(ne, 256);
+    // the difference map and, after it, the error word (one clear)
+    const int64_t npix = nx * ny;
+    MLCC_TRY(c->diff.reserve((size_t)(npix + 64) * sizeof(int32_t)));
+    int32_t *diff = c->diff.as<int32_t>(), *err = diff + npix;
+    const int64_t cb = ceil_div(n_r, 256);
+    const int64_t blocks = cb * ceil_div(rows, CROSS_ROWS);
     if (blocks > 0x7fffffff) return fail(MLCC_ERR_INVALID, "too many edges");
+    hipLaunchKernelGGL(zero_i32, dim3((unsigned)std::min<int64_t>(ceil_div(npix + 1, 256), 8192)),
+                       dim3(256), 0, c->stream, diff, npix + 1);
     hipLaunchKernelGGL(crossing_edges, dim3((unsigned)blocks), dim3(256), 0, c->stream, rows, n_r,
-                       wr, wi, chain_next, x0, y0, hx, hy, (int32_t)nx, (int32_t)ny,
-                       c->diff.as<int32_t>(), c->err.as<int32_t>());
-    hipLaunchKernelGGL(row_prefix, dim3((unsigned)ny), dim3(256), 0, c->stream,
-                       c->diff.as<int32_t>(), ncc, (int32_t)nx);
+                       cb, wr, wi, chain_next, x0, y0, hx, hy, (int32_t)nx, (int32_t)ny, diff, err);
+    hipLaunchKernelGGL(row_prefix, dim3((unsigned)ny), dim3(256), 0, c->stream, diff, ncc,
+                       (int32_t)nx);
     MLCC_HIP(hipGetLastError());
     int32_t herr = 0;
-    MLCC_HIP(hipMemcpyAsync(&herr, c->err.p, sizeof herr, hipMemcpyDeviceToHost, c->stream));
+    MLCC_HIP(hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, c->stream));
     MLCC_HIP(hipStreamSynchronize(c->stream));
     if (herr & 1)
         return fail(MLCC_ERR_INVALID,

@@ -96,6 +96,8 @@ struct Real {
     double tol1, tol2;  // rounding of the reference values of the two row identities
     int32_t n_poly;     // rectangular field: sheet terms (gamma holds gamma - d0); else 0
     int32_t n_extra;    // roots beyond 2 N: t - 1 for a rectangular field
+    int32_t root32;     // MLCC_FP64_R32: warm FP64 rows take the root-root sum in FP32
+    int32_t pad_;
     int64_t sheet_off;  // its record in the sheet array: d_2..d_{t-1} (n_poly), the lens-map
                         // terms d_2k / (2k + 1) (n_poly), start values of the extra roots
                         // (2 n_extra: re, im)
@@ -196,9 +198,9 @@ struct Ctx {
     DevBuf bmap;      // int2[blocks]: (front, block within front)
 
     // crossing / distance workspace
-    DevBuf diff;      // int32 per-row difference map
-    DevBuf err;       // int32 error flag
-    DevBuf edt_col;   // int32 column distances
+    DevBuf diff;      // int32 per-row difference map, then the crossing kernel's error word
+    DevBuf edt_col;   // distance map: caustic-mask words (uint64 per column and band of 64
+                      // rows), and the lower-envelope work rows of maps too wide for LDS
     DevBuf dmask;     // uint8 caustic-pixel mask (moving-source distances)
     // fast multipole star sums: the stars sorted by grid cell and each cell's
     // expansions (built by the root finder when asked for)

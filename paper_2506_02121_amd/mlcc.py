@@ -30,6 +30,8 @@ MLCC_ERR_STATE = -5
 MLCC_ERR_MATCH = -7
 MLCC_FP64 = 0
 MLCC_MIXED = 1
+MLCC_FP64_R32 = 2
+PRECISIONS = {"fp64": MLCC_FP64, "mixed": MLCC_MIXED, "fp64_r32": MLCC_FP64_R32}
 
 EXPORTED = [
     "mlcc_create", "mlcc_destroy", "mlcc_set_stream", "mlcc_last_error", "mlcc_set_lenses",
@@ -281,7 +283,7 @@ class Context:
         p.max_iter_cold = int(max_iter_cold)
         p.max_iter_warm = int(max_iter_warm)
         p.timing = int(bool(timing))
-        p.precision = {"fp64": MLCC_FP64, "mixed": MLCC_MIXED}[precision]
+        p.precision = PRECISIONS[precision]
         p.predictor = int(predictor)
         p.schedule = {"rounds": 0, "persistent": 1}[schedule]
         p.watchdog_ms = int(watchdog_ms)

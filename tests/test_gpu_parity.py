@@ -139,16 +139,24 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp64_r32"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_critical_curves_match_oracle(ctx, case):
+def test_critical_curves_match_oracle(ctx, case, precision):
+    """Both FP64 forms: the plain one (every term in double precision) and
+    the one with FP32 root-root sums in warm rows."""
     name, n, masses, ks, kap_s, g, m_steps, S = case
-    say("roots", case)
+    say("roots", case, precision)
     if name.startswith("tiny"):
         f = fields.tiny_field(0)
     else:
         f = fields.random_field(11, n, kappa_star=ks, kappa_s=kap_s, gamma=g, masses=masses)
-    R, cn, st, (rr, ri, cnt) = gpu_roots(ctx, f, m_steps, n_subchains=S)
+    R, cn, st, (rr, ri, cnt) = gpu_roots(ctx, f, m_steps, n_subchains=S, precision=precision)
     print("[stats]", st, flush=True)
+    # the plain form counts no FP32 work; the other runs its warm rows' root terms in FP32
+    if precision == "fp64":
+        assert st["algorithmic_flop_sweep_roots"] == 0.0 and st["root_updates_f32"] == 0
+    else:
+        assert st["algorithmic_flop_sweep_roots"] > 0.0
     R_ref, cn_ref, st_ref = oracle.critical_curves(f, m_steps, n_sub=1)
     check_roots_against_oracle(f, R, R_ref, name)
     # chain structure: row m = row 0 under chain_next, and the oracle grown
@@ -415,6 +423,25 @@ def test_distances_match_oracle(ctx, seed, ny, nx):
     d, bl = _dist_gpu(ctx, ncc, h, grid)
     assert np.array_equal(np.rint((d / h) ** 2).astype(np.int64), ref_d2)
     assert np.max(np.abs(d - ref_d) / np.maximum(ref_d, 1e-300)) <= 2.3e-16
+    assert np.array_equal(bl, ref_bl)
+
+
+@pytest.mark.parametrize("ny,nx,pixels", [(40, 1500, 1), (200, 1100, 3), (1300, 30, 2),
+                                          (65, 64, 5)])
+def test_distances_sparse_maps(ctx, ny, nx, pixels):
+    """Few caustic pixels far apart: rows whose outward search runs past its
+    window take the lower envelope instead; both must give the exact d^2.
+    Odd band counts (rows not a multiple of 64) and single-column strips."""
+    say("edt sparse", ny, nx, pixels)
+    rng = np.random.default_rng(ny * 7 + nx)
+    ncc = np.zeros((ny, nx), dtype=np.int32)
+    for _ in range(pixels):
+        r, c = int(rng.integers(0, ny)), int(rng.integers(0, nx))
+        ncc[r:min(r + 3, ny), c:min(c + 2, nx)] = 1
+    h = 0.01
+    ref_d, ref_bl, ref_d2 = oracle.edt_twopass(ncc, h)
+    d, bl = _dist_gpu(ctx, ncc, h)
+    assert np.array_equal(np.rint((d / h) ** 2).astype(np.int64), ref_d2)
     assert np.array_equal(bl, ref_bl)
 
 
