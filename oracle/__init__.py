@@ -284,12 +284,19 @@ def _grid_args(grid):
 
 
 def _w_args(w, chain_next):
-    w = np.asarray(w, dtype=np.complex128)
-    if w.ndim != 2:
-        raise ValueError("w must be (rows, n_r)")
-    wr, wi = _f64(w.real), _f64(w.imag)
+    """w: complex (rows, n_r), or a pair of real (rows, n_r) planes (re, im),
+    which large maps pass to avoid a complex copy."""
+    if isinstance(w, tuple):
+        wr, wi = _f64(w[0]), _f64(w[1])
+        if wr.ndim != 2 or wr.shape != wi.shape:
+            raise ValueError("w planes must be two (rows, n_r) arrays")
+    else:
+        w = np.asarray(w, dtype=np.complex128)
+        if w.ndim != 2:
+            raise ValueError("w must be (rows, n_r)")
+        wr, wi = _f64(w.real), _f64(w.imag)
     cn = None if chain_next is None else np.ascontiguousarray(chain_next, dtype=np.int32)
-    return (wr, wi, cn), (w.shape[0], w.shape[1], _p(wr, _D), _p(wi, _D), _p(cn, _I32))
+    return (wr, wi, cn), (wr.shape[0], wr.shape[1], _p(wr, _D), _p(wi, _D), _p(cn, _I32))
 
 
 def ncc_pixels(w, chain_next, grid):

@@ -7,7 +7,10 @@ centre-out as the GPU grows it (the same columns once the two centre
 rows are paired), and properties that
 hold at any size: the row identities sum r = 2 sum z_i and
 sum r^2 = 2 sum z_i^2 - 2M/c(phi), the closure row m = row 0 under
-chain_next, and crossing-map values at sampled pixels."""
+chain_next, the label of every column across every subchain boundary, and
+the whole crossing and distance maps of the GPU's own caustic vertices,
+pixel for pixel, against the oracle's edge-by-edge map and its exact
+two-pass distance transform."""
 import numpy as np
 import pytest
 
@@ -96,21 +99,58 @@ def subchain0_window(st, m_steps, half):
 
 
 FULL = [
-    # workload, sampled rows, half-width of the subchain-0 window, sampled pixels, star sums
-    ("n1k", 6, 40, 24, "direct"),
-    ("n10k", 2, 4, 8, "direct"),
-    ("n10k_mixed", 2, 4, 0, "direct"),
-    ("n10k", 2, 4, 8, "fmm"),
-    ("n10k_mixed", 2, 4, 0, "fmm"),
+    # workload, precision (None: the workload's), sampled rows, half-width of the
+    # subchain-0 window, whole crossing and distance maps, star sums
+    ("n1k", None, 6, 40, True, "direct"),
+    ("n10k", None, 2, 4, True, "direct"),
+    ("n10k", "fp64_r32", 2, 4, False, "direct"),
+    ("n10k_mixed", None, 2, 4, False, "direct"),
+    ("n10k", None, 2, 4, False, "fmm"),
+    ("n10k_mixed", None, 2, 4, False, "fmm"),
 ]
 
 
+def case_id(c):
+    return c[0] + ("_" + c[1] if c[1] else "") + ("_fmm" if c[5] == "fmm" else "")
+
+
+def check_whole_maps(ctx, mlcc, wl, cr, ci, cnh, m_steps, n_r, name):
+    """The crossing map of the GPU's caustics against the oracle's, every
+    pixel, and the distance map of that N_cc map against the oracle's exact
+    transform: squared pixel distances and border marks bit for bit."""
+    grid = mlcc.as_grid(wl.grid)
+    ncc_d = ctx.caustic_crossings(cr, ci, torch.as_tensor(cnh, device=cr.device), grid)
+    dist_d, bl_d = ctx.caustic_distances(grid, ncc_d)
+    torch.cuda.synchronize()
+    ncc = ncc_d.cpu().numpy()
+    wr = cr.view(m_steps + 1, n_r).cpu().numpy()
+    wi = ci.view(m_steps + 1, n_r).cpu().numpy()
+    ref = oracle.ncc_rows((wr, wi), cnh, grid)
+    del wr, wi
+    bad = int(np.count_nonzero(ncc != ref))
+    print(f"[{name}] N_cc map {grid.nx}x{grid.ny}: {bad} pixels differ from the oracle "
+          f"(max {int(ncc.max())}, {int(np.count_nonzero(ncc))} pixels inside caustics)",
+          flush=True)
+    assert bad == 0
+    h = 2.0 * grid.half_width / grid.nx
+    _, bl_ref, d2_ref = oracle.edt_twopass(ref, h)
+    dist = dist_d.cpu().numpy()
+    fin = np.isfinite(dist)
+    assert np.array_equal(fin, d2_ref >= 0)
+    d2 = np.full(dist.shape, -1, dtype=np.int64)
+    d2[fin] = np.rint((dist[fin] / h) ** 2).astype(np.int64)
+    assert np.array_equal(d2, d2_ref)
+    assert np.array_equal(dist[fin], np.sqrt(d2_ref[fin].astype(np.float64)) * h)
+    assert np.array_equal(bl_d.cpu().numpy(), bl_ref)
+    print(f"[{name}] distance map: d^2 and border marks equal the oracle's on every pixel "
+          f"(max distance {float(dist[fin].max()):.4f})", flush=True)
+
+
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("case", FULL, ids=[c[0] + ("_fmm" if c[4] == "fmm" else "")
-                                            for c in FULL])
+@pytest.mark.parametrize("case", FULL, ids=[case_id(c) for c in FULL])
 def test_full_size_single_field(mlcc, case):
-    wl_name, n_rows, half, n_pix, star_sums = case
-    name = wl_name + ("_fmm" if star_sums == "fmm" else "")
+    wl_name, prec, n_rows, half, maps, star_sums = case
+    name = case_id(case)
     say("full size", name)
     wl = fields.workload(wl_name)
     f, m_steps = wl.field, wl.m_steps
@@ -121,7 +161,8 @@ def test_full_size_single_field(mlcc, case):
         ctx.set_lenses(torch.as_tensor(f.x, device=dev), torch.as_tensor(f.y, device=dev),
                        torch.as_tensor(f.m, device=dev), f.kappa_s, f.gamma)
         rr, ri, cr, ci, cn, st, code = ctx.find_critical_curves(
-            m_steps, timing=True, caustics=True, precision=wl.precision, star_sums=star_sums)
+            m_steps, timing=True, caustics=True, precision=prec or wl.precision,
+            star_sums=star_sums)
         torch.cuda.synchronize()
         print("[stats]", {k: st[k] for k in ("n_subchains", "sweeps", "root_updates",
                                              "root_updates_f32", "rows_fallback",
@@ -139,7 +180,7 @@ def test_full_size_single_field(mlcc, case):
         keep = boundary_continuity(rr, ri, m_steps, st["n_subchains"])
         print(f"[{name}] columns keeping their label across subchain boundaries: {keep:.5f}",
               flush=True)
-        assert keep >= 0.999
+        assert keep == 1.0
         # sampled rows against cold-started oracle rows
         rng = np.random.default_rng(12345)
         rows = sorted(set([0, m_steps // 2, m_steps] +
@@ -164,20 +205,8 @@ def test_full_size_single_field(mlcc, case):
         colwise = float(np.max(np.abs(G_win[:, idx] - R_win)))
         print(f"[{name}] rows {lo}..{hi} of subchain 0, column-wise: {colwise:.3e}", flush=True)
         assert colwise < 1e-8
-        if n_pix:
-            # crossing map on the GPU's own caustics: exact at sampled pixels
-            grid = mlcc.as_grid(wl.grid)
-            ncc = ctx.caustic_crossings(cr, ci, cn, grid).cpu().numpy()
-            W = host_c(cr, ci)
-            prng = np.random.default_rng(7)
-            pix = np.stack([prng.integers(0, grid.ny, n_pix), prng.integers(0, grid.nx, n_pix)], 1)
-            # bias half the samples toward pixels with caustic crossings
-            hot = np.argwhere(ncc > 0)
-            if len(hot):
-                pix[: n_pix // 2] = hot[prng.integers(0, len(hot), n_pix // 2)]
-            ref = oracle.ncc_at(W, cnh, grid, pix[:, 0], pix[:, 1])
-            assert np.array_equal(ncc[pix[:, 0], pix[:, 1]], ref), name
-            print(f"[{name}] N_cc exact at {n_pix} sampled pixels (max {ncc.max()})", flush=True)
+        if maps:
+            check_whole_maps(ctx, mlcc, wl, cr, ci, cnh, m_steps, n_r, name)
     finally:
         ctx.close()
         torch.cuda.empty_cache()
@@ -228,7 +257,7 @@ def test_full_size_batched(mlcc):
             keep = min(keep, boundary_continuity(fr, fi, m_steps, st["n_subchains"]))
         print(f"[batched] columns keeping their label across boundaries (4 largest fields): "
               f"{keep:.5f}", flush=True)
-        assert keep >= 0.999
+        assert keep == 1.0
         # the three smallest fields: the whole chain against the oracle
         for i in order[:3]:
             f = fs[i]
