@@ -132,6 +132,56 @@ __device__ __forceinline__ void stream_tiles_pairs(const T *__restrict__ p, int 
     __syncthreads();
 }
 
+// Reciprocals shared by groups of this many consecutive terms (2 or 4; see
+// rcp_pair and rcp_quad).
+#ifndef MLCC_RCP_GROUP
+#define MLCC_RCP_GROUP 4
+#endif
+
+// The same stream, records taken four at a time: four(a, b, c, d) for
+// consecutive records, then two() and one() for what a partial tile leaves.
+// The terms meet the sums in the same order as with stream_tiles.
+template <class T, class One, class Two, class Four>
+__device__ __forceinline__ void stream_tiles_quads(const T *__restrict__ p, int n, T *lds, One &&one,
+                                                   Two &&two, Four &&four)
+{
+    if (n <= 0) return;
+    const int lane = threadIdx.x;
+    const int ntiles = (n + 63) >> 6;
+    T reg = p[min(lane, n - 1)];
+    for (int t = 0; t < ntiles; ++t) {
+        T *buf = lds + ((t & 1) << 6);
+        buf[lane] = reg;
+        __syncthreads();
+        if (t + 1 < ntiles) reg = p[min(((t + 1) << 6) + lane, n - 1)];
+        const int cnt = min(64, n - (t << 6));
+        if (cnt == 64) {
+#pragma unroll 2
+            for (int k = 0; k < 64; k += 4) four(buf[k], buf[k + 1], buf[k + 2], buf[k + 3]);
+        } else {
+            int k = 0;
+            for (; k + 3 < cnt; k += 4) four(buf[k], buf[k + 1], buf[k + 2], buf[k + 3]);
+            if (k + 1 < cnt) {
+                two(buf[k], buf[k + 1]);
+                k += 2;
+            }
+            if (k < cnt) one(buf[k]);
+        }
+    }
+    __syncthreads();
+}
+
+// The stream in the groups MLCC_RCP_GROUP asks for.
+template <class T, class One, class Two, class Four>
+__device__ __forceinline__ void stream_tiles_grouped(const T *__restrict__ p, int n, T *lds,
+                                                     One &&one, Two &&two, Four &&four)
+{
+    if constexpr (MLCC_RCP_GROUP == 4)
+        stream_tiles_quads(p, n, lds, one, two, four);
+    else
+        stream_tiles_pairs(p, n, lds, one, two);
+}
+
 // Star records: (x, y) when all masses are equal (the common mass is applied
 // once at the end), (x, y, m, 0) otherwise.
 template <bool EQUAL> struct StarRec;
@@ -184,6 +234,24 @@ __device__ __forceinline__ void rcp_pair(double a, double b, double &ia, double 
     ib = a * ip;
 }
 
+// Four reciprocals for the price of one: with p01 = ab, p23 = cd and the
+// refined reciprocal r of p01 p23, 1/a = b (p23 r), 1/b = a (p23 r),
+// 1/c = d (p01 r), 1/d = c (p01 r): 11 FP64 operations and one quarter-rate
+// v_rcp_f64 for four terms, against 10 and two for two pairs.  The product
+// of four squared distances stays far inside the double range for any
+// field (distances between 1e-30 and 1e30).
+__device__ __forceinline__ void rcp_quad(double a, double b, double c, double d, double &ia,
+                                         double &ib, double &ic, double &id)
+{
+    const double p01 = a * b, p23 = c * d;
+    const double r = rcp_refined<RCP_STAR>(p01 * p23);
+    const double q01 = p23 * r, q23 = p01 * r;   // 1/(ab), 1/(cd)
+    ia = b * q01;
+    ib = a * q01;
+    ic = d * q23;
+    id = c * q23;
+}
+
 template <bool EQUAL, class T>
 __device__ __forceinline__ void add_star_inv(Sums &S, double dx, double dy, double inv,
                                              const T &s);
@@ -205,6 +273,21 @@ __device__ __forceinline__ void add_star_pair(Sums &S, double zr, double zi, con
     rcp_pair(fma(dx, dx, dy * dy), fma(ex, ex, ey * ey), is, it);
     add_star_inv<EQUAL>(S, dx, dy, is, s);
     add_star_inv<EQUAL>(S, ex, ey, it, t);
+}
+
+template <bool EQUAL, class T>
+__device__ __forceinline__ void add_star_quad(Sums &S, double zr, double zi, const T &s,
+                                              const T &t, const T &v, const T &w)
+{
+    const double dx = zr - s.x, dy = zi - s.y, ex = zr - t.x, ey = zi - t.y;
+    const double fx = zr - v.x, fy = zi - v.y, gx = zr - w.x, gy = zi - w.y;
+    double is, it, iv, iw;
+    rcp_quad(fma(dx, dx, dy * dy), fma(ex, ex, ey * ey), fma(fx, fx, fy * fy),
+             fma(gx, gx, gy * gy), is, it, iv, iw);
+    add_star_inv<EQUAL>(S, dx, dy, is, s);
+    add_star_inv<EQUAL>(S, ex, ey, it, t);
+    add_star_inv<EQUAL>(S, fx, fy, iv, v);
+    add_star_inv<EQUAL>(S, gx, gy, iw, w);
 }
 
 template <bool EQUAL, class T>
@@ -257,6 +340,25 @@ __device__ __forceinline__ void add_root_pair(Sums &S, double zr, double zi, con
     S.Ri = fma(-dy, io, S.Ri);
     S.Rr = fma(ex, ip, S.Rr);
     S.Ri = fma(-ey, ip, S.Ri);
+}
+
+__device__ __forceinline__ void add_root_quad(Sums &S, double zr, double zi, const double2 &o,
+                                              const double2 &p, const double2 &q,
+                                              const double2 &r)
+{
+    const double dx = zr - o.x, dy = zi - o.y, ex = zr - p.x, ey = zi - p.y;
+    const double fx = zr - q.x, fy = zi - q.y, gx = zr - r.x, gy = zi - r.y;
+    double io, ip, iq, ir;
+    rcp_quad(fma(dx, dx, dy * dy), fma(ex, ex, ey * ey), fma(fx, fx, fy * fy),
+             fma(gx, gx, gy * gy), io, ip, iq, ir);
+    S.Rr = fma(dx, io, S.Rr);
+    S.Ri = fma(-dy, io, S.Ri);
+    S.Rr = fma(ex, ip, S.Rr);
+    S.Ri = fma(-ey, ip, S.Ri);
+    S.Rr = fma(fx, iq, S.Rr);
+    S.Ri = fma(-fy, iq, S.Ri);
+    S.Rr = fma(gx, ir, S.Rr);
+    S.Ri = fma(-gy, ir, S.Ri);
 }
 
 // The root-root term with FP32 arithmetic (MLCC_FP64_R32, warm rows).  Each
@@ -432,6 +534,13 @@ constexpr int STALL_START = 100;
 
 // Newton steps a root may take within one polish pass with multipole sums.
 constexpr int FMM_POLISH_STEPS = 3;
+
+// Further rows a polish pass with multipole sums may finish after its own
+// (persistent schedule; see polish_pass).
+#ifndef MLCC_FMM_XROWS
+#define MLCC_FMM_XROWS 7
+#endif
+constexpr int FMM_XROWS = MLCC_FMM_XROWS;
 
 // ---------------------------------------------------------------------------
 // Fast multipole star sums (Sec. 4.1: near stars directly, far stars through
@@ -714,6 +823,13 @@ template <class T> struct RoundArgs {
     double2 *iter0, *iter1;
     const double *sheet; // rectangular fields' sheet records (Real::sheet_off)
     const FmmArgs *fmm;  // fast multipole star sums: one record per field (kernels built with them)
+    // Several rows per polish pass (persistent schedule, multipole sums; null
+    // otherwise): per front the fewest further rows any block of the pass
+    // finished (reset to xrow_max by the front's finisher), and the stride
+    // of the row-sum slots (the launch's block count).
+    int32_t *xrows;
+    int32_t xrow_max;
+    int32_t nvslots;
 };
 
 // What one block knows about its front and star field.
@@ -722,7 +838,10 @@ template <class T> struct BlockCtx {
     int n_poly, n_extra;   // rectangular field: sheet terms and extra roots (else 0)
     const double *sheet;   // its record: d_2k, then d_2k / (2k + 1), then extra seeds
     int vslot;   // this block's slot in the per-block row sums (front order)
+    int hist, end_row;   // finished rows behind the current one (<= 3); the front's last row
     bool valid, boundary;
+    bool from_out;   // first pass of a row after a pass that ran several: the previous
+                     // row's roots come from the output, not the iterate buffer
     int64_t base_f, out_off, bnd_row_off;
     const T *stars;
     const double2 *zsrc;
@@ -746,6 +865,9 @@ __device__ __forceinline__ bool enter_fq(const RoundArgs<T> &A, int phase, int f
     B.vslot = F->blk0 + B.q;
     B.dir = F->dir;
     B.pred = (F->fresh && F->dir != 0 && F->hist >= 2) ? min(A.predictor, F->hist - 1) : 0;
+    B.hist = F->hist;
+    B.end_row = F->end_row;
+    B.from_out = F->fresh == 2 && F->dir != 0;
     B.n_r = R->n_r;
     B.n_stars = R->n_stars;
     B.n_poly = R->n_poly;
@@ -948,20 +1070,25 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
             S.s2r -= f1.x; S.s2i += 0.5 * f1.y;
             S.s3r += 0.5 * f2.x; S.s3i += 0.5 * f2.y;
         } else {
-            stream_tiles_pairs(stars, n_stars, reinterpret_cast<T *>(tiles),
-                               [&](const T &s) { add_star<EQUAL>(S, zr, zi, s); },
-                               [&](const T &s, const T &t) {
-                                   add_star_pair<EQUAL>(S, zr, zi, s, t);
-                               });
+            stream_tiles_grouped(stars, n_stars, reinterpret_cast<T *>(tiles),
+                                 [&](const T &s) { add_star<EQUAL>(S, zr, zi, s); },
+                                 [&](const T &s, const T &t) {
+                                     add_star_pair<EQUAL>(S, zr, zi, s, t);
+                                 },
+                                 [&](const T &s, const T &t, const T &v, const T &w) {
+                                     add_star_quad<EQUAL>(S, zr, zi, s, t, v, w);
+                                 });
         }
         if (!fast_roots_pass(A.fronts[B.f], A.reals[B.r])) {
-            // the other roots in FP64, two at a time outside the own block;
+            // the other roots in FP64, in groups outside the own block;
             // within it one at a time, skipping the root itself
             double2 *rtiles = reinterpret_cast<double2 *>(tiles);
             auto one = [&](const double2 &o) { add_root(S, zr, zi, o); };
             auto two = [&](const double2 &o, const double2 &p) { add_root_pair(S, zr, zi, o, p); };
+            auto four = [&](const double2 &o, const double2 &p, const double2 &q,
+                            const double2 &r) { add_root_quad(S, zr, zi, o, p, q, r); };
             const int own_hi = min(k0 + 64, n_r);
-            stream_tiles_pairs(zsrc, k0, rtiles, one, two);
+            stream_tiles_grouped(zsrc, k0, rtiles, one, two, four);
             stream_tiles(zsrc + k0, own_hi - k0, rtiles, [&](int j, const double2 &o) {
                 Sums T2 = S;
                 add_root(T2, zr, zi, o);
@@ -969,7 +1096,7 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
                 S.Rr = self ? S.Rr : T2.Rr;
                 S.Ri = self ? S.Ri : T2.Ri;
             });
-            stream_tiles_pairs(zsrc + own_hi, n_r - own_hi, rtiles, one, two);
+            stream_tiles_grouped(zsrc + own_hi, n_r - own_hi, rtiles, one, two, four);
             const Update u = finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k,
                                            B.sheet, B.n_poly);
             if (act) store(k, u);
@@ -1205,6 +1332,21 @@ __device__ __forceinline__ void add_star_polish_pair(PSums &S, double zr, double
 }
 
 template <bool EQUAL, class T>
+__device__ __forceinline__ void add_star_polish_quad(PSums &S, double zr, double zi, const T &s,
+                                                     const T &t, const T &v, const T &w)
+{
+    const double dx = zr - s.x, dy = zi - s.y, ex = zr - t.x, ey = zi - t.y;
+    const double fx = zr - v.x, fy = zi - v.y, gx = zr - w.x, gy = zi - w.y;
+    double is, it, iv, iw;
+    rcp_quad(fma(dx, dx, dy * dy), fma(ex, ex, ey * ey), fma(fx, fx, fy * fy),
+             fma(gx, gx, gy * gy), is, it, iv, iw);
+    add_star_polish_inv<EQUAL>(S, dx, dy, is, s);
+    add_star_polish_inv<EQUAL>(S, ex, ey, it, t);
+    add_star_polish_inv<EQUAL>(S, fx, fy, iv, v);
+    add_star_polish_inv<EQUAL>(S, gx, gy, iw, w);
+}
+
+template <bool EQUAL, class T>
 __device__ __forceinline__ void add_star_polish_inv(PSums &S, double dx, double dy, double inv,
                                                     const T &s)
 {
@@ -1296,9 +1438,15 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
     bool act = false;
     double er_ = 0.0;   // estimated error of the value this root ends the pass with
     if (valid) {
-        const double2 z = zsrc[k];
-        zr = z.x;
-        zi = z.y;
+        if (B.from_out) {
+            const int64_t o = B.out_off + (int64_t)(B.row - B.dir) * B.n_r + k;
+            zr = A.out_re[o];
+            zi = A.out_im[o];
+        } else {
+            const double2 z = zsrc[k];
+            zr = z.x;
+            zi = z.y;
+        }
         act = flagrow[base_f + k] != B.stamp;
         if (B.pred) predict(A, B, k, zr, zi);
         if (!act) er_ = A.errbuf[base_f + k];   // accepted in an earlier pass of this row
@@ -1384,11 +1532,14 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
         } else {
             PSums S;
             zero(S);
-            stream_tiles_pairs(stars, n_stars, reinterpret_cast<T *>(tiles),
-                               [&](const T &s) { add_star_polish<EQUAL>(S, zr, zi, s); },
-                               [&](const T &s, const T &t) {
-                                   add_star_polish_pair<EQUAL>(S, zr, zi, s, t);
-                               });
+            stream_tiles_grouped(stars, n_stars, reinterpret_cast<T *>(tiles),
+                                 [&](const T &s) { add_star_polish<EQUAL>(S, zr, zi, s); },
+                                 [&](const T &s, const T &t) {
+                                     add_star_polish_pair<EQUAL>(S, zr, zi, s, t);
+                                 },
+                                 [&](const T &s, const T &t, const T &v, const T &w) {
+                                     add_star_polish_quad<EQUAL>(S, zr, zi, s, t, v, w);
+                                 });
             u = polish_finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k);
         }
         if (act) {
@@ -1419,13 +1570,94 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
         A.vieta[2 * B.vslot + 1] = make_double4(t_e, t_e2, t_a, t_a2);
         if (n_after) atomicAdd(&A.counts[B.f], n_after);
     }
-    // updates of the pass: one per active root, or its Newton steps
-    int n_upd = n_act;
-    if (n_steps >= 0) {
-        n_upd = n_steps;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) n_upd += __shfl_xor(n_upd, off, 64);
+    int n_xsteps = 0;   // Newton steps this lane took in further rows
+    if constexpr (FMM) {
+        if (A.xrows) {
+            // Several rows per pass: once every root of the block is accepted
+            // in this row, the block goes on through the next rows of its
+            // front by itself, each root from the chain prediction of its own
+            // earlier rows, as the front's first pass of that row would (a
+            // Newton step couples no roots).  A row counts only when every
+            // root of the block is accepted in it: then its roots and caustics
+            // are written and its row sums kept in slot e; the first row that
+            // leaves a root open ends the pass, and nothing of it is kept.
+            // The front's last row is left to a pass of its own.
+            int done = 0;
+            if (B.dir != 0 && A.predictor > 0 && n_after == 0) {
+                double pr = fr_, pi = fi_;   // this root in the row before
+                for (int x = 1; x <= A.xrow_max; ++x) {
+                    BlockCtx<T> C = B;
+                    C.row = B.row + x * B.dir;
+                    if ((C.row - B.end_row) * B.dir >= 0) break;
+                    C.boundary = false;
+                    C.pred = min(A.predictor, min(B.hist + x, 3) - 1);
+                    const double2 un = A.unit[C.row];
+                    const double2 ex = make_double2(a * un.x, a * un.y);
+                    double xr = pr, xi = pi;
+                    if (valid) predict(A, C, k, xr, xi);
+                    bool open = valid;
+                    Update u{};
+                    for (int it = 0; it < FMM_POLISH_STEPS; ++it) {
+                        PSums S;
+                        zero(S);
+                        int cell;
+                        double2 f, f1, f2, g;
+                        double q;
+                        fmm_far(A.fmm[B.r], xr, xi, cell, f, f1, f2, g, q, false);
+                        const int n_near = fmm_near(A.fmm[B.r], cell, [&](const double4 &s4) {
+                            if constexpr (EQUAL)
+                                add_star_polish<EQUAL>(S, xr, xi, make_double2(s4.x, s4.y));
+                            else add_star_polish<EQUAL>(S, xr, xi, s4);
+                        });
+                        fmm_count(&A.ctl->fmm_near_polish, A.ctl->fmm_far_polish, open, n_near,
+                                  n_stars);
+                        S.s0r += f.x; S.s0i += f.y;
+                        S.s2r -= f1.x; S.s2i += 0.5 * f1.y;
+                        S.s3r += 0.5 * f2.x; S.s3i += 0.5 * f2.y;
+                        S.q += q;
+                        const Update v = polish_finish<EQUAL>(S, xr, xi, m0, ex, gamma, a, a1,
+                                                              tol_step2, tol_mu, k);
+                        if (open) {
+                            u = v;
+                            n_xsteps += 1;
+                            if (v.flag) {
+                                open = false;
+                            } else {
+                                xr = v.zr;
+                                xi = v.zi;
+                            }
+                        }
+                        if (!__ballot(open)) break;
+                    }
+                    if (__ballot(open)) break;
+                    if (valid) put(A, C, k, u);
+                    double t1r = valid ? u.zr : 0.0, t1i = valid ? u.zi : 0.0;
+                    double t2r = valid ? u.zr * u.zr - u.zi * u.zi : 0.0;
+                    double t2i = valid ? 2.0 * u.zr * u.zi : 0.0;
+                    const double b2 = valid ? u.zr * u.zr + u.zi * u.zi : 0.0, b1 = sqrt(b2);
+                    const double ue = valid ? u.err : 0.0;
+                    double q_e = ue, q_e2 = ue * (2.0 * b1 + ue), q_a = b1, q_a2 = b2;
+                    wave_sum(t1r); wave_sum(t1i); wave_sum(t2r); wave_sum(t2i);
+                    wave_sum(q_e); wave_sum(q_e2); wave_sum(q_a); wave_sum(q_a2);
+                    if (lane == 0) {
+                        const int64_t sl = 2 * ((int64_t)x * A.nvslots + B.vslot);
+                        A.vieta[sl] = make_double4(t1r, t1i, t2r, t2i);
+                        A.vieta[sl + 1] = make_double4(q_e, q_e2, q_a, q_a2);
+                    }
+                    pr = u.zr;
+                    pi = u.zi;
+                    done = x;
+                }
+            }
+            if (lane == 0) atomicMin(&A.xrows[B.f], done);
+        }
     }
+    // updates of the pass: one per active root, or its Newton steps (those of
+    // further rows included)
+    int n_upd = (n_steps >= 0 ? n_steps : 0) + n_xsteps;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) n_upd += __shfl_xor(n_upd, off, 64);
+    if (n_steps < 0) n_upd += n_act;
     if (lane == 0 && n_upd) atomicAdd(&A.passupd[B.f], n_upd);
 }
 
@@ -1559,6 +1791,27 @@ __device__ __forceinline__ int row_converged(Front &fr, int f, Front *fronts, in
     return -1;
 }
 
+// The two row identities of a polished row (see aberth_control) from its
+// row sums rs: sum r and sum r^2, then the error terms.
+__device__ __forceinline__ bool row_identities_hold(const Real &R, double2 u, const double4 *rs)
+{
+    const int bpf = (R.n_r + 63) / 64;
+    const double4 t = rs[0], q = rs[1];
+    const double a1r = t.x, a1i = t.y, a2r = t.z, a2i = t.w;
+    const double se = q.x, se2 = q.y, sa = q.z, sa2 = q.w;
+    const double cr = R.gamma - R.a * u.x, ci = -R.a * u.y;   // c(phi)
+    const double cc = cr * cr + ci * ci;
+    const double mcr = R.M * cr / cc, mci = -R.M * ci / cc;   // M / c
+    const double e1r = a1r - 2.0 * R.sz_r, e1i = a1i - 2.0 * R.sz_i;
+    const double e2r = a2r - (2.0 * R.sz2_r - 2.0 * mcr);
+    const double e2i = a2i - (2.0 * R.sz2_i - 2.0 * mci);
+    const double u_ro = 1.1102230246251565e-16;
+    const double tol1 = 2.0 * se + 2.0 * (12 + bpf) * u_ro * sa + R.tol1;
+    const double tol2 = 2.0 * se2 + 2.0 * (13 + bpf) * u_ro * sa2 + R.tol2 +
+                        16.0 * u_ro * sqrt(mcr * mcr + mci * mci);
+    return sqrt(e1r * e1r + e1i * e1i) <= tol1 && sqrt(e2r * e2r + e2i * e2i) <= tol2;
+}
+
 // One front after its pass (c = its roots still unconverged, or, after an
 // FP32 sweep, still moving; rs = its row sums when the pass was a polish).
 // Returns the partner front a finished cold start activated, else -1.
@@ -1594,23 +1847,7 @@ __device__ __attribute__((noinline)) int advance_front(Front &fr, int f, int32_t
         fr.tried |= TRIED_POLISH;
         bool retry = false;
         if (c == 0) {
-            const Real R = reals[fr.real];
-            const int bpf = (R.n_r + 63) / 64;
-            const double4 t = rs[0], q = rs[1];
-            const double a1r = t.x, a1i = t.y, a2r = t.z, a2i = t.w;
-            const double se = q.x, se2 = q.y, sa = q.z, sa2 = q.w;
-            const double2 u = unit[fr.row];
-            const double cr = R.gamma - R.a * u.x, ci = -R.a * u.y;   // c(phi)
-            const double cc = cr * cr + ci * ci;
-            const double mcr = R.M * cr / cc, mci = -R.M * ci / cc;   // M / c
-            const double e1r = a1r - 2.0 * R.sz_r, e1i = a1i - 2.0 * R.sz_i;
-            const double e2r = a2r - (2.0 * R.sz2_r - 2.0 * mcr);
-            const double e2i = a2i - (2.0 * R.sz2_i - 2.0 * mci);
-            const double u_ro = 1.1102230246251565e-16;
-            const double tol1 = 2.0 * se + 2.0 * (12 + bpf) * u_ro * sa + R.tol1;
-            const double tol2 = 2.0 * se2 + 2.0 * (13 + bpf) * u_ro * sa2 + R.tol2 +
-                                16.0 * u_ro * sqrt(mcr * mcr + mci * mci);
-            if (sqrt(e1r * e1r + e1i * e1i) <= tol1 && sqrt(e2r * e2r + e2i * e2i) <= tol2)
+            if (row_identities_hold(reals[fr.real], unit[fr.row], rs))
                 partner = row_converged(fr, f, fronts, st, f0, predictor);
             else
                 retry = true;
@@ -1931,7 +2168,7 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
             rs[0] = make_double4(v0, v1, v2, v3);
             rs[1] = make_double4(v4, v5, v6, v7);
         }
-        int partner = -1, state = FRONT_ACTIVE, finished = 0;
+        int partner = -1, state = FRONT_ACTIVE, finished = 0, xr = 0, dir0 = 0;
         int64_t p_off = 0;
         int p_par = 0;
         if (lane == 0) {
@@ -1955,10 +2192,47 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
             }
             const int32_t c = A.counts[tf];
             A.counts[tf] = 0;
-            const int dir0 = fr.dir;
+            dir0 = fr.dir;
+            const int row0 = fr.row, ph0 = fr.phase;
             partner = advance_front(fr, tf, c, rs, fronts_w, nullptr, 0, A.ctl, A.reals, A.unit,
                                     max_cold, max_warm, A.predictor);
             fr.par ^= 1;   // the pass wrote the other buffer
+            if (A.xrows && ph0 == PH_POLISH) {
+                // further rows the pass finished in every block (see polish_pass)
+                xr = A.xrows[tf];
+                A.xrows[tf] = A.xrow_max;
+                if (!(dir0 != 0 && fr.state == FRONT_ACTIVE && fr.phase == PH_POLISH &&
+                      fr.row == row0 + dir0))
+                    xr = 0;
+            }
+        }
+        // the further rows, in order, while their row identities hold
+        xr = __shfl(xr, 0, 64);
+        int moved = 0;
+        for (int x = 1; x <= xr; ++x) {
+            double v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0, v6 = 0, v7 = 0;
+            for (int b = lane; b < bpf; b += 64) {
+                const int64_t sl = 2 * ((int64_t)x * A.nvslots + fr.blk0 + b);
+                const double4 t = A.vieta[sl], u = A.vieta[sl + 1];
+                v0 += t.x; v1 += t.y; v2 += t.z; v3 += t.w;
+                v4 += u.x; v5 += u.y; v6 += u.z; v7 += u.w;
+            }
+            wave_sum(v0); wave_sum(v1); wave_sum(v2); wave_sum(v3);
+            wave_sum(v4); wave_sum(v5); wave_sum(v6); wave_sum(v7);
+            int ok = 0;
+            if (lane == 0) {
+                const double4 rx[2] = {make_double4(v0, v1, v2, v3), make_double4(v4, v5, v6, v7)};
+                if (row_identities_hold(*R, A.unit[fr.row], rx)) {
+                    row_converged(fr, tf, fronts_w, nullptr, 0, A.predictor);
+                    ok = 1;
+                }
+            }
+            ok = __shfl(ok, 0, 64);
+            if (!ok) break;
+            moved = x;
+        }
+        if (lane == 0) {
+            if (moved) fr.fresh = 2;   // its first pass takes the previous row from the output
             fronts_w[tf] = fr;
             state = fr.state;
             if (state != FRONT_ACTIVE) finished = (state == FRONT_FAILED && dir0 == 0) ? 2 : 1;
@@ -2368,7 +2642,12 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     MLCC_TRY(c->control.reserve(sizeof(Control)));
     MLCC_TRY(c->etab.reserve((size_t)(m + 1) * sizeof(double2)));
     MLCC_TRY(c->bnd.reserve((size_t)std::max<int64_t>(bnd_total, 1) * sizeof(double2)));
-    MLCC_TRY(c->vieta.reserve((size_t)2 * nblocks * sizeof(double4)));
+    // several rows per polish pass: the persistent schedule with multipole
+    // sums in the mixed form keeps row sums for FMM_XROWS further rows
+    const bool xrows_on = mixed && p->star_sums == MLCC_STARS_FMM &&
+                          p->schedule == MLCC_SCHEDULE_PERSISTENT && p->predictor > 0;
+    MLCC_TRY(c->vieta.reserve((size_t)2 * (xrows_on ? FMM_XROWS + 1 : 1) * nblocks *
+                              sizeof(double4)));
     MLCC_TRY(c->vsum.reserve((size_t)2 * F * sizeof(double4)));
     if (mixed) MLCC_TRY(c->errbuf.reserve((size_t)it_total * sizeof(double)));
     MLCC_TRY(c->reals_d.reserve((size_t)n_real * sizeof(Real)));
@@ -2625,12 +2904,15 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         const size_t o_tasks = (sizeof(PQueue) + 255) & ~(size_t)255;
         const size_t o_seq = o_tasks + (size_t)cap * sizeof(int2);
         const size_t o_fdone = o_seq + (size_t)cap * SEQ_STRIDE * sizeof(unsigned long long);
-        MLCC_TRY(c->pq.reserve(o_fdone + (size_t)F * sizeof(int32_t)));
+        const size_t o_xrows = o_fdone + (((size_t)F * sizeof(int32_t) + 255) & ~(size_t)255);
+        MLCC_TRY(c->pq.reserve(o_xrows + (size_t)F * sizeof(int32_t)));
         char *base = static_cast<char *>(c->pq.p);
         PQueue *dq = reinterpret_cast<PQueue *>(base);
         int2 *dtasks = reinterpret_cast<int2 *>(base + o_tasks);
         unsigned long long *dseq = reinterpret_cast<unsigned long long *>(base + o_seq);
         int32_t *dfdone = reinterpret_cast<int32_t *>(base + o_fdone);
+        int32_t *dxrows = reinterpret_cast<int32_t *>(base + o_xrows);
+        const std::vector<int32_t> xr0((size_t)F, FMM_XROWS);
         std::vector<int2> t0;
         for (int f = 0; f < F; ++f) {
             if (fr[f].state != FRONT_ACTIVE) continue;
@@ -2647,6 +2929,14 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
                                 rs));
         MLCC_HIP(hipMemcpyAsync(dseq, s0.data(), s0.size() * sizeof(unsigned long long),
                                 hipMemcpyHostToDevice, rs));
+        if (xrows_on)
+            MLCC_HIP(hipMemcpyAsync(dxrows, xr0.data(), xr0.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, rs));
+        auto set_xrows = [&](auto &A) {
+            A.xrows = xrows_on ? dxrows : nullptr;
+            A.xrow_max = xrows_on ? FMM_XROWS : 0;
+            A.nvslots = (int32_t)nblocks;
+        };
         int cus = 0, per_cu = 0, clock_khz = 0;
         MLCC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
         MLCC_HIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, c->device));
@@ -2672,6 +2962,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         const double2 *cur0 = c->iter[0].as<double2>();
         if (equal) {
             fill(A2, stars2, cur0, c->iter[1].as<double2>());
+            set_xrows(A2);
             A2.persistent = 1;
             A2.iter0 = c->iter[0].as<double2>();
             A2.iter1 = c->iter[1].as<double2>();
@@ -2687,6 +2978,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
                                    stall);
         } else {
             fill(A4, stars4, cur0, c->iter[1].as<double2>());
+            set_xrows(A4);
             A4.persistent = 1;
             A4.iter0 = c->iter[0].as<double2>();
             A4.iter1 = c->iter[1].as<double2>();
