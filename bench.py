@@ -141,7 +141,8 @@ def main():
     precision = args.precision or wl.precision
     if wl.fields:
         blk = batched_block(args, wl, precision, args.steps, args.warmup, serial=args.serial,
-                            fp64=True, multipole=args.forms, oracle_fields=4)
+                            fp64=args.forms, multipole=args.forms,
+                            oracle_fields=4 if args.oracle_rows > 0 else 0)
         out = headline(blk, f"batched: {WORKLOAD_TEXT['batched']}", precision)
         print(json.dumps(out), flush=True)
         return
@@ -248,13 +249,29 @@ def roofline(stats, workload, star_sums):
     return out
 
 
+def valu_fma_tflops(kind):
+    """The device's FP64 ("fp64") or unpacked FP32 ("fp32") FMA-chain rate in
+    TFLOP/s from libvalu_probe.so, the measurement aid built beside the
+    library (not part of its C-ABI)."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2506_02121_amd", "libvalu_probe.so")
+    lib = ctypes.CDLL(path)
+    lib.valu_probe_fma_tflops.argtypes = [ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_double)]
+    lib.valu_probe_fma_tflops.restype = ctypes.c_int
+    out = ctypes.c_double(0.0)
+    rc = lib.valu_probe_fma_tflops(0, {"fp64": 0, "fp32": 1}[kind], ctypes.byref(out))
+    if rc != 0:
+        raise RuntimeError(f"valu probe failed ({rc})")
+    return out.value
+
+
 def measured_peaks(k):
     """The device's measured FMA-chain rates beside the published peak, and
     the dominant kernel's fraction of them (FP64 and FP32 parts each priced
     at their measured rate)."""
-    from paper_2506_02121_amd import mlcc
-    p64 = mlcc.measure_valu_peak(0, "fp64")
-    p32 = mlcc.measure_valu_peak(0, "fp32")
+    p64 = valu_fma_tflops("fp64")
+    p32 = valu_fma_tflops("fp32")
     out = {"fp64_fma_tflops": p64, "fp32_fma_tflops": p32,
            "method": "8 independent FMA chains per lane, 8 waves per SIMD, HIP events"}
     f64, f32 = k.get("flop_f64"), k.get("flop_f32")
@@ -622,7 +639,9 @@ def batched_block(args, wl, precision, steps, warmup, serial, fp64, multipole, o
             log(f"batched {label or prec} step {i}: {time.perf_counter() - ts:.3f} s")
         return time.perf_counter() - t0, st
 
-    blocks = ctx.field_blocks(m_steps)
+    # each field's (roots offset, chain_next offset, n_r) in the flat outputs
+    blocks = [((m_steps + 1) * 2 * int(a), 2 * int(a), 2 * int(b - a))
+              for a, b in zip(off[:-1], off[1:])]
     order = np.argsort([f.n for f in fs])
     picks = sorted(set(order[np.linspace(0, len(fs) - 1, max(1, oracle_fields)).astype(int)]
                        .tolist())) if oracle_fields else []

@@ -220,6 +220,10 @@ typedef struct {
                               terms are truncated after ~0.47^(p+1) of their size.  Below
                               p ~ 28 the jumps of F between neighbouring cells exceed what the
                               1e-9 cutoffs resolve, and roots near cell borders may not settle */
+    int32_t cold_restart_sweeps; /* an FP64 cold start still unsettled after this many sweeps
+                              begins again, once, from the second set of start values (z_i +- i;
+                              a rectangular sheet's extra roots turned by half their spacing);
+                              0 = 100.  Takes effect only below max_iter_cold */
 } mlcc_cc_params;
 
 /* The paper's cutoffs (Sec. 3.2 footnote: 1e-9 and |mu| > 1e9),
@@ -267,7 +271,8 @@ typedef struct {
                                 (8 p more in sweeps of unequal masses).  FP32 sweeps take these
                                 sums in FP64: their star part counts in algorithmic_flop, their
                                 root terms stay in algorithmic_flop_f32 */
-    int64_t cold_restarts;   /* FP64 cold starts still unsettled after 100 sweeps and begun again
+    int64_t cold_restarts;   /* FP64 cold starts still unsettled after cold_restart_sweeps
+                                sweeps and begun again
                                 from the second set of start values (z_i +- i; a rectangular
                                 sheet's extra roots turned by half their spacing) */
 } mlcc_cc_stats;
@@ -422,17 +427,6 @@ mlcc_status mlcc_distance_histogram(mlcc_ctx *ctx, int64_t count, const double *
                                     const uint8_t *border_limited, const int32_t *ncc,
                                     int32_t ncc_lo, int32_t n_classes, int32_t n_bins,
                                     double d_max, int64_t *counts);
-
-/*
- * measure_valu_peak -- a measurement aid, not an operation of the paper: the
- * vector-ALU rate this device reaches on independent FMA chains (kind 0 =
- * FP64 v_fma_f64, 1 = FP32 v_fma_f32, unpacked), in TFLOP/s (FMA = 2 FLOP),
- * the achievable reference beside the published peaks in the rooflines of
- * the root-finder kernels.  Runs ~0.1 s of kernels on a stream of its own on
- * `device` (allocates and frees 2 MB); synchronous.
- *   tflops  host double, written on success
- */
-mlcc_status mlcc_measure_valu_peak(int device, int kind, double *tflops);
 
 #ifdef __cplusplus
 }

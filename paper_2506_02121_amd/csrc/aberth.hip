@@ -529,7 +529,8 @@ __device__ __forceinline__ Update finish(Sums S, double zr, double zi, double m0
 constexpr int SPARSE_MAX = 16;
 
 // An FP64 cold start still unsettled after this many sweeps (cold starts
-// take 11-30) starts again from the second set of start values.
+// take 11-30) starts again from the second set of start values (the
+// default of mlcc_cc_params.cold_restart_sweeps).
 constexpr int STALL_START = 100;
 
 // Newton steps a root may take within one polish pass with multipole sums.
@@ -1874,8 +1875,8 @@ __device__ __attribute__((noinline)) int advance_front(Front &fr, int f, int32_t
         partner = row_converged(fr, f, fronts, st, f0, predictor);
     } else {
         fr.sweeps += 1;
-        if (fr.dir == 0 && fr.phase == PH_F64 && fr.seedvar == 0 && fr.sweeps >= STALL_START &&
-            fr.sweeps < max_cold) {
+        if (fr.dir == 0 && fr.phase == PH_F64 && fr.seedvar == 0 &&
+            fr.sweeps >= reals[fr.real].restart && fr.sweeps < max_cold) {
             // a stalled cold start: once, all over again from other seeds
             fr.seedvar = 1;
             fr.reseed = 1;
@@ -2566,6 +2567,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         R.tol1 = 8.0 * u_ro * h.sum_abs_z;
         R.tol2 = 16.0 * u_ro * h.sum_abs_z2;
         R.root32 = p->precision == MLCC_FP64_R32 ? 1 : 0;
+        R.restart = p->cold_restart_sweeps > 0 ? p->cold_restart_sweeps : STALL_START;
         const int bpf = (int)ceil_div(n_r, 64);
         for (int s = 0; s < S; ++s) {
             const int32_t lo = (int32_t)(s * L), hi = (int32_t)(lo + L), cen = (int32_t)(lo + L / 2);

@@ -461,6 +461,8 @@ mlcc_status mlcc_find_critical_curves(mlcc_ctx *ctx, const mlcc_cc_params *param
         return fail(MLCC_ERR_INVALID, "tol_inv_mu must be >= 0 and finite");
     if (p.max_iter_cold < 0 || p.max_iter_warm < 0)
         return fail(MLCC_ERR_INVALID, "iteration caps must be >= 0");
+    if (p.cold_restart_sweeps < 0)
+        return fail(MLCC_ERR_INVALID, "cold_restart_sweeps must be >= 0");
     if (p.precision != MLCC_FP64 && p.precision != MLCC_MIXED && p.precision != MLCC_FP64_R32)
         return fail(MLCC_ERR_INVALID, "unknown precision %d", p.precision);
     if (p.predictor < 0 || p.predictor > 2)

@@ -1,11 +1,15 @@
-// Measured vector-ALU rate of the device, the reference beside the published
-// peaks in the roofline of the root-finder kernels: eight independent FMA
-// chains per lane, enough waves to fill every SIMD, timed with HIP events.
-#include <cmath>
-
-#include "mlcc_internal.h"
-
-namespace mlcc {
+// Measured vector-ALU rate of the device: a measurement aid for the
+// benchmark's rooflines, not part of the method and not on the library's
+// C-ABI.  Built into its own library (libvalu_probe.so) with the same
+// compiler flags as libmlcc.so.  Eight independent FMA chains per lane,
+// enough waves to fill every SIMD, timed with HIP events.
+//
+//   int valu_probe_fma_tflops(int device, int kind, double *tflops)
+//     kind 0 = FP64 v_fma_f64, 1 = FP32 v_fma_f32 (unpacked); writes the rate
+//     in TFLOP/s (FMA = 2 FLOP).  Returns 0, -1 for a bad argument, or the
+//     hipError_t of the first HIP call that failed.  Runs ~0.1 s of kernels on
+//     a stream of its own (allocates and frees 2 MB); synchronous.
+#include <hip/hip_runtime.h>
 
 namespace {
 
@@ -29,24 +33,24 @@ __global__ void __launch_bounds__(PROBE_THREADS) fma_chains(T *__restrict__ out,
 }
 
 template <class T>
-mlcc_status run_probe(int device, double *tflops)
+int run_probe(int device, double *tflops)
 {
-    MLCC_HIP(hipSetDevice(device));
+    hipError_t first = hipSuccess;
+    auto chk = [&](hipError_t e) {
+        if (e != hipSuccess && first == hipSuccess) first = e;
+        return e == hipSuccess;
+    };
     int cus = 0;
-    MLCC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-    if (cus < 1) return fail(MLCC_ERR_HIP, "device reports no compute units");
+    if (!chk(hipSetDevice(device)) ||
+        !chk(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)))
+        return (int)first;
+    if (cus < 1) return -1;
     const int blocks = cus * 8;   // 8 waves of 64 per SIMD
     const int iters = 1 << 16;
     T *out = nullptr;
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    mlcc_status st = MLCC_OK;
     float ms = 0.f;
-    auto chk = [&](hipError_t e) {
-        if (e != hipSuccess && st == MLCC_OK)
-            st = fail(MLCC_ERR_HIP, "probe: %s", hipGetErrorString(e));
-        return e == hipSuccess;
-    };
     if (chk(hipMalloc(&out, (size_t)blocks * PROBE_THREADS * sizeof(T))) &&
         chk(hipStreamCreate(&s)) && chk(hipEventCreate(&e0)) && chk(hipEventCreate(&e1))) {
         // one untimed launch (clocks, code load), then four timed ones
@@ -65,24 +69,19 @@ mlcc_status run_probe(int device, double *tflops)
     if (e1) (void)hipEventDestroy(e1);
     if (s) (void)hipStreamDestroy(s);
     if (out) (void)hipFree(out);
-    if (st != MLCC_OK) return st;
-    if (!(ms > 0.f)) return fail(MLCC_ERR_HIP, "probe: no elapsed time");
+    if (first != hipSuccess) return (int)first;
+    if (!(ms > 0.f)) return -1;
     const double flop = 4.0 * 2.0 * PROBE_CHAINS * (double)iters * blocks * PROBE_THREADS;
     *tflops = flop / (ms * 1e-3) / 1e12;
-    return MLCC_OK;
+    return 0;
 }
 
 }  // namespace
 
-}  // namespace mlcc
-
-using namespace mlcc;
-
-extern "C" mlcc_status mlcc_measure_valu_peak(int device, int kind, double *tflops)
+extern "C" int valu_probe_fma_tflops(int device, int kind, double *tflops)
 {
-    clear_error();
-    if (!tflops) return fail(MLCC_ERR_INVALID, "tflops is NULL");
+    if (!tflops) return -1;
     if (kind == 0) return run_probe<double>(device, tflops);
     if (kind == 1) return run_probe<float>(device, tflops);
-    return fail(MLCC_ERR_INVALID, "unknown kind %d (0 = FP64 FMA, 1 = FP32 FMA)", kind);
+    return -1;
 }

@@ -37,7 +37,7 @@ EXPORTED = [
     "mlcc_create", "mlcc_destroy", "mlcc_set_stream", "mlcc_last_error", "mlcc_set_lenses",
     "mlcc_set_lenses_batched", "mlcc_cc_params_default", "mlcc_find_critical_curves",
     "mlcc_find_critical_curves_batched", "mlcc_map_caustics",
-    "mlcc_caustic_crossings", "mlcc_caustic_distances", "mlcc_measure_valu_peak",
+    "mlcc_caustic_crossings", "mlcc_caustic_distances",
     "mlcc_set_lenses_rect", "mlcc_rect_taylor_degree", "mlcc_num_roots",
     "mlcc_caustic_distances_directional", "mlcc_distance_histogram",
 ]
@@ -50,7 +50,7 @@ class CCParams(ctypes.Structure):
                 ("tol_inv_mu", ctypes.c_double), ("timing", ctypes.c_int32),
                 ("predictor", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("watchdog_ms", ctypes.c_int32), ("star_sums", ctypes.c_int32),
-                ("fmm_order", ctypes.c_int32)]
+                ("fmm_order", ctypes.c_int32), ("cold_restart_sweeps", ctypes.c_int32)]
 
 
 class CCStats(ctypes.Structure):
@@ -100,7 +100,6 @@ _SIG = {
     "mlcc_caustic_crossings": ([_vp, _i64, _i64, _vp, _vp, _vp, ctypes.POINTER(GridC), _vp],
                                ctypes.c_int),
     "mlcc_caustic_distances": ([_vp, ctypes.POINTER(GridC), _vp, _vp, _vp], ctypes.c_int),
-    "mlcc_measure_valu_peak": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(_d)], ctypes.c_int),
     "mlcc_set_lenses_rect": ([_vp, _i64, _vp, _vp, _vp, _d, _d, _d, _d, _d, ctypes.c_int32],
                              ctypes.c_int),
     "mlcc_rect_taylor_degree": ([_d, _d, _d, _d, _d, ctypes.POINTER(ctypes.c_int32)],
@@ -126,17 +125,6 @@ class MlccError(RuntimeError):
 def _check(code: int):
     if code != MLCC_OK:
         raise MlccError(code, _lib.mlcc_last_error().decode())
-
-
-def measure_valu_peak(device: int = 0, kind: str = "fp64") -> float:
-    """TFLOP/s this device reaches on independent FMA chains ("fp64" or
-    "fp32", unpacked): the measured reference beside the published peaks."""
-    kinds = {"fp64": 0, "fp32": 1}
-    if kind not in kinds:
-        raise ValueError(f"kind must be one of {sorted(kinds)}")
-    out = _d(0.0)
-    _check(_lib.mlcc_measure_valu_peak(int(device), kinds[kind], ctypes.byref(out)))
-    return out.value
 
 
 def rect_taylor_degree(kappa_star: float, c1: float, c2: float, s: float, eps: float) -> int:
@@ -270,7 +258,8 @@ class Context:
                              caustics_out=None, raise_on_error: bool = True,
                              precision: str = "fp64", predictor: int = 2,
                              schedule: str = "persistent", watchdog_ms: int = 0,
-                             star_sums: str = "direct", fmm_order: int = 0):
+                             star_sums: str = "direct", fmm_order: int = 0,
+                             cold_restart_sweeps: int = 0):
         """Returns (roots_re, roots_im, chain_next, stats, status), or with
         caustics=True (roots_re, roots_im, caus_re, caus_im, chain_next, stats,
         status).  One field: arrays are (m_steps + 1, n_r) float64 device
@@ -289,6 +278,7 @@ class Context:
         p.watchdog_ms = int(watchdog_ms)
         p.star_sums = {"direct": 0, "fmm": 1}[star_sums]
         p.fmm_order = int(fmm_order)
+        p.cold_restart_sweeps = int(cold_restart_sweeps)
         n_r = self.num_roots()
         shape = (m_steps + 1, n_r) if self.star_offsets is None else ((m_steps + 1) * n_r,)
         if out is None:
