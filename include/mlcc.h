@@ -373,6 +373,29 @@ mlcc_status mlcc_caustic_crossings(mlcc_ctx *ctx, int64_t rows, int64_t n_r,
                                    int32_t *ncc);
 
 /*
+ * caustic_crossings_noalloc -- mlcc_caustic_crossings for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and the same result, bit
+ * for bit, but the difference map and error word live in a fixed device
+ * array of MLCC_NOALLOC_MAX_PIXELS + 64 int32 (16 MiB) that the library holds
+ * on each GPU it runs on until the process ends, instead of context memory.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); the caller passes inputs and outputs as for
+ * mlcc_caustic_crossings.  Every call on one GPU shares that GPU's array and
+ * clears it first: calls that overlap on one GPU (from several contexts,
+ * streams or threads) race and must be serialised by the caller.
+ *   arguments     as mlcc_caustic_crossings
+ * MLCC_ERR_INVALID if nx * ny > MLCC_NOALLOC_MAX_PIXELS (use
+ * mlcc_caustic_crossings), and for every case mlcc_caustic_crossings
+ * rejects.  Synchronous.
+ */
+#define MLCC_NOALLOC_MAX_PIXELS (2048 * 2048)
+mlcc_status mlcc_caustic_crossings_noalloc(mlcc_ctx *ctx, int64_t rows, int64_t n_r,
+                                           const double *w_re, const double *w_im,
+                                           const int32_t *chain_next, const mlcc_grid *grid,
+                                           int32_t *ncc);
+
+/*
  * caustic_distances -- distance from every pixel centre to the nearest
  * caustic pixel, for an expanding source (Sec. 5.2: Euclidean distance
  * transform of the N_cc map).  A caustic pixel is one with a 4-neighbour of

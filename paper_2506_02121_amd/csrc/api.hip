@@ -164,6 +164,7 @@ mlcc_status mlcc_create(mlcc_ctx **out, int device, void *hip_stream)
     if (device < 0 || device >= ndev)
         return fail(MLCC_ERR_INVALID, "device %d out of range (%d devices)", device, ndev);
     MLCC_HIP(hipSetDevice(device));
+    MLCC_TRY(noalloc_scratch_init(device));
     mlcc_ctx *c = new (std::nothrow) mlcc_ctx();
     if (!c) return fail(MLCC_ERR_NOMEM, "context allocation failed");
     c->impl.device = device;
@@ -547,6 +548,25 @@ mlcc_status mlcc_caustic_crossings(mlcc_ctx *ctx, int64_t rows, int64_t n_r, con
     MLCC_TRY(check_device_ptr(&c, ncc, "ncc"));
     clear_error();
     return run_caustic_crossings(&c, rows, n_r, w_re, w_im, chain_next, grid, ncc);
+}
+
+mlcc_status mlcc_caustic_crossings_noalloc(mlcc_ctx *ctx, int64_t rows, int64_t n_r,
+                                           const double *w_re, const double *w_im,
+                                           const int32_t *chain_next, const mlcc_grid *grid,
+                                           int32_t *ncc)
+{
+    if (!ctx) return fail(MLCC_ERR_INVALID, "ctx is NULL");
+    Ctx &c = ctx->impl;
+    MLCC_TRY(use_device(&c));
+    if (rows < 1 || n_r < 1) return fail(MLCC_ERR_INVALID, "need rows >= 1 and n_r >= 1");
+    if (rows > ((int64_t)1 << 40) / n_r) return fail(MLCC_ERR_INVALID, "rows * n_r too large");
+    MLCC_TRY(check_grid(grid, false));
+    MLCC_TRY(check_device_ptr(&c, w_re, "w_re"));
+    MLCC_TRY(check_device_ptr(&c, w_im, "w_im"));
+    if (chain_next) MLCC_TRY(check_device_ptr(&c, chain_next, "chain_next"));
+    MLCC_TRY(check_device_ptr(&c, ncc, "ncc"));
+    clear_error();
+    return run_caustic_crossings_noalloc(&c, rows, n_r, w_re, w_im, chain_next, grid, ncc);
 }
 
 mlcc_status mlcc_caustic_distances(mlcc_ctx *ctx, const mlcc_grid *grid, const int32_t *ncc,

@@ -11,6 +11,7 @@
 // are lattice points; the crossing test is a 128-bit integer comparison, and
 // the first column is a floating-point estimate corrected by that exact test.
 #include <algorithm>
+#include <mutex>
 
 #include "mlcc_internal.h"
 
@@ -158,20 +159,22 @@ row_prefix(const int32_t *__restrict__ diff, int32_t *__restrict__ ncc, int32_t 
     }
 }
 
-mlcc_status run_caustic_crossings(Ctx *c, int64_t rows, int64_t n_r, const double *wr,
+// The three launches and the error readback of one crossing map, with the
+// difference map (npix int32) and the error word after it in `diff`.
+static mlcc_status crossings_into(Ctx *c, int64_t rows, int64_t n_r, const double *wr,
                                   const double *wi, const int32_t *chain_next,
-                                  const mlcc_grid *g, int32_t *ncc)
+                                  const mlcc_grid *g, int32_t *ncc, int32_t *diff)
 {
     const int64_t nx = g->nx, ny = g->ny;
     const double x0 = g->center_re - g->half_width, y0 = g->center_im - g->half_height;
     const double hx = (2.0 * g->half_width) / (double)nx, hy = (2.0 * g->half_height) / (double)ny;
-    // the difference map and, after it, the error word (one clear)
     const int64_t npix = nx * ny;
-    MLCC_TRY(c->diff.reserve((size_t)(npix + 64) * sizeof(int32_t)));
-    int32_t *diff = c->diff.as<int32_t>(), *err = diff + npix;
+    int32_t *err = diff + npix;
     const int64_t cb = ceil_div(n_r, 256);
     const int64_t blocks = cb * ceil_div(rows, CROSS_ROWS);
     if (blocks > 0x7fffffff) return fail(MLCC_ERR_INVALID, "too many edges");
+    // one clear of the difference map and the error word (a kernel, not a
+    // memset node, so that a captured graph replays it correctly)
     hipLaunchKernelGGL(zero_i32, dim3((unsigned)std::min<int64_t>(ceil_div(npix + 1, 256), 8192)),
                        dim3(256), 0, c->stream, diff, npix + 1);
     hipLaunchKernelGGL(crossing_edges, dim3((unsigned)blocks), dim3(256), 0, c->stream, rows, n_r,
@@ -187,6 +190,61 @@ mlcc_status run_caustic_crossings(Ctx *c, int64_t rows, int64_t n_r, const doubl
                     "a caustic vertex is not finite or lies more than 2^29 pixels from the grid");
     if (herr & 2) return fail(MLCC_ERR_INVALID, "chain_next holds an index outside [0, n_r)");
     return MLCC_OK;
+}
+
+mlcc_status run_caustic_crossings(Ctx *c, int64_t rows, int64_t n_r, const double *wr,
+                                  const double *wi, const int32_t *chain_next,
+                                  const mlcc_grid *g, int32_t *ncc)
+{
+    const int64_t npix = (int64_t)g->nx * g->ny;
+    MLCC_TRY(c->diff.reserve((size_t)(npix + 64) * sizeof(int32_t)));
+    return crossings_into(c, rows, n_r, wr, wi, chain_next, g, ncc, c->diff.as<int32_t>());
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the difference map and the error word live in a
+// fixed device array instead of context memory.  In host code `scratch` only
+// names the symbol; its device address on each GPU comes from
+// hipGetSymbolAddress at context creation and is the one passed to kernels.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) int32_t scratch[MLCC_NOALLOC_MAX_PIXELS + 64];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex scratch_mu;
+static int32_t *scratch_dev[MAX_DEVICES];   // device address of `scratch`, per device
+
+mlcc_status noalloc_scratch_init(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES)
+        return fail(MLCC_ERR_INVALID, "device %d beyond the %d the library supports", device,
+                    MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_dev[device]) return MLCC_OK;
+    void *p = nullptr;
+    MLCC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(MLCC_ERR_HIP, "hipGetSymbolAddress gave no address for the scratch array");
+    scratch_dev[device] = static_cast<int32_t *>(p);
+    return MLCC_OK;
+}
+
+mlcc_status run_caustic_crossings_noalloc(Ctx *c, int64_t rows, int64_t n_r, const double *wr,
+                                          const double *wi, const int32_t *chain_next,
+                                          const mlcc_grid *g, int32_t *ncc)
+{
+    const int64_t npix = (int64_t)g->nx * g->ny;
+    if (npix > MLCC_NOALLOC_MAX_PIXELS)
+        return fail(MLCC_ERR_INVALID,
+                    "caustic_crossings_noalloc: %lld pixels exceed the fixed scratch of %lld "
+                    "(use mlcc_caustic_crossings)",
+                    (long long)npix, (long long)MLCC_NOALLOC_MAX_PIXELS);
+    int32_t *diff = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(scratch_mu);
+        diff = (c->device >= 0 && c->device < MAX_DEVICES) ? scratch_dev[c->device] : nullptr;
+    }
+    if (!diff) return fail(MLCC_ERR_STATE, "the scratch array of device %d is not set up", c->device);
+    return crossings_into(c, rows, n_r, wr, wi, chain_next, g, ncc, diff);
 }
 
 } // namespace mlcc

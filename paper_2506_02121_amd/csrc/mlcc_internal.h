@@ -230,6 +230,12 @@ mlcc_status launch_map_caustics(Ctx *c, int64_t count, const double *zr, const d
 mlcc_status run_caustic_crossings(Ctx *c, int64_t rows, int64_t n_r, const double *wr,
                                   const double *wi, const int32_t *chain_next,
                                   const mlcc_grid *g, int32_t *ncc);
+mlcc_status run_caustic_crossings_noalloc(Ctx *c, int64_t rows, int64_t n_r, const double *wr,
+                                          const double *wi, const int32_t *chain_next,
+                                          const mlcc_grid *g, int32_t *ncc);
+// Looks up, once per device (the device current), the device address of the
+// allocation-free crossing map's fixed scratch array (crossings.hip).
+mlcc_status noalloc_scratch_init(int device);
 mlcc_status launch_caustic_distances(Ctx *c, const mlcc_grid *g, const int32_t *ncc,
                                      double *dist, uint8_t *border_limited);
 

@@ -31,6 +31,7 @@ MLCC_ERR_MATCH = -7
 MLCC_FP64 = 0
 MLCC_MIXED = 1
 MLCC_FP64_R32 = 2
+MLCC_NOALLOC_MAX_PIXELS = 2048 * 2048
 PRECISIONS = {"fp64": MLCC_FP64, "mixed": MLCC_MIXED, "fp64_r32": MLCC_FP64_R32}
 
 EXPORTED = [
@@ -40,6 +41,7 @@ EXPORTED = [
     "mlcc_caustic_crossings", "mlcc_caustic_distances",
     "mlcc_set_lenses_rect", "mlcc_rect_taylor_degree", "mlcc_num_roots",
     "mlcc_caustic_distances_directional", "mlcc_distance_histogram",
+    "mlcc_caustic_crossings_noalloc",
 ]
 
 
@@ -99,6 +101,8 @@ _SIG = {
     "mlcc_map_caustics": ([_vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
     "mlcc_caustic_crossings": ([_vp, _i64, _i64, _vp, _vp, _vp, ctypes.POINTER(GridC), _vp],
                                ctypes.c_int),
+    "mlcc_caustic_crossings_noalloc": ([_vp, _i64, _i64, _vp, _vp, _vp, ctypes.POINTER(GridC),
+                                        _vp], ctypes.c_int),
     "mlcc_caustic_distances": ([_vp, ctypes.POINTER(GridC), _vp, _vp, _vp], ctypes.c_int),
     "mlcc_set_lenses_rect": ([_vp, _i64, _vp, _vp, _vp, _d, _d, _d, _d, _d, ctypes.c_int32],
                              ctypes.c_int),
@@ -323,7 +327,11 @@ class Context:
         return wr, wi
 
     def caustic_crossings(self, w_re: torch.Tensor, w_im: torch.Tensor,
-                          chain_next: Optional[torch.Tensor], grid, out=None):
+                          chain_next: Optional[torch.Tensor], grid, out=None,
+                          noalloc: bool = False):
+        """N_cc map; noalloc=True calls mlcc_caustic_crossings_noalloc (fixed
+        device scratch, at most MLCC_NOALLOC_MAX_PIXELS pixels; `out` should
+        then be given, or torch allocates it here)."""
         _need(w_re, torch.float64, self.device, "w_re")
         _need(w_im, torch.float64, self.device, "w_im")
         if w_re.dim() != 2 or w_re.shape != w_im.shape:
@@ -335,9 +343,9 @@ class Context:
                                                       device=self.device)
         self._stream()
         gc = g.c()
-        _check(_lib.mlcc_caustic_crossings(self._h, w_re.shape[0], w_re.shape[1], _ptr(w_re),
-                                           _ptr(w_im), _ptr(chain_next), ctypes.byref(gc),
-                                           _ptr(ncc)))
+        fn = _lib.mlcc_caustic_crossings_noalloc if noalloc else _lib.mlcc_caustic_crossings
+        _check(fn(self._h, w_re.shape[0], w_re.shape[1], _ptr(w_re), _ptr(w_im),
+                  _ptr(chain_next), ctypes.byref(gc), _ptr(ncc)))
         return ncc
 
     def caustic_distances(self, grid, ncc: torch.Tensor, border_limited: bool = True, out=None):
