@@ -83,7 +83,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--schedule", default="persistent", choices=["rounds", "persistent"],
                     help="root-finder scheduling: global rounds, or one persistent launch")
-    ap.add_argument("--cpu-rows", type=int, default=6,
+    ap.add_argument("--cpu-rows", type=int, default=12,
                     help="warm rows of the oracle timed for the CPU baseline")
     ap.add_argument("--star-sums", dest="star_sums", default="direct", choices=["direct", "fmm"],
                     help="star sums of the timed run: direct, or fast multipole")
@@ -668,7 +668,8 @@ def batched_block(args, wl, precision, steps, warmup, serial, fp64, multipole, o
                 "fields": [int(i) for i in picks], "n_stars": [int(fs[i].n) for i in picks],
                 "rows": sample_rows}
 
-    elapsed, stats = timed(precision, warmup, steps)
+    star_sums = getattr(args, "star_sums", "direct") if args.workload == "batched" else "direct"
+    elapsed, stats = timed(precision, warmup, steps, star_sums=star_sums)
     roots_per_step = m_steps * 2 * n_tot
     s0 = stats[-1]
     blk = {
@@ -676,8 +677,8 @@ def batched_block(args, wl, precision, steps, warmup, serial, fp64, multipole, o
         "ms_per_step": 1e3 * elapsed / steps,
         "config": {"fields": len(fs), "total_stars": n_tot, "roots_per_row": 2 * n_tot,
                    "phase_steps": m_steps, "precision": precision, "predictor": args.predictor,
-                   "schedule": args.schedule, "seed": args.seed},
-        "roofline": roofline(stats, "batched", "direct"),
+                   "schedule": args.schedule, "star_sums": star_sums, "seed": args.seed},
+        "roofline": roofline(stats, "batched", star_sums),
         "stats": {k: s0[k] for k in ("sweeps", "root_updates", "root_updates_f32",
                                      "polish_updates", "rows_fallback", "n_subchains",
                                      "cold_sweeps", "max_row_sweeps", "match_maxdist")},
@@ -695,7 +696,7 @@ def batched_block(args, wl, precision, steps, warmup, serial, fp64, multipole, o
                                f.kappa_s, f.gamma)
                 ctx.find_critical_curves(
                     m_steps, caustics=True, precision=precision, predictor=args.predictor,
-                    schedule=args.schedule,
+                    schedule=args.schedule, star_sums=star_sums,
                     out=(roots_re[sl].view(shape), roots_im[sl].view(shape)),
                     caustics_out=(w_re[sl].view(shape), w_im[sl].view(shape)))
             torch.cuda.synchronize()
@@ -709,14 +710,14 @@ def batched_block(args, wl, precision, steps, warmup, serial, fp64, multipole, o
             "speedup_of_batched": el_s / (elapsed / steps), "accuracy": accuracy()}
         log(f"batched: serial {el_s:.3f} s for {len(fs)} calls")
     if fp64 and precision != "fp64":
-        el2, st2 = timed("fp64", 0, 1)
+        el2, st2 = timed("fp64", 0, 1, star_sums=star_sums)
         ks2 = root_kernels(st2)
         blk["fp64"] = {
             "what": "the same batch in one call, plain FP64",
             "value": roots_per_step / el2, "ms_per_step": 1e3 * el2, "steps": 1,
             "speedup_of_timed_form_over_fp64": el2 / (elapsed / steps),
             "frac": ks2[0]["frac"], "accuracy": accuracy()}
-    if multipole:
+    if multipole and star_sums == "direct":
         try:
             el3, st3 = timed(precision, 1, steps, "fmm", f"{precision} multipole")
             blk["multipole"] = {

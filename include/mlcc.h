@@ -77,7 +77,8 @@ typedef enum {
     MLCC_SCHEDULE_ROUNDS = 0,     /* global rounds: every front's pass, then a control kernel
                                      advancing all fronts; batches of rounds run as hipGraphs;
                                      per-kind kernel times in the stats */
-    MLCC_SCHEDULE_PERSISTENT = 1  /* the default: one persistent launch, (front, block) passes
+    MLCC_SCHEDULE_PERSISTENT = 1  /* the default: one persistent launch (captured into a
+                                     hipGraph and run from it), (front, block) passes
                                      from a device-side queue, each front advanced by the work
                                      group that finishes its pass, no global rounds.  Same
                                      results bit for bit; no front waits for the slowest pass

@@ -200,6 +200,25 @@ __device__ __forceinline__ void wave_sum(double &v)
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
 }
 
+// Agent-scope atomic loads: what another work group published reaches this
+// one through them whichever XCD (and L2) each runs on.
+__device__ __forceinline__ unsigned long long load_acquire(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t load_acquire(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long load_relaxed(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t load_relaxed(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------------------
 // FP64 Aberth sweep
 // ---------------------------------------------------------------------------
@@ -295,7 +314,10 @@ __device__ __forceinline__ void add_star_inv(Sums &S, double dx, double dy, doub
                                              const T &s)
 {
     // u = conj(d) / |d|^2 = ux - i uy, with a = ux^2, b = uy^2:
-    //   u^2 = (a - b) - 2 i ux uy,   u^3 = ux (a - 3b) + i uy (b - 3a)
+    //   u^2 = (a - b) - 2 i ux uy,   u^3 = ux (a - 3b) + i uy (b - 3a),
+    // and since a + b = |u|^2 = inv, a - 3b = inv - 4b and b - 3a = inv - 4a:
+    // -4 is an inline constant of the three-operand FP64 FMA, while -3 would
+    // take the two-operand accumulating form and a register copy per term.
     const double ux = dx * inv;
     const double uy = dy * inv;
     const double a = ux * ux, b = uy * uy;
@@ -304,8 +326,8 @@ __device__ __forceinline__ void add_star_inv(Sums &S, double dx, double dy, doub
     if (EQUAL) {
         S.s2r += a - b;
         S.s2i = fma(ux, uy, S.s2i);
-        S.s3r = fma(ux, fma(-3.0, b, a), S.s3r);
-        S.s3i = fma(uy, fma(-3.0, a, b), S.s3i);
+        S.s3r = fma(ux, fma(-4.0, b, inv), S.s3r);
+        S.s3i = fma(uy, fma(-4.0, a, inv), S.s3i);
     } else {
         const double mi = StarRec<EQUAL>::mass(s);
         const double mux = mi * ux, muy = mi * uy;
@@ -313,8 +335,8 @@ __device__ __forceinline__ void add_star_inv(Sums &S, double dx, double dy, doub
         S.s0i -= muy;
         S.s2r = fma(mi, a - b, S.s2r);
         S.s2i = fma(mux, uy, S.s2i);
-        S.s3r = fma(mux, fma(-3.0, b, a), S.s3r);
-        S.s3i = fma(muy, fma(-3.0, a, b), S.s3i);
+        S.s3r = fma(mux, fma(-4.0, b, inv), S.s3r);
+        S.s3i = fma(muy, fma(-4.0, a, inv), S.s3i);
     }
 }
 
@@ -542,6 +564,24 @@ constexpr int FMM_POLISH_STEPS = 3;
 #define MLCC_FMM_XROWS 7
 #endif
 constexpr int FMM_XROWS = MLCC_FMM_XROWS;
+
+// With direct star sums a pass over a few dozen stars is short, and the
+// queue claim, the fences and the front's advance cost more than its sums:
+// fields of at most XROWS_DIRECT_MAX_N stars also let a polish pass go on
+// through up to DIRECT_XROWS further rows.  Larger fields keep one row per
+// pass: the front keeps only the rows every one of its blocks finished, so
+// with more blocks per front more of the further rows are thrown away, and
+// their passes are long enough to pay for the queue (measured on batches of
+// equal fields: 2.4x faster at N = 50, 1.7x at 100, 1.1x at 200, 3x slower
+// at 500).
+#ifndef MLCC_XROWS_DIRECT_MAX_N
+#define MLCC_XROWS_DIRECT_MAX_N 160
+#endif
+#ifndef MLCC_DIRECT_XROWS
+#define MLCC_DIRECT_XROWS 7
+#endif
+constexpr int XROWS_DIRECT_MAX_N = MLCC_XROWS_DIRECT_MAX_N;
+constexpr int DIRECT_XROWS = MLCC_DIRECT_XROWS;
 
 // ---------------------------------------------------------------------------
 // Fast multipole star sums (Sec. 4.1: near stars directly, far stars through
@@ -824,10 +864,11 @@ template <class T> struct RoundArgs {
     double2 *iter0, *iter1;
     const double *sheet; // rectangular fields' sheet records (Real::sheet_off)
     const FmmArgs *fmm;  // fast multipole star sums: one record per field (kernels built with them)
-    // Several rows per polish pass (persistent schedule, multipole sums; null
+    // Several rows per polish pass (persistent schedule, mixed form; null
     // otherwise): per front the fewest further rows any block of the pass
-    // finished (reset to xrow_max by the front's finisher), and the stride
-    // of the row-sum slots (the launch's block count).
+    // finished (reset to its field's Real::xrows by the front's finisher), the
+    // largest Real::xrows of the call, and the stride of the row-sum slots
+    // (the launch's block count).
     int32_t *xrows;
     int32_t xrow_max;
     int32_t nvslots;
@@ -1206,7 +1247,8 @@ __device__ __forceinline__ void sweep_f32_pass(const RoundArgs<typename StarRec<
             [&](int, const T &s) {
                 const float dx = (float)(zr - s.x), dy = (float)(zi - s.y);
                 const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, dy * dy));
-                // as in add_star: p2i accumulates sum m ux uy (Im u^2 = -2 ux uy)
+                // as in add_star: p2i accumulates sum m ux uy (Im u^2 = -2 ux uy),
+                // and a - 3b = inv - 4b, b - 3a = inv - 4a
                 const float ux = dx * inv, uy = dy * inv;
                 const float a = ux * ux, b = uy * uy;
                 p1r += ux;
@@ -1214,15 +1256,15 @@ __device__ __forceinline__ void sweep_f32_pass(const RoundArgs<typename StarRec<
                 if (EQUAL) {
                     p2r += a - b;
                     p2i = fmaf(ux, uy, p2i);
-                    p3r = fmaf(ux, fmaf(-3.0f, b, a), p3r);
-                    p3i = fmaf(uy, fmaf(-3.0f, a, b), p3i);
+                    p3r = fmaf(ux, fmaf(-4.0f, b, inv), p3r);
+                    p3i = fmaf(uy, fmaf(-4.0f, a, inv), p3i);
                 } else {
                     const float mi = (float)StarRec<EQUAL>::mass(s);
                     const float mux = mi * ux, muy = mi * uy;
                     p2r = fmaf(mi, a - b, p2r);
                     p2i = fmaf(mux, uy, p2i);
-                    p3r = fmaf(mux, fmaf(-3.0f, b, a), p3r);
-                    p3i = fmaf(muy, fmaf(-3.0f, a, b), p3i);
+                    p3r = fmaf(mux, fmaf(-4.0f, b, inv), p3r);
+                    p3i = fmaf(muy, fmaf(-4.0f, a, inv), p3i);
                 }
             },
             [&]() {
@@ -1352,7 +1394,8 @@ __device__ __forceinline__ void add_star_polish_inv(PSums &S, double dx, double 
                                                     const T &s)
 {
     // u = ux - i uy, a = ux^2, b = uy^2:  u^2 = (a - b) - 2i ux uy,
-    // u^3 = ux (a - 3b) + i uy (b - 3a),  |u|^4 = inv^2
+    // u^3 = ux (a - 3b) + i uy (b - 3a) = ux (inv - 4b) + i uy (inv - 4a)
+    // (a + b = inv; see add_star_inv),  |u|^4 = inv^2
     // (s2i accumulates sum m ux uy; polish_finish turns it into Im s2 = -2 that)
     const double ux = dx * inv;
     const double uy = dy * inv;
@@ -1361,8 +1404,8 @@ __device__ __forceinline__ void add_star_polish_inv(PSums &S, double dx, double 
         S.s0r += ux; S.s0i -= uy;
         S.s2r += a - b;
         S.s2i = fma(ux, uy, S.s2i);
-        S.s3r = fma(ux, fma(-3.0, b, a), S.s3r);
-        S.s3i = fma(uy, fma(-3.0, a, b), S.s3i);
+        S.s3r = fma(ux, fma(-4.0, b, inv), S.s3r);
+        S.s3i = fma(uy, fma(-4.0, a, inv), S.s3i);
         S.q = fma(inv, inv, S.q);
     } else {
         const double mi = StarRec<EQUAL>::mass(s);
@@ -1370,8 +1413,8 @@ __device__ __forceinline__ void add_star_polish_inv(PSums &S, double dx, double 
         S.s0r += mux; S.s0i -= muy;
         S.s2r = fma(mi, a - b, S.s2r);
         S.s2i = fma(mux, uy, S.s2i);
-        S.s3r = fma(mux, fma(-3.0, b, a), S.s3r);
-        S.s3i = fma(muy, fma(-3.0, a, b), S.s3i);
+        S.s3r = fma(mux, fma(-4.0, b, inv), S.s3r);
+        S.s3i = fma(muy, fma(-4.0, a, inv), S.s3i);
         S.q = fma(mi * inv, inv, S.q);
     }
 }
@@ -1572,32 +1615,37 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
         if (n_after) atomicAdd(&A.counts[B.f], n_after);
     }
     int n_xsteps = 0;   // Newton steps this lane took in further rows
-    if constexpr (FMM) {
-        if (A.xrows) {
-            // Several rows per pass: once every root of the block is accepted
-            // in this row, the block goes on through the next rows of its
-            // front by itself, each root from the chain prediction of its own
-            // earlier rows, as the front's first pass of that row would (a
-            // Newton step couples no roots).  A row counts only when every
-            // root of the block is accepted in it: then its roots and caustics
-            // are written and its row sums kept in slot e; the first row that
-            // leaves a root open ends the pass, and nothing of it is kept.
-            // The front's last row is left to a pass of its own.
-            int done = 0;
-            if (B.dir != 0 && A.predictor > 0 && n_after == 0) {
-                double pr = fr_, pi = fi_;   // this root in the row before
-                for (int x = 1; x <= A.xrow_max; ++x) {
-                    BlockCtx<T> C = B;
-                    C.row = B.row + x * B.dir;
-                    if ((C.row - B.end_row) * B.dir >= 0) break;
-                    C.boundary = false;
-                    C.pred = min(A.predictor, min(B.hist + x, 3) - 1);
-                    const double2 un = A.unit[C.row];
-                    const double2 ex = make_double2(a * un.x, a * un.y);
-                    double xr = pr, xi = pi;
-                    if (valid) predict(A, C, k, xr, xi);
-                    bool open = valid;
-                    Update u{};
+    const int xmax = A.xrows ? A.reals[B.r].xrows : 0;
+    if (xmax > 0) {
+        // Several rows per pass: once every root of the block is accepted in
+        // this row, the block goes on through the next rows of its front by
+        // itself, each root from the chain prediction of its own earlier rows,
+        // as the front's first pass of that row would (a Newton step couples
+        // no roots).  A row counts only when every root of the block is
+        // accepted in it: then its roots and caustics are written and its row
+        // sums kept in slot x; the first row that leaves a root open ends the
+        // pass, and nothing of it is kept.  The front's last row is left to a
+        // pass of its own.
+        int done = 0;
+        if (B.dir != 0 && A.predictor > 0 && n_after == 0) {
+            double pr = fr_, pi = fi_;   // this root in the row before
+            const unsigned long long vmask = __ballot(valid);
+            for (int x = 1; x <= xmax; ++x) {
+                BlockCtx<T> C = B;
+                C.row = B.row + x * B.dir;
+                if ((C.row - B.end_row) * B.dir >= 0) break;
+                // another block of the front already stopped short of this row:
+                // the front will not keep it
+                if (load_relaxed(&A.xrows[B.f]) < x) break;
+                C.boundary = false;
+                C.pred = min(A.predictor, min(B.hist + x, 3) - 1);
+                const double2 un = A.unit[C.row];
+                const double2 ex = make_double2(a * un.x, a * un.y);
+                double xr = pr, xi = pi;
+                if (valid && C.pred) predict(A, C, k, xr, xi);
+                bool open = valid;
+                Update u{};
+                if constexpr (FMM) {
                     for (int it = 0; it < FMM_POLISH_STEPS; ++it) {
                         PSums S;
                         zero(S);
@@ -1630,28 +1678,68 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
                         }
                         if (!__ballot(open)) break;
                     }
-                    if (__ballot(open)) break;
-                    if (valid) put(A, C, k, u);
-                    double t1r = valid ? u.zr : 0.0, t1i = valid ? u.zi : 0.0;
-                    double t2r = valid ? u.zr * u.zr - u.zi * u.zi : 0.0;
-                    double t2i = valid ? 2.0 * u.zr * u.zi : 0.0;
-                    const double b2 = valid ? u.zr * u.zr + u.zi * u.zi : 0.0, b1 = sqrt(b2);
-                    const double ue = valid ? u.err : 0.0;
-                    double q_e = ue, q_e2 = ue * (2.0 * b1 + ue), q_a = b1, q_a2 = b2;
-                    wave_sum(t1r); wave_sum(t1i); wave_sum(t2r); wave_sum(t2i);
-                    wave_sum(q_e); wave_sum(q_e2); wave_sum(q_a); wave_sum(q_a2);
-                    if (lane == 0) {
-                        const int64_t sl = 2 * ((int64_t)x * A.nvslots + B.vslot);
-                        A.vieta[sl] = make_double4(t1r, t1i, t2r, t2i);
-                        A.vieta[sl + 1] = make_double4(q_e, q_e2, q_a, q_a2);
+                } else {
+                    // one Newton step per root from direct sums, exactly as
+                    // the first pass of the row takes it: the whole wave per
+                    // root when the block holds few roots, else one lane each
+                    if (__popcll(vmask) <= SPARSE_MAX) {
+                        unsigned long long mm = vmask;
+                        while (mm) {
+                            const int l = __ffsll((long long)mm) - 1;
+                            mm &= mm - 1;
+                            const double xk = __shfl(xr, l, 64), yk = __shfl(xi, l, 64);
+                            PSums S;
+                            zero(S);
+#pragma unroll 4
+                            for (int i = lane; i < n_stars; i += 64)
+                                add_star_polish<EQUAL>(S, xk, yk, stars[i]);
+                            wave_sum(S.s0r); wave_sum(S.s0i); wave_sum(S.s2r); wave_sum(S.s2i);
+                            wave_sum(S.s3r); wave_sum(S.s3i); wave_sum(S.q);
+                            const Update v = polish_finish<EQUAL>(S, xk, yk, m0, ex, gamma, a,
+                                                                  a1, tol_step2, tol_mu, k0 + l);
+                            if (lane == l) u = v;
+                        }
+                    } else {
+                        PSums S;
+                        zero(S);
+                        stream_tiles_grouped(stars, n_stars, reinterpret_cast<T *>(tiles),
+                                             [&](const T &s) { add_star_polish<EQUAL>(S, xr, xi, s); },
+                                             [&](const T &s, const T &t) {
+                                                 add_star_polish_pair<EQUAL>(S, xr, xi, s, t);
+                                             },
+                                             [&](const T &s, const T &t, const T &v, const T &w) {
+                                                 add_star_polish_quad<EQUAL>(S, xr, xi, s, t, v, w);
+                                             });
+                        u = polish_finish<EQUAL>(S, xr, xi, m0, ex, gamma, a, a1, tol_step2, tol_mu,
+                                                 k);
                     }
-                    pr = u.zr;
-                    pi = u.zi;
-                    done = x;
+                    open = valid && !u.flag;
                 }
+                // (with direct sums the finisher counts the rows the front keeps)
+                if (__ballot(open)) {
+                    if (lane == 0) atomicMin(&A.xrows[B.f], done);   // tell the other blocks now
+                    break;
+                }
+                if (valid) put(A, C, k, u);
+                double t1r = valid ? u.zr : 0.0, t1i = valid ? u.zi : 0.0;
+                double t2r = valid ? u.zr * u.zr - u.zi * u.zi : 0.0;
+                double t2i = valid ? 2.0 * u.zr * u.zi : 0.0;
+                const double b2 = valid ? u.zr * u.zr + u.zi * u.zi : 0.0, b1 = sqrt(b2);
+                const double ue = valid ? u.err : 0.0;
+                double q_e = ue, q_e2 = ue * (2.0 * b1 + ue), q_a = b1, q_a2 = b2;
+                wave_sum(t1r); wave_sum(t1i); wave_sum(t2r); wave_sum(t2i);
+                wave_sum(q_e); wave_sum(q_e2); wave_sum(q_a); wave_sum(q_a2);
+                if (lane == 0) {
+                    const int64_t sl = 2 * ((int64_t)x * A.nvslots + B.vslot);
+                    A.vieta[sl] = make_double4(t1r, t1i, t2r, t2i);
+                    A.vieta[sl + 1] = make_double4(q_e, q_e2, q_a, q_a2);
+                }
+                pr = u.zr;
+                pi = u.zi;
+                done = x;
             }
-            if (lane == 0) atomicMin(&A.xrows[B.f], done);
         }
+        if (lane == 0) atomicMin(&A.xrows[B.f], done);
     }
     // updates of the pass: one per active root, or its Newton steps (those of
     // further rows included)
@@ -2055,23 +2143,6 @@ struct PQueue {
 // Slot sequence numbers are spread one per 64-byte line.
 constexpr int SEQ_STRIDE = 8;
 
-__device__ __forceinline__ unsigned long long load_acquire(const unsigned long long *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int32_t load_acquire(const int32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long load_relaxed(const unsigned long long *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int32_t load_relaxed(const int32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Queues the bpf block passes of front f (whole wave).
 __device__ __forceinline__ void push_front(PQueue *q, int2 *tasks, unsigned long long *seq,
                                            unsigned long long mask, int f, int bpf)
@@ -2201,7 +2272,7 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
             if (A.xrows && ph0 == PH_POLISH) {
                 // further rows the pass finished in every block (see polish_pass)
                 xr = A.xrows[tf];
-                A.xrows[tf] = A.xrow_max;
+                A.xrows[tf] = R->xrows;
                 if (!(dir0 != 0 && fr.state == FRONT_ACTIVE && fr.phase == PH_POLISH &&
                       fr.row == row0 + dir0))
                     xr = 0;
@@ -2233,6 +2304,15 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
             moved = x;
         }
         if (lane == 0) {
+            if constexpr (!FMM) {
+                // the further rows the front keeps, one Newton step per root
+                // each, as the first pass of each row would have counted them
+                if (moved) {
+                    const unsigned long long ux = (unsigned long long)moved * (unsigned)R->n_r;
+                    atomicAdd(&A.ctl->polish_updates, ux);
+                    atomicAdd(&A.ctl->star_updates_polish, ux * (unsigned)R->n_stars);
+                }
+            }
             if (moved) fr.fresh = 2;   // its first pass takes the previous row from the output
             fronts_w[tf] = fr;
             state = fr.state;
@@ -2568,6 +2648,14 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         R.tol2 = 16.0 * u_ro * h.sum_abs_z2;
         R.root32 = p->precision == MLCC_FP64_R32 ? 1 : 0;
         R.restart = p->cold_restart_sweeps > 0 ? p->cold_restart_sweeps : STALL_START;
+        // further rows per polish pass (persistent mixed form with the chain
+        // predictor): every field with multipole sums, small fields with direct
+        // ones
+        R.xrows = 0;
+        if (mixed && p->schedule == MLCC_SCHEDULE_PERSISTENT && p->predictor > 0) {
+            if (p->star_sums == MLCC_STARS_FMM) R.xrows = FMM_XROWS;
+            else if (h.n <= XROWS_DIRECT_MAX_N) R.xrows = DIRECT_XROWS;
+        }
         const int bpf = (int)ceil_div(n_r, 64);
         for (int s = 0; s < S; ++s) {
             const int32_t lo = (int32_t)(s * L), hi = (int32_t)(lo + L), cen = (int32_t)(lo + L / 2);
@@ -2644,12 +2732,12 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     MLCC_TRY(c->control.reserve(sizeof(Control)));
     MLCC_TRY(c->etab.reserve((size_t)(m + 1) * sizeof(double2)));
     MLCC_TRY(c->bnd.reserve((size_t)std::max<int64_t>(bnd_total, 1) * sizeof(double2)));
-    // several rows per polish pass: the persistent schedule with multipole
-    // sums in the mixed form keeps row sums for FMM_XROWS further rows
-    const bool xrows_on = mixed && p->star_sums == MLCC_STARS_FMM &&
-                          p->schedule == MLCC_SCHEDULE_PERSISTENT && p->predictor > 0;
-    MLCC_TRY(c->vieta.reserve((size_t)2 * (xrows_on ? FMM_XROWS + 1 : 1) * nblocks *
-                              sizeof(double4)));
+    // several rows per polish pass: row sums for the most further rows any
+    // field takes
+    int xrow_max = 0;
+    for (const Real &R : rd) xrow_max = std::max(xrow_max, (int)R.xrows);
+    const bool xrows_on = xrow_max > 0;
+    MLCC_TRY(c->vieta.reserve((size_t)2 * (xrow_max + 1) * nblocks * sizeof(double4)));
     MLCC_TRY(c->vsum.reserve((size_t)2 * F * sizeof(double4)));
     if (mixed) MLCC_TRY(c->errbuf.reserve((size_t)it_total * sizeof(double)));
     MLCC_TRY(c->reals_d.reserve((size_t)n_real * sizeof(Real)));
@@ -2914,7 +3002,8 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         unsigned long long *dseq = reinterpret_cast<unsigned long long *>(base + o_seq);
         int32_t *dfdone = reinterpret_cast<int32_t *>(base + o_fdone);
         int32_t *dxrows = reinterpret_cast<int32_t *>(base + o_xrows);
-        const std::vector<int32_t> xr0((size_t)F, FMM_XROWS);
+        std::vector<int32_t> xr0((size_t)F, 0);
+        for (int f = 0; f < F; ++f) xr0[f] = rd[fr[f].real].xrows;
         std::vector<int2> t0;
         for (int f = 0; f < F; ++f) {
             if (fr[f].state != FRONT_ACTIVE) continue;
@@ -2936,7 +3025,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
                                     hipMemcpyHostToDevice, rs));
         auto set_xrows = [&](auto &A) {
             A.xrows = xrows_on ? dxrows : nullptr;
-            A.xrow_max = xrows_on ? FMM_XROWS : 0;
+            A.xrow_max = xrow_max;
             A.nvslots = (int32_t)nblocks;
         };
         int cus = 0, per_cu = 0, clock_khz = 0;
@@ -2955,49 +3044,70 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         // finished anywhere
         const unsigned long long stall =
             (unsigned long long)clock_khz * (unsigned long long)(p->watchdog_ms > 0 ? p->watchdog_ms : 5000);
+        const double2 *cur0 = c->iter[0].as<double2>();
+        // The one launch is captured into a hipGraph (a single kernel node; the
+        // queue and counters above are set by copies outside it) and run from
+        // the graph.
+        auto launch = [&]() {
+            if (equal) {
+                fill(A2, stars2, cur0, c->iter[1].as<double2>());
+                set_xrows(A2);
+                A2.persistent = 1;
+                A2.iter0 = c->iter[0].as<double2>();
+                A2.iter1 = c->iter[1].as<double2>();
+                if (fmm_on)
+                    hipLaunchKernelGGL((aberth_persistent<true, true>), dim3(workers), dim3(64), 0,
+                                       rs, A2, c->fronts.as<Front>(), dq, dtasks, dseq,
+                                       (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
+                                       stall);
+                else
+                    hipLaunchKernelGGL((aberth_persistent<true, false>), dim3(workers), dim3(64), 0,
+                                       rs, A2, c->fronts.as<Front>(), dq, dtasks, dseq,
+                                       (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
+                                       stall);
+            } else {
+                fill(A4, stars4, cur0, c->iter[1].as<double2>());
+                set_xrows(A4);
+                A4.persistent = 1;
+                A4.iter0 = c->iter[0].as<double2>();
+                A4.iter1 = c->iter[1].as<double2>();
+                if (fmm_on)
+                    hipLaunchKernelGGL((aberth_persistent<false, true>), dim3(workers), dim3(64), 0,
+                                       rs, A4, c->fronts.as<Front>(), dq, dtasks, dseq,
+                                       (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
+                                       stall);
+                else
+                    hipLaunchKernelGGL((aberth_persistent<false, false>), dim3(workers), dim3(64), 0,
+                                       rs, A4, c->fronts.as<Front>(), dq, dtasks, dseq,
+                                       (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
+                                       stall);
+            }
+        };
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t gx = nullptr;
+        MLCC_HIP(hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal));
+        launch();
+        const hipError_t le = hipGetLastError();
+        hipError_t e = hipStreamEndCapture(rs, &graph);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            MLCC_HIP(le);
+            MLCC_HIP(e);
+        }
+        e = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        MLCC_HIP(e);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (p->timing) {
             MLCC_HIP(hipEventCreate(&e0));
             MLCC_HIP(hipEventCreate(&e1));
             MLCC_HIP(hipEventRecord(e0, rs));
         }
-        const double2 *cur0 = c->iter[0].as<double2>();
-        if (equal) {
-            fill(A2, stars2, cur0, c->iter[1].as<double2>());
-            set_xrows(A2);
-            A2.persistent = 1;
-            A2.iter0 = c->iter[0].as<double2>();
-            A2.iter1 = c->iter[1].as<double2>();
-            if (fmm_on)
-                hipLaunchKernelGGL((aberth_persistent<true, true>), dim3(workers), dim3(64), 0, rs,
-                                   A2, c->fronts.as<Front>(), dq, dtasks, dseq,
-                                   (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
-                                   stall);
-            else
-                hipLaunchKernelGGL((aberth_persistent<true, false>), dim3(workers), dim3(64), 0, rs,
-                                   A2, c->fronts.as<Front>(), dq, dtasks, dseq,
-                                   (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
-                                   stall);
-        } else {
-            fill(A4, stars4, cur0, c->iter[1].as<double2>());
-            set_xrows(A4);
-            A4.persistent = 1;
-            A4.iter0 = c->iter[0].as<double2>();
-            A4.iter1 = c->iter[1].as<double2>();
-            if (fmm_on)
-                hipLaunchKernelGGL((aberth_persistent<false, true>), dim3(workers), dim3(64), 0, rs,
-                                   A4, c->fronts.as<Front>(), dq, dtasks, dseq,
-                                   (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
-                                   stall);
-            else
-                hipLaunchKernelGGL((aberth_persistent<false, false>), dim3(workers), dim3(64), 0,
-                                   rs, A4, c->fronts.as<Front>(), dq, dtasks, dseq,
-                                   (unsigned long long)(cap - 1), dfdone, F, max_cold, max_warm,
-                                   stall);
-        }
-        MLCC_HIP(hipGetLastError());
-        if (p->timing) MLCC_HIP(hipEventRecord(e1, rs));
-        MLCC_HIP(hipStreamSynchronize(rs));
+        e = hipGraphLaunch(gx, rs);
+        if (e == hipSuccess && p->timing) e = hipEventRecord(e1, rs);
+        if (e == hipSuccess) e = hipStreamSynchronize(rs);
+        (void)hipGraphExecDestroy(gx);
+        MLCC_HIP(e);
         if (p->timing) {
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);

@@ -98,6 +98,8 @@ struct Real {
     int32_t n_extra;    // roots beyond 2 N: t - 1 for a rectangular field
     int32_t root32;     // MLCC_FP64_R32: warm FP64 rows take the root-root sum in FP32
     int32_t restart;    // FP64 sweeps after which an unsettled cold start begins again
+    int32_t xrows;      // persistent mixed form: further rows a polish pass may finish (0: none)
+    int32_t pad_;
     int64_t sheet_off;  // its record in the sheet array: d_2..d_{t-1} (n_poly), the lens-map
                         // terms d_2k / (2k + 1) (n_poly), start values of the extra roots
                         // (2 n_extra: re, im)
