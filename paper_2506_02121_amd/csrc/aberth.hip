@@ -2377,11 +2377,16 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
 // latency of its chain of dependent loads (cell, coefficients chunk by
 // chunk, near-cell ranges): measured on n10k at 4 waves per SIMD, a polish
 // pass occupies ~94k SIMD cycles whatever N, and the star part of a sweep
-// is priced the same; the root terms keep their cost.
+// is priced the same; the root terms keep their cost.  In the persistent
+// mixed form a multipole polish pass goes on through up to 7 further rows
+// (polish_pass): a front then needs ~6x fewer passes in a row per row, which
+// an S sweep of n10k (S = 5 ... 40: 299, 288, 289, 303, 311, 340 ms at S = 5,
+// 8, 10, 20, 25, 40) and of the batched workload (S = 2 best) bear out.
 struct TuneModel {
     double cold_sweeps = 27.0, rounds_per_row = 2.1, tail = 0.8, round_us = 40.0;
     double clock_hz = 2.4e9, simds = 1024.0;
     double fmm_star_cycles = 94000.0;
+    double fmm_rows_per_pass = 6.0;
 };
 
 static double pass_cycles(int kind, double n, bool fmm)
@@ -2394,7 +2399,7 @@ static double pass_cycles(int kind, double n, bool fmm)
 }
 
 static double predicted_seconds(const std::vector<RealHost> &reals, int64_t m, int64_t s, bool mixed,
-                         int predictor, bool fmm)
+                         int predictor, bool fmm, bool xrows)
 {
     const TuneModel tm;
     double work = 0.0, blocks_all = 0.0, longest = 0.0;
@@ -2417,7 +2422,9 @@ static double predicted_seconds(const std::vector<RealHost> &reals, int64_t m, i
     // about half of the 2S fronts are in a full pass at any time
     const double waves = (double)s * blocks_all;
     const double simds = std::min(tm.simds, std::max(1.0, waves / 2.0));
-    const double rounds = tm.rounds_per_row * (double)(m / 2) / (double)s + tm.cold_sweeps;
+    const double rows_per_pass = (xrows && mixed && fmm && predictor > 0) ? tm.fmm_rows_per_pass : 1.0;
+    const double rounds =
+        tm.rounds_per_row * (double)(m / 2) / (double)s / rows_per_pass + tm.cold_sweeps;
     return work / (simds * tm.clock_hz) +
            rounds * (tm.tail * longest / tm.clock_hz + tm.round_us * 1e-6);
 }
@@ -2427,7 +2434,7 @@ static double predicted_seconds(const std::vector<RealHost> &reals, int64_t m, i
 // predicted time among those that leave every subchain at least 16 rows and
 // keep the front table within MAX_FRONTS.
 static int autotune_subchains(const std::vector<RealHost> &reals, int64_t m, bool mixed,
-                              int predictor, bool fmm)
+                              int predictor, bool fmm, bool persistent)
 {
     const int64_t half = m / 2;
     const int64_t s_max = std::max<int64_t>(
@@ -2436,7 +2443,7 @@ static int autotune_subchains(const std::vector<RealHost> &reals, int64_t m, boo
     int best_s = 1;
     for (int64_t s = 1; s <= std::min<int64_t>(half, std::min<int64_t>(s_max, 4096)); ++s) {
         if (half % s) continue;
-        const double t = predicted_seconds(reals, m, s, mixed, predictor, fmm);
+        const double t = predicted_seconds(reals, m, s, mixed, predictor, fmm, persistent);
         if (t < best * 0.999) {
             best = t;
             best_s = (int)s;
@@ -2589,7 +2596,8 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     int S = p->n_subchains;
     if (S <= 0)
         S = autotune_subchains(c->reals, m, mixed, p->predictor,
-                               p->star_sums == MLCC_STARS_FMM);
+                               p->star_sums == MLCC_STARS_FMM,
+                               p->schedule == MLCC_SCHEDULE_PERSISTENT);
     if ((m / 2) % S) return fail(MLCC_ERR_INVALID, "n_subchains=%d must divide m/2", S);
     const int64_t L = m / S;
     const int max_cold = p->max_iter_cold > 0 ? p->max_iter_cold : 500;
