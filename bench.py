@@ -812,6 +812,9 @@ def cpu_baseline(f, m_steps, rows):
                    f"untimed cold start at row {c}: {ups} root updates in {dt:.1f} s"),
         "one_thread": {"value": n_r / dt1, "unit": "roots/s",
                        "sample": f"warm row {c + rows + 1}: {up1} root updates in {dt1:.1f} s"},
+        # per root update (one pass of a root over the stars and the other
+        # roots), the unit that does not depend on how a row is warm-started
+        "root_updates_per_s": ups / dt,
     }
     out.update(host_cpu())
     return out

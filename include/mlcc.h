@@ -49,8 +49,8 @@ typedef enum {
                       precision.  Each reciprocal 1/|d|^2 is the hardware estimate
                       refined by one Newton step (relative error below 2^-47, against
                       2^-53 for a correctly rounded division); consecutive star terms,
-                      and consecutive root-root terms, are taken in pairs that share
-                      one refined reciprocal of the product of their two |d|^2 */
+                      and consecutive root-root terms, are taken in groups of four that
+                      share one refined reciprocal of the product of their four |d|^2 */
     MLCC_MIXED = 1,/* Aberth sweeps in FP32 (FP64 star distances, FP32 sums per tile of
                       64 stars carried in FP64), every root finished by FP64 Newton
                       polish passes that accept a root on the same cutoffs as the
@@ -60,8 +60,12 @@ typedef enum {
                       the polish straight from the chain prediction (predictor > 0),
                       else after one FP32 sweep.  A row the polish does not settle
                       gets one FP32 sweep and the polish again, then restarts from
-                      its start values with FP64 Aberth sweeps.  Results meet the
-                      same cutoffs as MLCC_FP64. */
+                      its start values with FP64 Aberth sweeps.  With the persistent
+                      schedule and the chain predictor a polish pass whose roots are
+                      all accepted goes on through up to 7 further rows of its front
+                      (multipole star sums; direct sums for fields of at most 160
+                      stars); the results are those of one row per pass.  Results
+                      meet the same cutoffs as MLCC_FP64. */
     MLCC_FP64_R32 = 2 /* not the paper's precision: MLCC_FP64, except that in warm rows
                       the root-root sum R = sum_{r != k} 1/(z_k - z_r) of the Aberth
                       correction is formed in FP32 (each coordinate split into an FP32
