@@ -45,7 +45,8 @@ def grid_for(ny, nx, h):
                nx=nx, ny=ny)
 
 
-ANGLES = [0.0, np.pi / 4, np.pi / 2, 0.3, 1.9, np.pi, 3.7, 5.0, 1.75 * np.pi]
+ANGLES = [0.0, np.pi / 4, np.pi / 2, 0.3, 1.9, 0.75 * np.pi, np.pi, 1.25 * np.pi, 3.7, 1.5 * np.pi, 5.0,
+          1.75 * np.pi]
 
 
 @pytest.mark.parametrize("angle", ANGLES)
