@@ -802,40 +802,79 @@ fmm_p2l(int32_t G, int32_t p, int32_t stride, double x0, double y0, double w, in
     if (lane == 0) qfar[cell] = q;
 }
 
-// Calls body(star) for the stars of the 3 x 3 cells around `cell`; returns
-// their number.
+// Calls body(star) for the stars of the 3 x 3 cells around `cell`, in the
+// order of the sorted list (the block's three grid rows, each a run of
+// adjacent cells), and returns their number.  The records are read
+// NEAR_BATCH at a time, all loads of a batch issued before the first body
+// runs: lanes of a wave sit in different cells, so every record is a
+// gather from L2, and one load per body would wait out that latency for
+// each near star.
+#ifndef MLCC_NEAR_BATCH
+#define MLCC_NEAR_BATCH 4
+#endif
+constexpr int NEAR_BATCH = MLCC_NEAR_BATCH;
+
 template <class Body>
 __device__ __forceinline__ int fmm_near(const FmmArgs &M, int cell, Body &&body)
 {
     if (cell < 0) return 0;
     const int ix = cell % M.G, iy = cell / M.G;
-    int n = 0;
-    for (int y = max(iy - 1, 0); y <= min(iy + 1, M.G - 1); ++y) {
-        const int q0 = y * M.G + max(ix - 1, 0), q1 = y * M.G + min(ix + 1, M.G - 1);
+    const int xa = max(ix - 1, 0), xb = min(ix + 1, M.G - 1);
+    int lo[3], len[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int y = iy - 1 + r;
         // the cells of one grid row are adjacent in the sorted order
+        const bool in = y >= 0 && y < M.G;
+        const int q0 = (in ? y : iy) * M.G + xa, q1 = (in ? y : iy) * M.G + xb;
         const int i0 = M.cell_start[q0], i1 = M.cell_start[q1 + 1];
-        n += i1 - i0;
-#pragma unroll 4
-        for (int i = i0; i < i1; ++i) body(M.fstars[i]);
+        lo[r] = i0;
+        len[r] = in ? i1 - i0 : 0;
+    }
+    const int l01 = len[0] + len[1], n = l01 + len[2];
+    for (int j = 0; j < n; j += NEAR_BATCH) {
+        double4 rec[NEAR_BATCH];
+#pragma unroll
+        for (int u = 0; u < NEAR_BATCH; ++u) {
+            const int t = j + u;
+            const int i = t < len[0] ? lo[0] + t : t < l01 ? lo[1] + (t - len[0]) : lo[2] + (t - l01);
+            rec[u] = M.fstars[t < n ? i : 0];   // past the end: a valid record, not used
+        }
+#pragma unroll
+        for (int u = 0; u < NEAR_BATCH; ++u)
+            if (j + u < n) body(rec[u]);
     }
     return n;
 }
 
-// Adds a wave's near-field star terms and far-field evaluations (lanes that
-// updated a root) to the totals behind the algorithmic FLOP count.
-// far[0]: evaluations, far[1]: evaluations times the field's star count
-// (the direct terms they replace).
-__device__ __forceinline__ void fmm_count(unsigned long long *near, unsigned long long *far,
-                                          bool act, int n_near, int n_stars)
+// A wave's multipole tallies (see FMM_STRIPES): near-field star terms,
+// far-field evaluations (lanes that updated a root) and those evaluations
+// times the field's star count (the direct terms they replace).  The values
+// are wave-uniform.
+struct FmmTally {
+    unsigned long long near = 0, far = 0, far_n = 0;
+};
+
+__device__ __forceinline__ void fmm_count(FmmTally &t, bool act, int n_near, int n_stars)
 {
     int v = act ? n_near : 0;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = __builtin_amdgcn_readfirstlane(v);
     const int n_act = __popcll(__ballot(act));
-    if ((threadIdx.x & 63) == 0 && n_act) {
-        atomicAdd(near, (unsigned long long)v);
-        atomicAdd(&far[0], (unsigned long long)n_act);
-        atomicAdd(&far[1], (unsigned long long)n_act * (unsigned long long)n_stars);
+    t.near += (unsigned long long)v;
+    t.far += (unsigned long long)n_act;
+    t.far_n += (unsigned long long)n_act * (unsigned long long)n_stars;
+}
+
+// Adds a wave's tallies to its work group's copy (kind: FMM_T_*).
+__device__ __forceinline__ void fmm_flush(unsigned long long *tally, int kind, const FmmTally &t)
+{
+    if ((threadIdx.x & 63) == 0 && t.far) {
+        unsigned long long *s = tally + (blockIdx.x % FMM_STRIPES) * FMM_STRIPE_U64 + kind;
+        atomicAdd(&s[0], t.near);
+        atomicAdd(&s[1], t.far);
+        atomicAdd(&s[2], t.far_n);
     }
 }
 
@@ -857,6 +896,7 @@ template <class T> struct RoundArgs {
     int32_t *counts;
     int32_t *passupd;  // per front: roots updated by this round's pass (the control kernel sums them)
     Control *ctl;
+    unsigned long long *fmm_tally;   // multipole tallies (FMM_STRIPES copies)
     double4 *vieta;    // two per block: row sums, and their error terms
     double *errbuf;    // estimated error of each polished root
     int32_t predictor;
@@ -1105,7 +1145,9 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
                 if constexpr (EQUAL) add_star<EQUAL>(S, zr, zi, make_double2(s4.x, s4.y));
                 else add_star<EQUAL>(S, zr, zi, s4);
             });
-            fmm_count(&A.ctl->fmm_near, A.ctl->fmm_far, act, n_near, n_stars);
+            FmmTally tl;
+            fmm_count(tl, act, n_near, n_stars);
+            fmm_flush(A.fmm_tally, FMM_T_F64, tl);
             // far terms in the accumulators' conventions (s2i holds -Im/2)
             S.s1r += g.x; S.s1i += g.y;
             if (!EQUAL) { S.s0r += f.x; S.s0i += f.y; }
@@ -1237,7 +1279,9 @@ __device__ __forceinline__ void sweep_f32_pass(const RoundArgs<typename StarRec<
             if constexpr (EQUAL) add_star<EQUAL>(S, zr, zi, make_double2(s4.x, s4.y));
             else add_star<EQUAL>(S, zr, zi, s4);
         });
-        fmm_count(&A.ctl->fmm_near_f32, A.ctl->fmm_far_f32, valid, n_near, n_stars);
+        FmmTally tl;
+        fmm_count(tl, valid, n_near, n_stars);
+        fmm_flush(A.fmm_tally, FMM_T_F32, tl);
         S1r = S.s1r + g.x; S1i = S.s1i + g.y;
         S2r = S.s2r - f1.x; S2i = S.s2i + 0.5 * f1.y;
         S3r = S.s3r + 0.5 * f2.x; S3i = S.s3i + 0.5 * f2.y;
@@ -1481,6 +1525,7 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
     double zr = 0.0, zi = 0.0;
     bool act = false;
     double er_ = 0.0;   // estimated error of the value this root ends the pass with
+    FmmTally ptl;       // multipole tallies of the whole pass, added once at its end
     if (valid) {
         if (B.from_out) {
             const int64_t o = B.out_off + (int64_t)(B.row - B.dir) * B.n_r + k;
@@ -1553,8 +1598,7 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
                         add_star_polish<EQUAL>(S, xr, xi, make_double2(s4.x, s4.y));
                     else add_star_polish<EQUAL>(S, xr, xi, s4);
                 });
-                fmm_count(&A.ctl->fmm_near_polish, A.ctl->fmm_far_polish, open, n_near,
-                          n_stars);
+                fmm_count(ptl, open, n_near, n_stars);
                 S.s0r += f.x; S.s0i += f.y;
                 S.s2r -= f1.x; S.s2i += 0.5 * f1.y;
                 S.s3r += 0.5 * f2.x; S.s3i += 0.5 * f2.y;
@@ -1658,8 +1702,7 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
                                 add_star_polish<EQUAL>(S, xr, xi, make_double2(s4.x, s4.y));
                             else add_star_polish<EQUAL>(S, xr, xi, s4);
                         });
-                        fmm_count(&A.ctl->fmm_near_polish, A.ctl->fmm_far_polish, open, n_near,
-                                  n_stars);
+                        fmm_count(ptl, open, n_near, n_stars);
                         S.s0r += f.x; S.s0i += f.y;
                         S.s2r -= f1.x; S.s2i += 0.5 * f1.y;
                         S.s3r += 0.5 * f2.x; S.s3i += 0.5 * f2.y;
@@ -1748,6 +1791,7 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
     for (int off = 32; off >= 1; off >>= 1) n_upd += __shfl_xor(n_upd, off, 64);
     if (n_steps < 0) n_upd += n_act;
     if (lane == 0 && n_upd) atomicAdd(&A.passupd[B.f], n_upd);
+    if constexpr (FMM) fmm_flush(A.fmm_tally, FMM_T_POLISH, ptl);
 }
 
 template <bool EQUAL, bool FMM>
@@ -2738,6 +2782,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     MLCC_TRY(c->counts.reserve((size_t)F * sizeof(int32_t)));
     MLCC_TRY(c->passupd.reserve((size_t)F * sizeof(int32_t)));
     MLCC_TRY(c->control.reserve(sizeof(Control)));
+    MLCC_TRY(c->fmm_tally.reserve((size_t)FMM_STRIPES * FMM_STRIPE_U64 * sizeof(uint64_t)));
     MLCC_TRY(c->etab.reserve((size_t)(m + 1) * sizeof(double2)));
     MLCC_TRY(c->bnd.reserve((size_t)std::max<int64_t>(bnd_total, 1) * sizeof(double2)));
     // several rows per polish pass: row sums for the most further rows any
@@ -2790,6 +2835,8 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
     MLCC_HIP(hipMemcpyAsync(c->control.p, &ctl0, sizeof ctl0, hipMemcpyHostToDevice, c->stream));
     MLCC_HIP(hipMemsetAsync(c->flagrow.p, 0xff, (size_t)it_total * sizeof(int32_t), c->stream));
     MLCC_HIP(hipMemsetAsync(c->counts.p, 0, F * sizeof(int32_t), c->stream));
+    MLCC_HIP(hipMemsetAsync(c->fmm_tally.p, 0,
+                            (size_t)FMM_STRIPES * FMM_STRIPE_U64 * sizeof(uint64_t), c->stream));
     MLCC_HIP(hipMemsetAsync(c->passupd.p, 0, F * sizeof(int32_t), c->stream));
     if (equal)
         hipLaunchKernelGGL(seed_centres<double2>, dim3((unsigned)ngrid), dim3(64), 0, c->stream,
@@ -2833,6 +2880,7 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         A.counts = c->counts.as<int32_t>();
         A.passupd = c->passupd.as<int32_t>();
         A.ctl = c->control.as<Control>();
+        A.fmm_tally = c->fmm_tally.as<unsigned long long>();
         A.vieta = c->vieta.as<double4>();
         A.predictor = p->predictor;
         A.errbuf = mixed ? c->errbuf.as<double>() : nullptr;
@@ -3182,10 +3230,22 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
 
     Control h{};
     MLCC_HIP(hipMemcpyAsync(&h, dctl, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    std::vector<uint64_t> tally((size_t)FMM_STRIPES * FMM_STRIPE_U64);
+    MLCC_HIP(hipMemcpyAsync(tally.data(), c->fmm_tally.p, tally.size() * sizeof(uint64_t),
+                            hipMemcpyDeviceToHost, c->stream));
     std::vector<Front> fin(F);
     MLCC_HIP(hipMemcpyAsync(fin.data(), c->fronts.p, F * sizeof(Front), hipMemcpyDeviceToHost,
                             c->stream));
     MLCC_HIP(hipStreamSynchronize(c->stream));
+    // the multipole tallies, summed over their copies
+    uint64_t ft[9] = {};
+    for (int q = 0; q < FMM_STRIPES; ++q)
+        for (int v = 0; v < 9; ++v) ft[v] += tally[(size_t)q * FMM_STRIPE_U64 + v];
+    const uint64_t fmm_near = ft[FMM_T_F64], fmm_far[2] = {ft[FMM_T_F64 + 1], ft[FMM_T_F64 + 2]};
+    const uint64_t fmm_near_polish = ft[FMM_T_POLISH],
+                   fmm_far_polish[2] = {ft[FMM_T_POLISH + 1], ft[FMM_T_POLISH + 2]};
+    const uint64_t fmm_near_f32 = ft[FMM_T_F32],
+                   fmm_far_f32[2] = {ft[FMM_T_F32 + 1], ft[FMM_T_F32 + 2]};
 
     mlcc_status result = MLCC_OK;
     double maxdist = 0.0;
@@ -3325,16 +3385,16 @@ mlcc_status find_critical_curves_impl(Ctx *c, const mlcc_cc_params *p, double *r
         if (fmm_on) {
             const double pf = (double)fmm_recs[0].p;
             const double unit_g = equal ? 0.0 : 8.0 * pf;
-            far64 = (double)h.fmm_far[0] * (26.0 * pf + 20.0 + unit_g) +
-                    (double)h.fmm_far_f32[0] * (26.0 * pf + 20.0 + unit_g) +
-                    29.0 * (double)h.fmm_near_f32;
-            farpol = (double)h.fmm_far_polish[0] * (26.0 * pf + 20.0);
-            star64 += (double)h.fmm_near - (double)h.fmm_far[1];
-            starpol += (double)h.fmm_near_polish - (double)h.fmm_far_polish[1];
-            star32_off = 29.0 * (double)h.fmm_far_f32[1];
-            stats->fmm_near_terms = (int64_t)(h.fmm_near + h.fmm_near_polish + h.fmm_near_f32);
+            far64 = (double)fmm_far[0] * (26.0 * pf + 20.0 + unit_g) +
+                    (double)fmm_far_f32[0] * (26.0 * pf + 20.0 + unit_g) +
+                    29.0 * (double)fmm_near_f32;
+            farpol = (double)fmm_far_polish[0] * (26.0 * pf + 20.0);
+            star64 += (double)fmm_near - (double)fmm_far[1];
+            starpol += (double)fmm_near_polish - (double)fmm_far_polish[1];
+            star32_off = 29.0 * (double)fmm_far_f32[1];
+            stats->fmm_near_terms = (int64_t)(fmm_near + fmm_near_polish + fmm_near_f32);
             stats->fmm_far_evals =
-                (int64_t)(h.fmm_far[0] + h.fmm_far_polish[0] + h.fmm_far_f32[0]);
+                (int64_t)(fmm_far[0] + fmm_far_polish[0] + fmm_far_f32[0]);
         }
         stats->algorithmic_flop = 29.0 * star64 + far64 +
                                   20.0 * (double)(h.star_updates - h.star_updates_fast) -

@@ -181,8 +181,8 @@ void mlcc_destroy(mlcc_ctx *ctx)
     (void)hipSetDevice(c.device);
     (void)hipStreamSynchronize(c.stream);
     DevBuf *bufs[] = {&c.stars, &c.mass, &c.stars4, &c.sheet_d, &c.sheet, &c.iter[0], &c.iter[1],
-                      &c.flagrow, &c.fronts, &c.counts, &c.control, &c.etab, &c.bnd, &c.perm,
-                      &c.match_aux, &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.vsum,
+                      &c.flagrow, &c.fronts, &c.counts, &c.control, &c.fmm_tally, &c.etab,
+                      &c.bnd, &c.perm, &c.match_aux, &c.relabel, &c.workflags, &c.vieta, &c.errbuf, &c.vsum,
                       &c.pq, &c.passupd, &c.reals_d, &c.bmap, &c.diff, &c.edt_col,
                       &c.dmask, &c.fmm_cs, &c.fmm_st, &c.fmm_st2, &c.fmm_cf, &c.fmm_cg,
                       &c.fmm_q, &c.fmm_m, &c.fmm_args};

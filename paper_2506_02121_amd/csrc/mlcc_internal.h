@@ -151,13 +151,17 @@ struct Control {
     unsigned long long star_updates_polish;
     unsigned long long updates_fast;      // FP64 Aberth updates of warm FP64-mode rows, whose
     unsigned long long star_updates_fast; // root-root terms run in FP32 (and their star counts)
-    // fast-multipole star sums: near-field star terms, far-field series
-    // evaluations ([0]) and those evaluations times their field's star count
-    // ([1]) of the updates that took them (FP64 sweeps; polish; FP32 sweeps)
-    unsigned long long fmm_near, fmm_far[2];
-    unsigned long long fmm_near_polish, fmm_far_polish[2];
-    unsigned long long fmm_near_f32, fmm_far_f32[2];
 };
+
+// Tallies of the fast-multipole star sums behind the algorithmic FLOP count,
+// per pass kind (FMM_T_F64, FMM_T_POLISH, FMM_T_F32): near-field star terms
+// (+0), far-field series evaluations (+1) and those evaluations times their
+// field's star count (+2).  Work groups add to one of FMM_STRIPES copies, each
+// on a cache line of its own, so that the adds of thousands of work groups
+// do not queue on one address; the host sums the copies.
+constexpr int FMM_STRIPES = 16;
+constexpr int FMM_STRIPE_U64 = 16;   // 128 bytes per copy
+enum { FMM_T_F64 = 0, FMM_T_POLISH = 3, FMM_T_F32 = 6 };
 
 struct Ctx {
     int device = 0;
@@ -186,6 +190,7 @@ struct Ctx {
     DevBuf counts;    // int32[F]: unflagged roots after the last sweep
     DevBuf passupd;   // int32[F]: roots updated by the last round's pass
     DevBuf control;   // Control
+    DevBuf fmm_tally; // uint64[FMM_STRIPES * FMM_STRIPE_U64]: multipole tallies
     DevBuf etab;      // double2[m + 1]: (1 - kappa_s) e^{-i phi_j}
     DevBuf bnd;       // double2[(S - 1) * n_r]: duplicate boundary rows
     DevBuf perm;      // int32[(S + 1) * n_r]: pairings and global labels
