@@ -103,48 +103,24 @@ __device__ __forceinline__ void stream_tiles(const T *__restrict__ p, int n, T *
     stream_tiles_ex(p, n, lds, Same{}, body, NoEnd{});
 }
 
-// The same stream, records taken two at a time: two(a, b) for consecutive
-// records, one(a) for the last of an odd count.  The terms meet the sums in
-// the same order as with stream_tiles.
-template <class T, class One, class Two>
-__device__ __forceinline__ void stream_tiles_pairs(const T *__restrict__ p, int n, T *lds, One &&one,
-                                                   Two &&two)
-{
-    if (n <= 0) return;
-    const int lane = threadIdx.x;
-    const int ntiles = (n + 63) >> 6;
-    T reg = p[min(lane, n - 1)];
-    for (int t = 0; t < ntiles; ++t) {
-        T *buf = lds + ((t & 1) << 6);
-        buf[lane] = reg;
-        __syncthreads();
-        if (t + 1 < ntiles) reg = p[min(((t + 1) << 6) + lane, n - 1)];
-        const int cnt = min(64, n - (t << 6));
-        if (cnt == 64) {
-#pragma unroll 4
-            for (int k = 0; k < 64; k += 2) two(buf[k], buf[k + 1]);
-        } else {
-            int k = 0;
-            for (; k + 1 < cnt; k += 2) two(buf[k], buf[k + 1]);
-            if (k < cnt) one(buf[k]);
-        }
-    }
-    __syncthreads();
-}
-
-// Reciprocals shared by groups of this many consecutive terms (2 or 4; see
-// rcp_pair and rcp_quad).
+// Reciprocals are shared by groups of this many consecutive terms (1, 2, 4
+// or 8; see RcpTree).
 #ifndef MLCC_RCP_GROUP
-#define MLCC_RCP_GROUP 4
+#define MLCC_RCP_GROUP 8
 #endif
 
-// The same stream, records taken four at a time: four(a, b, c, d) for
-// consecutive records, then two() and one() for what a partial tile leaves.
-// The terms meet the sums in the same order as with stream_tiles.
-template <class T, class One, class Two, class Four>
-__device__ __forceinline__ void stream_tiles_quads(const T *__restrict__ p, int n, T *lds, One &&one,
-                                                   Two &&two, Four &&four)
+template <int G> using GroupOf = std::integral_constant<int, G>;
+
+// The same stream, records handed to group(GroupOf<G>{}, r) with r pointing
+// at G consecutive records in LDS: G = MLCC_RCP_GROUP in full tiles, and a
+// partial tile ends with groups of half, a quarter ... of that.  The terms
+// meet the sums in the same order as with stream_tiles.
+template <class T, class Group>
+__device__ __forceinline__ void stream_tiles_grouped(const T *__restrict__ p, int n, T *lds,
+                                                     Group &&group)
 {
+    constexpr int G = MLCC_RCP_GROUP;
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8, "group of 1, 2, 4 or 8 terms");
     if (n <= 0) return;
     const int lane = threadIdx.x;
     const int ntiles = (n + 63) >> 6;
@@ -156,30 +132,29 @@ __device__ __forceinline__ void stream_tiles_quads(const T *__restrict__ p, int 
         if (t + 1 < ntiles) reg = p[min(((t + 1) << 6) + lane, n - 1)];
         const int cnt = min(64, n - (t << 6));
         if (cnt == 64) {
-#pragma unroll 2
-            for (int k = 0; k < 64; k += 4) four(buf[k], buf[k + 1], buf[k + 2], buf[k + 3]);
+#pragma unroll G >= 8 ? 1 : 8 / G
+            for (int k = 0; k < 64; k += G) group(GroupOf<G>{}, buf + k);
         } else {
             int k = 0;
-            for (; k + 3 < cnt; k += 4) four(buf[k], buf[k + 1], buf[k + 2], buf[k + 3]);
-            if (k + 1 < cnt) {
-                two(buf[k], buf[k + 1]);
-                k += 2;
+            for (; k + G <= cnt; k += G) group(GroupOf<G>{}, buf + k);
+            if constexpr (G > 4) {
+                if (k + 4 <= cnt) {
+                    group(GroupOf<4>{}, buf + k);
+                    k += 4;
+                }
             }
-            if (k < cnt) one(buf[k]);
+            if constexpr (G > 2) {
+                if (k + 2 <= cnt) {
+                    group(GroupOf<2>{}, buf + k);
+                    k += 2;
+                }
+            }
+            if constexpr (G > 1) {
+                if (k < cnt) group(GroupOf<1>{}, buf + k);
+            }
         }
     }
     __syncthreads();
-}
-
-// The stream in the groups MLCC_RCP_GROUP asks for.
-template <class T, class One, class Two, class Four>
-__device__ __forceinline__ void stream_tiles_grouped(const T *__restrict__ p, int n, T *lds,
-                                                     One &&one, Two &&two, Four &&four)
-{
-    if constexpr (MLCC_RCP_GROUP == 4)
-        stream_tiles_quads(p, n, lds, one, two, four);
-    else
-        stream_tiles_pairs(p, n, lds, one, two);
 }
 
 // Star records: (x, y) when all masses are equal (the common mass is applied
@@ -241,34 +216,38 @@ __device__ __forceinline__ void zero(Sums &S)
     S.s1r = S.s1i = S.s0r = S.s0i = S.s2r = S.s2i = S.s3r = S.s3i = S.Rr = S.Ri = 0.0;
 }
 
-// Two reciprocals for the price of one: 1/a = b/(ab), 1/b = a/(ab), with the
-// refined reciprocal of the product (the same ~2^-47 relative error).  The
-// quarter-rate v_rcp_f64 and its Newton step are ~24% of a star term's issue
-// cycles.  A zero distance makes both terms non-finite, as it makes its own
-// term non-finite alone, and the iterate is nudged either way.
-__device__ __forceinline__ void rcp_pair(double a, double b, double &ia, double &ib)
-{
-    const double ip = rcp_refined<RCP_STAR>(a * b);
-    ia = b * ip;
-    ib = a * ip;
-}
+// G reciprocals for the price of one: with r the refined reciprocal of the
+// product of q[0..G), the reciprocals of the two halves' products are
+// 1/P_lo = P_hi r and 1/P_hi = P_lo r, and so on down to single terms
+// (1/a = b/(ab)).  For eight terms: 23 FP64 operations and one quarter-rate
+// v_rcp_f64, against 22 and two for two groups of four; the relative error
+// stays at the refined reciprocal's ~2^-47 plus a rounding per level.  The
+// quarter-rate v_rcp_f64 and its Newton step would be ~24% of a star term's
+// issue cycles without sharing.  The product of eight squared distances stays
+// inside the double range for distances between 1e-19 and 1e19.  A zero
+// distance makes every term of its group non-finite, as it makes its own term
+// non-finite alone, and the iterate is nudged either way.
+template <int G> struct RcpTree {
+    static __device__ __forceinline__ double prod(const double *q)
+    {
+        return RcpTree<G / 2>::prod(q) * RcpTree<G / 2>::prod(q + G / 2);
+    }
+    static __device__ __forceinline__ void down(const double *q, double r, double *iq)
+    {
+        const double lo = RcpTree<G / 2>::prod(q), hi = RcpTree<G / 2>::prod(q + G / 2);
+        RcpTree<G / 2>::down(q, hi * r, iq);
+        RcpTree<G / 2>::down(q + G / 2, lo * r, iq + G / 2);
+    }
+};
+template <> struct RcpTree<1> {
+    static __device__ __forceinline__ double prod(const double *q) { return q[0]; }
+    static __device__ __forceinline__ void down(const double *, double r, double *iq) { iq[0] = r; }
+};
 
-// Four reciprocals for the price of one: with p01 = ab, p23 = cd and the
-// refined reciprocal r of p01 p23, 1/a = b (p23 r), 1/b = a (p23 r),
-// 1/c = d (p01 r), 1/d = c (p01 r): 11 FP64 operations and one quarter-rate
-// v_rcp_f64 for four terms, against 10 and two for two pairs.  The product
-// of four squared distances stays far inside the double range for any
-// field (distances between 1e-30 and 1e30).
-__device__ __forceinline__ void rcp_quad(double a, double b, double c, double d, double &ia,
-                                         double &ib, double &ic, double &id)
+template <int G>
+__device__ __forceinline__ void rcp_group(const double (&q)[G], double (&iq)[G])
 {
-    const double p01 = a * b, p23 = c * d;
-    const double r = rcp_refined<RCP_STAR>(p01 * p23);
-    const double q01 = p23 * r, q23 = p01 * r;   // 1/(ab), 1/(cd)
-    ia = b * q01;
-    ib = a * q01;
-    ic = d * q23;
-    id = c * q23;
+    RcpTree<G>::down(q, rcp_refined<RCP_STAR>(RcpTree<G>::prod(q)), iq);
 }
 
 template <bool EQUAL, class T>
@@ -283,30 +262,21 @@ __device__ __forceinline__ void add_star(Sums &S, double zr, double zi, const T 
     add_star_inv<EQUAL>(S, dx, dy, rcp_refined<RCP_STAR>(fma(dx, dx, dy * dy)), s);
 }
 
-template <bool EQUAL, class T>
-__device__ __forceinline__ void add_star_pair(Sums &S, double zr, double zi, const T &s,
-                                              const T &t)
+// G consecutive star terms sharing one refined reciprocal (rcp_group), in
+// the order add_star would take them.
+template <bool EQUAL, int G, class T>
+__device__ __forceinline__ void add_star_group(Sums &S, double zr, double zi, const T *r)
 {
-    const double dx = zr - s.x, dy = zi - s.y, ex = zr - t.x, ey = zi - t.y;
-    double is, it;
-    rcp_pair(fma(dx, dx, dy * dy), fma(ex, ex, ey * ey), is, it);
-    add_star_inv<EQUAL>(S, dx, dy, is, s);
-    add_star_inv<EQUAL>(S, ex, ey, it, t);
-}
-
-template <bool EQUAL, class T>
-__device__ __forceinline__ void add_star_quad(Sums &S, double zr, double zi, const T &s,
-                                              const T &t, const T &v, const T &w)
-{
-    const double dx = zr - s.x, dy = zi - s.y, ex = zr - t.x, ey = zi - t.y;
-    const double fx = zr - v.x, fy = zi - v.y, gx = zr - w.x, gy = zi - w.y;
-    double is, it, iv, iw;
-    rcp_quad(fma(dx, dx, dy * dy), fma(ex, ex, ey * ey), fma(fx, fx, fy * fy),
-             fma(gx, gx, gy * gy), is, it, iv, iw);
-    add_star_inv<EQUAL>(S, dx, dy, is, s);
-    add_star_inv<EQUAL>(S, ex, ey, it, t);
-    add_star_inv<EQUAL>(S, fx, fy, iv, v);
-    add_star_inv<EQUAL>(S, gx, gy, iw, w);
+    double dx[G], dy[G], q[G], iq[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        dx[j] = zr - r[j].x;
+        dy[j] = zi - r[j].y;
+        q[j] = fma(dx[j], dx[j], dy[j] * dy[j]);
+    }
+    rcp_group<G>(q, iq);
+#pragma unroll
+    for (int j = 0; j < G; ++j) add_star_inv<EQUAL>(S, dx[j], dy[j], iq[j], r[j]);
 }
 
 template <bool EQUAL, class T>
@@ -314,29 +284,33 @@ __device__ __forceinline__ void add_star_inv(Sums &S, double dx, double dy, doub
                                              const T &s)
 {
     // u = conj(d) / |d|^2 = ux - i uy, with a = ux^2, b = uy^2:
-    //   u^2 = (a - b) - 2 i ux uy,   u^3 = ux (a - 3b) + i uy (b - 3a),
-    // and since a + b = |u|^2 = inv, a - 3b = inv - 4b and b - 3a = inv - 4a:
-    // -4 is an inline constant of the three-operand FP64 FMA, while -3 would
-    // take the two-operand accumulating form and a register copy per term.
+    //   u^2 = (a - b) - 2 i ux uy,   u^3 = ux (a - 3b) + i uy (b - 3a).
+    // Since a + b = |u|^2 = inv, only b is squared: t = a - b = inv - 2b,
+    // a - 3b = t - 2b and b - 3a = 4b - 3 inv = -2t - inv.  Every
+    // coefficient is an inline constant of the three-operand FP64 FMA and the
+    // negated inv a source modifier, so u^2 and u^3 take one product and four
+    // FMAs instead of two products and four FMAs.
     const double ux = dx * inv;
     const double uy = dy * inv;
-    const double a = ux * ux, b = uy * uy;
+    const double b = uy * uy;
+    const double t = fma(-2.0, b, inv);
+    const double c3r = fma(-2.0, b, t), c3i = fma(-2.0, t, -inv);
     S.s1r += ux;
     S.s1i -= uy;
     if (EQUAL) {
-        S.s2r += a - b;
+        S.s2r += t;
         S.s2i = fma(ux, uy, S.s2i);
-        S.s3r = fma(ux, fma(-4.0, b, inv), S.s3r);
-        S.s3i = fma(uy, fma(-4.0, a, inv), S.s3i);
+        S.s3r = fma(ux, c3r, S.s3r);
+        S.s3i = fma(uy, c3i, S.s3i);
     } else {
         const double mi = StarRec<EQUAL>::mass(s);
         const double mux = mi * ux, muy = mi * uy;
         S.s0r += mux;
         S.s0i -= muy;
-        S.s2r = fma(mi, a - b, S.s2r);
+        S.s2r = fma(mi, t, S.s2r);
         S.s2i = fma(mux, uy, S.s2i);
-        S.s3r = fma(mux, fma(-4.0, b, inv), S.s3r);
-        S.s3i = fma(muy, fma(-4.0, a, inv), S.s3i);
+        S.s3r = fma(mux, c3r, S.s3r);
+        S.s3i = fma(muy, c3i, S.s3i);
     }
 }
 
@@ -349,38 +323,25 @@ __device__ __forceinline__ void add_root(Sums &S, double zr, double zi, const do
     S.Ri = fma(-dy, inv, S.Ri);
 }
 
-// Two root-root terms sharing one refined reciprocal (rcp_pair), in the
-// order add_root would take them.  Two iterates at one point make both
-// terms non-finite, as one term alone would be, and the iterate is nudged.
-__device__ __forceinline__ void add_root_pair(Sums &S, double zr, double zi, const double2 &o,
-                                              const double2 &p)
+// G root-root terms sharing one refined reciprocal (rcp_group), in the order
+// add_root would take them.  Two iterates at one point make every term of the
+// group non-finite, as one term alone would be, and the iterate is nudged.
+template <int G>
+__device__ __forceinline__ void add_root_group(Sums &S, double zr, double zi, const double2 *r)
 {
-    const double dx = zr - o.x, dy = zi - o.y, ex = zr - p.x, ey = zi - p.y;
-    double io, ip;
-    rcp_pair(fma(dx, dx, dy * dy), fma(ex, ex, ey * ey), io, ip);
-    S.Rr = fma(dx, io, S.Rr);
-    S.Ri = fma(-dy, io, S.Ri);
-    S.Rr = fma(ex, ip, S.Rr);
-    S.Ri = fma(-ey, ip, S.Ri);
-}
-
-__device__ __forceinline__ void add_root_quad(Sums &S, double zr, double zi, const double2 &o,
-                                              const double2 &p, const double2 &q,
-                                              const double2 &r)
-{
-    const double dx = zr - o.x, dy = zi - o.y, ex = zr - p.x, ey = zi - p.y;
-    const double fx = zr - q.x, fy = zi - q.y, gx = zr - r.x, gy = zi - r.y;
-    double io, ip, iq, ir;
-    rcp_quad(fma(dx, dx, dy * dy), fma(ex, ex, ey * ey), fma(fx, fx, fy * fy),
-             fma(gx, gx, gy * gy), io, ip, iq, ir);
-    S.Rr = fma(dx, io, S.Rr);
-    S.Ri = fma(-dy, io, S.Ri);
-    S.Rr = fma(ex, ip, S.Rr);
-    S.Ri = fma(-ey, ip, S.Ri);
-    S.Rr = fma(fx, iq, S.Rr);
-    S.Ri = fma(-fy, iq, S.Ri);
-    S.Rr = fma(gx, ir, S.Rr);
-    S.Ri = fma(-gy, ir, S.Ri);
+    double dx[G], dy[G], q[G], iq[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        dx[j] = zr - r[j].x;
+        dy[j] = zi - r[j].y;
+        q[j] = fma(dx[j], dx[j], dy[j] * dy[j]);
+    }
+    rcp_group<G>(q, iq);
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        S.Rr = fma(dx[j], iq[j], S.Rr);
+        S.Ri = fma(-dy[j], iq[j], S.Ri);
+    }
 }
 
 // The root-root term with FP32 arithmetic (MLCC_FP64_R32, warm rows).  Each
@@ -1155,24 +1116,19 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
             S.s3r += 0.5 * f2.x; S.s3i += 0.5 * f2.y;
         } else {
             stream_tiles_grouped(stars, n_stars, reinterpret_cast<T *>(tiles),
-                                 [&](const T &s) { add_star<EQUAL>(S, zr, zi, s); },
-                                 [&](const T &s, const T &t) {
-                                     add_star_pair<EQUAL>(S, zr, zi, s, t);
-                                 },
-                                 [&](const T &s, const T &t, const T &v, const T &w) {
-                                     add_star_quad<EQUAL>(S, zr, zi, s, t, v, w);
+                                 [&](auto g, const T *r) {
+                                     add_star_group<EQUAL, decltype(g)::value>(S, zr, zi, r);
                                  });
         }
         if (!fast_roots_pass(A.fronts[B.f], A.reals[B.r])) {
             // the other roots in FP64, in groups outside the own block;
             // within it one at a time, skipping the root itself
             double2 *rtiles = reinterpret_cast<double2 *>(tiles);
-            auto one = [&](const double2 &o) { add_root(S, zr, zi, o); };
-            auto two = [&](const double2 &o, const double2 &p) { add_root_pair(S, zr, zi, o, p); };
-            auto four = [&](const double2 &o, const double2 &p, const double2 &q,
-                            const double2 &r) { add_root_quad(S, zr, zi, o, p, q, r); };
+            auto group = [&](auto g, const double2 *r) {
+                add_root_group<decltype(g)::value>(S, zr, zi, r);
+            };
             const int own_hi = min(k0 + 64, n_r);
-            stream_tiles_grouped(zsrc, k0, rtiles, one, two, four);
+            stream_tiles_grouped(zsrc, k0, rtiles, group);
             stream_tiles(zsrc + k0, own_hi - k0, rtiles, [&](int j, const double2 &o) {
                 Sums T2 = S;
                 add_root(T2, zr, zi, o);
@@ -1180,7 +1136,7 @@ __device__ __forceinline__ void sweep_f64_pass(const RoundArgs<typename StarRec<
                 S.Rr = self ? S.Rr : T2.Rr;
                 S.Ri = self ? S.Ri : T2.Ri;
             });
-            stream_tiles_grouped(zsrc + own_hi, n_r - own_hi, rtiles, one, two, four);
+            stream_tiles_grouped(zsrc + own_hi, n_r - own_hi, rtiles, group);
             const Update u = finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k,
                                            B.sheet, B.n_poly);
             if (act) store(k, u);
@@ -1407,30 +1363,20 @@ __device__ __forceinline__ void add_star_polish(PSums &S, double zr, double zi, 
     add_star_polish_inv<EQUAL>(S, dx, dy, rcp_refined<RCP_STAR>(fma(dx, dx, dy * dy)), s);
 }
 
-template <bool EQUAL, class T>
-__device__ __forceinline__ void add_star_polish_pair(PSums &S, double zr, double zi, const T &s,
-                                                     const T &t)
+// G consecutive polish star terms sharing one refined reciprocal.
+template <bool EQUAL, int G, class T>
+__device__ __forceinline__ void add_star_polish_group(PSums &S, double zr, double zi, const T *r)
 {
-    const double dx = zr - s.x, dy = zi - s.y, ex = zr - t.x, ey = zi - t.y;
-    double is, it;
-    rcp_pair(fma(dx, dx, dy * dy), fma(ex, ex, ey * ey), is, it);
-    add_star_polish_inv<EQUAL>(S, dx, dy, is, s);
-    add_star_polish_inv<EQUAL>(S, ex, ey, it, t);
-}
-
-template <bool EQUAL, class T>
-__device__ __forceinline__ void add_star_polish_quad(PSums &S, double zr, double zi, const T &s,
-                                                     const T &t, const T &v, const T &w)
-{
-    const double dx = zr - s.x, dy = zi - s.y, ex = zr - t.x, ey = zi - t.y;
-    const double fx = zr - v.x, fy = zi - v.y, gx = zr - w.x, gy = zi - w.y;
-    double is, it, iv, iw;
-    rcp_quad(fma(dx, dx, dy * dy), fma(ex, ex, ey * ey), fma(fx, fx, fy * fy),
-             fma(gx, gx, gy * gy), is, it, iv, iw);
-    add_star_polish_inv<EQUAL>(S, dx, dy, is, s);
-    add_star_polish_inv<EQUAL>(S, ex, ey, it, t);
-    add_star_polish_inv<EQUAL>(S, fx, fy, iv, v);
-    add_star_polish_inv<EQUAL>(S, gx, gy, iw, w);
+    double dx[G], dy[G], q[G], iq[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        dx[j] = zr - r[j].x;
+        dy[j] = zi - r[j].y;
+        q[j] = fma(dx[j], dx[j], dy[j] * dy[j]);
+    }
+    rcp_group<G>(q, iq);
+#pragma unroll
+    for (int j = 0; j < G; ++j) add_star_polish_inv<EQUAL>(S, dx[j], dy[j], iq[j], r[j]);
 }
 
 template <bool EQUAL, class T>
@@ -1438,27 +1384,30 @@ __device__ __forceinline__ void add_star_polish_inv(PSums &S, double dx, double 
                                                     const T &s)
 {
     // u = ux - i uy, a = ux^2, b = uy^2:  u^2 = (a - b) - 2i ux uy,
-    // u^3 = ux (a - 3b) + i uy (b - 3a) = ux (inv - 4b) + i uy (inv - 4a)
-    // (a + b = inv; see add_star_inv),  |u|^4 = inv^2
+    // u^3 = ux (a - 3b) + i uy (b - 3a), formed from b alone as in
+    // add_star_inv (t = a - b = inv - 2b, a - 3b = t - 2b, b - 3a = -2t - inv);
+    // |u|^4 = inv^2
     // (s2i accumulates sum m ux uy; polish_finish turns it into Im s2 = -2 that)
     const double ux = dx * inv;
     const double uy = dy * inv;
-    const double a = ux * ux, b = uy * uy;
+    const double b = uy * uy;
+    const double t = fma(-2.0, b, inv);
+    const double c3r = fma(-2.0, b, t), c3i = fma(-2.0, t, -inv);
     if (EQUAL) {
         S.s0r += ux; S.s0i -= uy;
-        S.s2r += a - b;
+        S.s2r += t;
         S.s2i = fma(ux, uy, S.s2i);
-        S.s3r = fma(ux, fma(-4.0, b, inv), S.s3r);
-        S.s3i = fma(uy, fma(-4.0, a, inv), S.s3i);
+        S.s3r = fma(ux, c3r, S.s3r);
+        S.s3i = fma(uy, c3i, S.s3i);
         S.q = fma(inv, inv, S.q);
     } else {
         const double mi = StarRec<EQUAL>::mass(s);
         const double mux = mi * ux, muy = mi * uy;
         S.s0r += mux; S.s0i -= muy;
-        S.s2r = fma(mi, a - b, S.s2r);
+        S.s2r = fma(mi, t, S.s2r);
         S.s2i = fma(mux, uy, S.s2i);
-        S.s3r = fma(mux, fma(-4.0, b, inv), S.s3r);
-        S.s3i = fma(muy, fma(-4.0, a, inv), S.s3i);
+        S.s3r = fma(mux, c3r, S.s3r);
+        S.s3i = fma(muy, c3i, S.s3i);
         S.q = fma(mi * inv, inv, S.q);
     }
 }
@@ -1621,12 +1570,9 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
             PSums S;
             zero(S);
             stream_tiles_grouped(stars, n_stars, reinterpret_cast<T *>(tiles),
-                                 [&](const T &s) { add_star_polish<EQUAL>(S, zr, zi, s); },
-                                 [&](const T &s, const T &t) {
-                                     add_star_polish_pair<EQUAL>(S, zr, zi, s, t);
-                                 },
-                                 [&](const T &s, const T &t, const T &v, const T &w) {
-                                     add_star_polish_quad<EQUAL>(S, zr, zi, s, t, v, w);
+                                 [&](auto g, const T *r) {
+                                     add_star_polish_group<EQUAL, decltype(g)::value>(S, zr, zi,
+                                                                                      r);
                                  });
             u = polish_finish<EQUAL>(S, zr, zi, m0, e, gamma, a, a1, tol_step2, tol_mu, k);
         }
@@ -1746,12 +1692,9 @@ __device__ __forceinline__ void polish_pass(const RoundArgs<typename StarRec<EQU
                         PSums S;
                         zero(S);
                         stream_tiles_grouped(stars, n_stars, reinterpret_cast<T *>(tiles),
-                                             [&](const T &s) { add_star_polish<EQUAL>(S, xr, xi, s); },
-                                             [&](const T &s, const T &t) {
-                                                 add_star_polish_pair<EQUAL>(S, xr, xi, s, t);
-                                             },
-                                             [&](const T &s, const T &t, const T &v, const T &w) {
-                                                 add_star_polish_quad<EQUAL>(S, xr, xi, s, t, v, w);
+                                             [&](auto g, const T *r) {
+                                                 add_star_polish_group<EQUAL, decltype(g)::value>(
+                                                     S, xr, xi, r);
                                              });
                         u = polish_finish<EQUAL>(S, xr, xi, m0, ex, gamma, a, a1, tol_step2, tol_mu,
                                                  k);
