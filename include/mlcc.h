@@ -49,8 +49,8 @@ typedef enum {
                       precision.  Each reciprocal 1/|d|^2 is the hardware estimate
                       refined by one Newton step (relative error below 2^-47, against
                       2^-53 for a correctly rounded division); consecutive star terms,
-                      and consecutive root-root terms, are taken in groups of four that
-                      share one refined reciprocal of the product of their four |d|^2 */
+                      and consecutive root-root terms, are taken in groups of eight that
+                      share one refined reciprocal of the product of their eight |d|^2 */
     MLCC_MIXED = 1,/* Aberth sweeps in FP32 (FP64 star distances, FP32 sums per tile of
                       64 stars carried in FP64), every root finished by FP64 Newton
                       polish passes that accept a root on the same cutoffs as the
