@@ -1388,12 +1388,12 @@ __device__ __forceinline__ void add_star_polish_inv(PSums &S, double dx, double 
     // add_star_inv (t = a - b = inv - 2b, a - 3b = t - 2b, b - 3a = -2t - inv);
     // |u|^4 = inv^2
     // (s2i accumulates sum m ux uy; polish_finish turns it into Im s2 = -2 that)
-    const double ux = dx * inv;
     const double uy = dy * inv;
     const double b = uy * uy;
     const double t = fma(-2.0, b, inv);
     const double c3r = fma(-2.0, b, t), c3i = fma(-2.0, t, -inv);
     if (EQUAL) {
+        const double ux = dx * inv;
         S.s0r += ux; S.s0i -= uy;
         S.s2r += t;
         S.s2i = fma(ux, uy, S.s2i);
@@ -1401,14 +1401,17 @@ __device__ __forceinline__ void add_star_polish_inv(PSums &S, double dx, double 
         S.s3i = fma(uy, c3i, S.s3i);
         S.q = fma(inv, inv, S.q);
     } else {
+        // the mass enters through m inv, shared by m u = conj(d) m inv and
+        // the bound's m inv^2; u's real part is not needed on its own
         const double mi = StarRec<EQUAL>::mass(s);
-        const double mux = mi * ux, muy = mi * uy;
+        const double minv = mi * inv;
+        const double mux = dx * minv, muy = mi * uy;
         S.s0r += mux; S.s0i -= muy;
         S.s2r = fma(mi, t, S.s2r);
         S.s2i = fma(mux, uy, S.s2i);
         S.s3r = fma(mux, c3r, S.s3r);
         S.s3i = fma(muy, c3i, S.s3i);
-        S.q = fma(mi * inv, inv, S.q);
+        S.q = fma(minv, inv, S.q);
     }
 }
 
