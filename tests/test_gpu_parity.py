@@ -222,6 +222,27 @@ def test_mixed_precision_matches_oracle(ctx, case):
     print(f"[{name}] mixed: max root error {worst:.3e}, max caustic error {wworst:.3e}", flush=True)
 
 
+
+# Star and root counts whose partial tiles end in every mix of the shorter
+# groups the term loops fall back to (8 terms share a reciprocal in full
+# groups; a tile's remainder takes groups of 4, 2 and 1): stars 13 = 8+4+1,
+# 15 = 8+4+2+1, 39 = 32+4+2+1, 46 = 40+4+2, 71 = 64+4+2+1; the other roots
+# of a row past a block's own 64 end in remainders of 14 = 8+4+2 and 28 = 24+4.
+TAIL_CASES = [(13, "equal"), (15, "salpeter"), (39, "equal"), (46, "salpeter"), (71, "equal")]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,masses", TAIL_CASES, ids=[f"n{c[0]}_{c[1]}" for c in TAIL_CASES])
+def test_term_group_tails_match_oracle(ctx, n, masses, precision):
+    say("group tails", n, masses, precision)
+    f = fields.random_field(29, n, kappa_star=0.45, kappa_s=0.1, gamma=0.35, masses=masses)
+    m_steps = 120
+    R, cn, st, _ = gpu_roots(ctx, f, m_steps, n_subchains=2, precision=precision)
+    R_ref, _, _ = oracle.critical_curves(f, m_steps, n_sub=1)
+    check_roots_against_oracle(f, R, R_ref, f"tails n{n} {masses} {precision}")
+    assert sorted(cn.tolist()) == list(range(2 * n))
+    assert np.max(np.abs(R[-1] - R[0][cn])) < 1e-8
+
 PREDICTOR_CASES = [
     # name, n, masses, kappa_star, kappa_s, gamma, m_steps, n_sub, precision, predictor
     ("n100_lin", 100, "equal", 0.5, 0.0, 0.3, 400, 4, "fp64", 1),
