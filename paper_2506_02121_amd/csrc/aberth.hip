@@ -2345,15 +2345,17 @@ aberth_persistent(RoundArgs<typename StarRec<EQUAL>::T> A, Front *__restrict__ f
 // Cost of one wave's pass over a field of N stars and n_r = 2N roots, in
 // SIMD cycles (issue costs measured per wave64 instruction with eight
 // independent chains per lane: FP64 add/mul ~4.8, FMA ~5.3, v_rcp_f64
-// ~16.6; FP32 add/mul ~2.7, FMA ~4.1, v_rcp_f32 ~8.6; the kernels spend ~21
-// instructions per star term and ~7 per root term in a sweep, ~22 per star
-// term in the polish):
+// ~16.6; FP32 add/mul ~2.7, FMA ~4.1, v_rcp_f32 ~8.6), fitted when the
+// kernels spent ~21 instructions per star term and ~9 per root term in a
+// sweep and ~22 per star term in the polish (now ~19, ~9 and ~20 with the
+// eight-term reciprocal groups; S depends on the ratios of these costs,
+// which moved by a few per cent):
 //   FP64 Aberth sweep   114 N + 47 n_r
 //   FP32 Aberth sweep    56 N + 22 n_r
 //   FP64 Newton polish  120 N
-// (Warm FP64 rows take their root terms in FP32, ~40 instead of ~47 cycles
-// per root; the model keeps 47, and S sweeps of measured run times put its
-// choice within 1% of the best S on the workloads tried.)
+// (Warm rows of MLCC_FP64_R32 take their root terms in FP32, ~40 instead of
+// ~47 cycles per root; the model keeps 47, and S sweeps of measured run
+// times put its choice within 1% of the best S on the workloads tried.)
 // A run does, per field, u (m + S) row passes of every block (u ~ 1.03
 // with the chain predictor, ~2 without; in the mixed form a row without a
 // prediction takes an FP32 sweep and a polish) plus S cold starts of ~27
