@@ -409,6 +409,7 @@ mlcc_status mlcc_caustic_crossings_noalloc(mlcc_ctx *ctx, int64_t rows, int64_t 
  * the map: border_limited marks those (distance > distance to the map edge).
  * With no caustic pixel at all every distance is +inf and every mark 1.
  * Pixels must be square: |hx - hy| <= 1e-9 hx; distances are in units of hx.
+ * nx + ny <= 30000 (MLCC_ERR_INVALID otherwise).
  *   ncc             device int32[ny * nx]
  *   dist            device float64[ny * nx]: sqrt(d2) * hx, d2 the exact
  *                   integer squared pixel distance

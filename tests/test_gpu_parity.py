@@ -472,6 +472,20 @@ def test_distances_no_caustic(ctx):
     assert np.all(np.isinf(d)) and np.all(bl == 1)
 
 
+def test_distances_reject_oversized_maps(ctx, mlcc):
+    """nx + ny above 30000 is refused before any kernel runs (the row pass
+    keeps one envelope length per 64-column segment of a row in a fixed LDS
+    array), so small buffers stand in for the map."""
+    say("edt size limit")
+    ncc = torch.zeros(16, dtype=torch.int32, device="cuda")
+    dist = torch.zeros(16, dtype=torch.float64, device="cuda")
+    big = mlcc.Grid(0.0, 0.0, 100.0, 75.0, 20000, 15000)
+    with pytest.raises(mlcc.MlccError, match="30000"):
+        ctx.caustic_distances(big, ncc, border_limited=False, out=(dist, None))
+    torch.cuda.synchronize()
+    assert float(dist.abs().sum()) == 0.0
+
+
 # --------------------------------------------------------------------------
 # end to end on the tiny field
 # --------------------------------------------------------------------------
