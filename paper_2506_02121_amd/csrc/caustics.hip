@@ -5,44 +5,39 @@
 // and m_i / conj(d) = m_i d / |d|^2.  A rectangular field (Sec. 4.2, App. B)
 // adds its sheet's Taylor terms: gamma becomes gamma - d0 and
 //   w -= sum_k d_2k conj(z)^(2k+1) / (2k+1).
-// One lane per point; star tiles stream through LDS.
+// One lane per point; star tiles stream through LDS, and groups of eight
+// star terms share one refined reciprocal.
 #include <type_traits>
 
 #include "mlcc_internal.h"
+#include "term_groups.h"
 
 namespace mlcc {
 
-__device__ __forceinline__ double rcp_full(double x)
-{
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
-}
+// Reciprocals in the lens map take two Newton steps (about an ulp; the
+// root finder's accept test needs only one), shared by groups of star terms
+// as in the root finder.
+constexpr int RCP_MAP = 2;
 
-// Same streaming scheme as the root finder: tiles of 64 star records fetched
-// with coalesced vector loads one tile ahead, parked in LDS, read back with
-// broadcast LDS reads (one-wave work groups).
-template <class T, class Body>
-__device__ __forceinline__ void stream_star_tiles(const T *__restrict__ p, int n, T *lds,
-                                                  Body &&body)
+// G consecutive star terms m_i d / |d|^2 added to (sr, si).
+template <bool EQUAL, int G, class T>
+__device__ __forceinline__ void add_map_group(double &sr, double &si, double x, double y,
+                                              const T *r)
 {
-    const int lane = threadIdx.x;
-    const int ntiles = (n + 63) >> 6;
-    T reg = p[min(lane, n - 1)];
-    for (int t = 0; t < ntiles; ++t) {
-        T *buf = lds + ((t & 1) << 6);
-        buf[lane] = reg;
-        __syncthreads();
-        if (t + 1 < ntiles) reg = p[min(((t + 1) << 6) + lane, n - 1)];
-        const int cnt = min(64, n - (t << 6));
-        if (cnt == 64) {
-#pragma unroll 8
-            for (int k = 0; k < 64; ++k) body(buf[k]);
-        } else {
-            for (int k = 0; k < cnt; ++k) body(buf[k]);
-        }
+    double dx[G], dy[G], q[G], iq[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        dx[j] = x - r[j].x;
+        dy[j] = y - r[j].y;
+        q[j] = fma(dx[j], dx[j], dy[j] * dy[j]);
+    }
+    rcp_group<G, RCP_MAP>(q, iq);
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        double v = iq[j];
+        if constexpr (!EQUAL) v *= r[j].z;
+        sr = fma(v, dx[j], sr);
+        si = fma(v, dy[j], si);
     }
 }
 
@@ -61,12 +56,8 @@ map_caustics_f64(const typename std::conditional<EQUAL, double2, double4>::type 
     const double x = valid ? zr[k] : 0.0;
     const double y = valid ? zi[k] : 0.0;
     double sr = 0.0, si = 0.0;
-    stream_star_tiles(stars, n_stars, tiles, [&](const T &s) {
-        const double dx = x - s.x, dy = y - s.y;
-        double q = rcp_full(fma(dx, dx, dy * dy));
-        if constexpr (!EQUAL) q *= s.z;
-        sr = fma(q, dx, sr);
-        si = fma(q, dy, si);
+    stream_tiles_grouped(stars, n_stars, tiles, [&](auto g, const T *r) {
+        add_map_group<EQUAL, decltype(g)::value>(sr, si, x, y, r);
     });
     if (EQUAL) {   // every mass equals m0
         sr *= m0;
