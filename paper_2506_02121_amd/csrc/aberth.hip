@@ -1146,8 +1146,9 @@ __device__ __forceinline__ void sweep_f32_pass(const RoundArgs<typename StarRec<
             [&](int, const T &s) {
                 const float dx = (float)(zr - s.x), dy = (float)(zi - s.y);
                 const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, dy * dy));
-                // as in add_star: p2i accumulates sum m ux uy (Im u^2 = -2 ux uy),
-                // and a - 3b = inv - 4b, b - 3a = inv - 4a
+                // a = ux^2, b = uy^2: p2i accumulates sum m ux uy (Im u^2 =
+                // -2 ux uy), and since a + b = inv, a - 3b = inv - 4b and
+                // b - 3a = inv - 4a
                 const float ux = dx * inv, uy = dy * inv;
                 const float a = ux * ux, b = uy * uy;
                 p1r += ux;
